@@ -1,0 +1,747 @@
+/*
+ * FP64 CPU oracle for PROFusion's tracking-and-fusion hot path (arXiv 2509.24236).
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the plain, slow reference that the HIP library is
+ * checked against. Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it. It shares no code, header, table or helper with the HIP library, and the HIP
+ * library never calls it.
+ *
+ * Everything is double precision, built with -O2 -ffp-contract=off and no fast-math. The only
+ * parallelism is OpenMP over independent particles or independent z-slabs of the volume, which
+ * does not change any arithmetic. Each function names the passage of the paper it follows.
+ *
+ * Readings of passages the paper leaves open are listed where they are used (pose direction,
+ * the meaning of "Delta P * P", the sampling box, the valid-grid rule, empty sets, the SO(3)
+ * average, and the order of the search-size update).
+ *
+ * Volume storage: T[(k*ny + j)*nx + i] and W[...] for voxel (i, j, k) whose centre is
+ * origin + vs*(i, j, k). T is the normalised TSDF (sdf / tau, so the 1/tau of the fitness
+ * equation is folded into storage); T = +1 means unobserved or free beyond the band.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct { double R[9]; double t[3]; } orc_pose;            /* camera -> world */
+typedef struct { double fx, fy, cx, cy; int32_t width, height; } orc_intr;
+typedef struct {
+    int32_t nx, ny, nz, w_max;
+    double vs, tau;
+    double origin[3];
+    double* T;
+    double* W;
+} orc_vol;
+
+/* ----------------------------------------------------------------------------------------
+ * Counter-based random numbers (reading: the paper does not name a generator).
+ * SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the n-th output (n = 0, 1, ...) of the
+ * generator whose state starts at `seed` is mix(seed + (n + 1) * gamma), with
+ * gamma = 0x9E3779B97F4A7C15 and the mix of the published reference implementation.
+ * ---------------------------------------------------------------------------------------- */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t n) {
+    uint64_t z = seed + (n + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* The draw for (frame t, iteration i, particle k, dimension d) uses counter
+ * n = t<<40 | i<<32 | k<<3 | d, and maps the top 53 bits to a in [-1, 1): a = 2u - 1,
+ * u = (x >> 11) * 2^-53. Both steps are exact in double precision. */
+uint64_t orc_counter(int64_t t, int64_t i, int64_t k, int64_t d) {
+    return ((uint64_t)t << 40) | ((uint64_t)i << 32) | ((uint64_t)k << 3) | (uint64_t)d;
+}
+
+double orc_uniform_pm1(uint64_t seed, int64_t t, int64_t i, int64_t k, int64_t d) {
+    uint64_t x = orc_splitmix64(seed, orc_counter(t, i, k, d));
+    double u = (double)(x >> 11) * 0x1.0p-53;
+    return 2.0 * u - 1.0;
+}
+
+/* ----------------------------------------------------------------------------------------
+ * SO(3) exponential (Rodrigues) and logarithm. The paper averages rotations "in SO(3)"
+ * (Sec. III-B); the exponential maps rotation vectors (radians) to matrices.
+ * R = I + A K + B K^2 with K = [r]x, A = sin(th)/th, B = (1 - cos(th))/th^2, and the Taylor
+ * forms A = 1 - th^2/6, B = 1/2 - th^2/24 for th < 1e-6.
+ * ---------------------------------------------------------------------------------------- */
+void orc_so3_exp(const double r[3], double R[9]) {
+    double th2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double th = sqrt(th2);
+    double A, B;
+    if (th < 1e-6) {
+        A = 1.0 - th2 / 6.0;
+        B = 0.5 - th2 / 24.0;
+    } else {
+        A = sin(th) / th;
+        B = (1.0 - cos(th)) / th2;
+    }
+    double K[9] = {0.0, -r[2], r[1], r[2], 0.0, -r[0], -r[1], r[0], 0.0};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double k2 = 0.0;
+            for (int c = 0; c < 3; ++c) k2 += K[a * 3 + c] * K[c * 3 + b];
+            R[a * 3 + b] = (a == b ? 1.0 : 0.0) + A * K[a * 3 + b] + B * k2;
+        }
+}
+
+/* Logarithm: th = acos((tr R - 1)/2); r = th / (2 sin th) * vee(R - R^T); near th = 0 the
+ * factor tends to 1/2; near th = pi the axis comes from the diagonal of (R + I)/2. */
+void orc_so3_log(const double R[9], double r[3]) {
+    double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+    if (c > 1.0) c = 1.0;
+    if (c < -1.0) c = -1.0;
+    double th = acos(c);
+    double v[3] = {R[7] - R[5], R[2] - R[6], R[3] - R[1]};
+    if (th < 1e-7) {
+        for (int a = 0; a < 3; ++a) r[a] = 0.5 * v[a];
+        return;
+    }
+    if (M_PI - th < 1e-6) {
+        double d[3] = {sqrt(fmax(0.0, 0.5 * (R[0] + 1.0))), sqrt(fmax(0.0, 0.5 * (R[4] + 1.0))),
+                       sqrt(fmax(0.0, 0.5 * (R[8] + 1.0)))};
+        int m = (d[0] >= d[1] && d[0] >= d[2]) ? 0 : (d[1] >= d[2] ? 1 : 2);
+        double ax[3];
+        ax[m] = d[m];
+        for (int a = 0; a < 3; ++a)
+            if (a != m) ax[a] = 0.5 * R[m * 3 + a] / d[m];   /* (R + R^T)/2 off-diagonal = ax_m ax_a */
+        double n = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+        for (int a = 0; a < 3; ++a) r[a] = th * ax[a] / n;
+        return;
+    }
+    double f = th / (2.0 * sin(th));
+    for (int a = 0; a < 3; ++a) r[a] = f * v[a];
+}
+
+static void mat3_mul(const double A[9], const double B[9], double C[9]) {
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) s += A[a * 3 + c] * B[c * 3 + b];
+            C[a * 3 + b] = s;
+        }
+}
+
+static void mat3_vec(const double A[9], const double x[3], double y[3]) {
+    for (int a = 0; a < 3; ++a) y[a] = A[a * 3 + 0] * x[0] + A[a * 3 + 1] * x[1] + A[a * 3 + 2] * x[2];
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Delta-pose composition "Delta P_k P^(i-1)" (Sec. III-B).
+ * Reading DECOUPLED (mode 0, default): the delta rotation acts about the camera centre on
+ * world-aligned axes and the delta translation is added: (exp(r) R, t + tau). This keeps the
+ * search size s = (omega degrees, v cm) meaning a rotation of omega and a shift of v.
+ * Reading LITERAL (mode 1): the left product with Delta P = [exp(r) | tau]:
+ * (exp(r) R, exp(r) t + tau).
+ * ---------------------------------------------------------------------------------------- */
+void orc_compose(int mode, const double r[3], const double tau[3], const orc_pose* P, orc_pose* out) {
+    double E[9], Rn[9], tn[3];
+    orc_so3_exp(r, E);
+    mat3_mul(E, P->R, Rn);
+    if (mode == 1) {
+        mat3_vec(E, P->t, tn);
+        for (int a = 0; a < 3; ++a) tn[a] += tau[a];
+    } else {
+        for (int a = 0; a < 3; ++a) tn[a] = P->t[a] + tau[a];
+    }
+    memcpy(out->R, Rn, sizeof Rn);
+    memcpy(out->t, tn, sizeof tn);
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Back-projection of the depth image to the metric point cloud M_t (Sec. III, problem
+ * setting). Pixel (u, v) with depth z is valid iff z is finite and > 0 (reading: no range
+ * clip) and u, v are multiples of `pixel_stride`. x = (u - cx) z / fx, y = (v - cy) z / fy.
+ * Points are written compacted in raster order (v-major), xyz interleaved.
+ * ---------------------------------------------------------------------------------------- */
+int64_t orc_backproject(const float* depth, const orc_intr* K, int32_t pixel_stride, double* xyz,
+                        int32_t* pix) {
+    int64_t n = 0;
+    for (int v = 0; v < K->height; ++v)
+        for (int u = 0; u < K->width; ++u) {
+            if (u % pixel_stride != 0 || v % pixel_stride != 0) continue;
+            double z = (double)depth[(int64_t)v * K->width + u];
+            if (!(isfinite(z) && z > 0.0)) continue;
+            xyz[3 * n + 0] = ((double)u - K->cx) * z / K->fx;
+            xyz[3 * n + 1] = ((double)v - K->cy) * z / K->fy;
+            xyz[3 * n + 2] = z;
+            if (pix) pix[n] = v * K->width + u;
+            ++n;
+        }
+    return n;
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Initial volume: T = +1 (unobserved), W = 0 (Sec. III overview: the TSDF is a dense tensor).
+ * ---------------------------------------------------------------------------------------- */
+void orc_vol_init(orc_vol* V) {
+    int64_t n = (int64_t)V->nx * V->ny * V->nz;
+    for (int64_t q = 0; q < n; ++q) {
+        V->T[q] = 1.0;
+        V->W[q] = 0.0;
+    }
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Fusion of one aligned depth frame, "the same as KinectFusion" (Sec. III overview; Fig. 2:
+ * modify known grids, fill new ones). Reading of the unspecified details:
+ *   q = R^T (p - t); skip if q_z <= 0; project u = fx q_x/q_z + cx, v = fy q_y/q_z + cy; nearest
+ *   pixel (floor(u + 1/2), floor(v + 1/2)); skip outside the image or on invalid depth;
+ *   eta = D - q_z; skip if eta < -tau; phi = min(1, eta/tau);
+ *   T <- (T W + phi)/(W + 1); W <- min(W + 1, W_max) (at the cap the update still uses W_max).
+ * If `amb` is non-null, voxel flags are written: bit 0 when a decision (pixel choice within
+ * `pix_margin` of a rounding boundary, q_z within `eta_margin` of 0, or eta within
+ * `eta_margin` of -tau) is so close that a lower-precision implementation may take it the
+ * other way. Returns the number of updated voxels.
+ * ---------------------------------------------------------------------------------------- */
+int64_t orc_integrate(orc_vol* V, const float* depth, const orc_intr* K, const orc_pose* P,
+                      uint8_t* amb, double pix_margin, double eta_margin) {
+    int64_t total = 0;
+#pragma omp parallel for reduction(+ : total) schedule(static)
+    for (int k = 0; k < V->nz; ++k) {
+        for (int j = 0; j < V->ny; ++j)
+            for (int i = 0; i < V->nx; ++i) {
+                int64_t idx = ((int64_t)k * V->ny + j) * V->nx + i;
+                uint8_t flag = 0;
+                double p[3] = {V->origin[0] + V->vs * i, V->origin[1] + V->vs * j, V->origin[2] + V->vs * k};
+                double d[3] = {p[0] - P->t[0], p[1] - P->t[1], p[2] - P->t[2]};
+                double q[3];
+                for (int a = 0; a < 3; ++a) q[a] = P->R[0 * 3 + a] * d[0] + P->R[1 * 3 + a] * d[1] + P->R[2 * 3 + a] * d[2];
+                if (fabs(q[2]) < eta_margin) flag = 1;
+                if (q[2] <= 0.0) {
+                    if (amb) amb[idx] = flag;
+                    continue;
+                }
+                double u = K->fx * q[0] / q[2] + K->cx;
+                double v = K->fy * q[1] / q[2] + K->cy;
+                double uh = u + 0.5, vh = v + 0.5;
+                if (fabs(uh - nearbyint(uh)) < pix_margin || fabs(vh - nearbyint(vh)) < pix_margin) flag = 1;
+                double uf = floor(uh), vf = floor(vh);
+                if (uf < 0.0 || uf >= K->width || vf < 0.0 || vf >= K->height) {
+                    if (amb) amb[idx] = flag;
+                    continue;
+                }
+                int ui = (int)uf, vi = (int)vf;
+                double D = (double)depth[(int64_t)vi * K->width + ui];
+                if (!(isfinite(D) && D > 0.0)) {
+                    if (amb) amb[idx] = flag;
+                    continue;
+                }
+                double eta = D - q[2];
+                if (fabs(eta + V->tau) < eta_margin) flag = 1;
+                if (amb) amb[idx] = flag;
+                if (eta < -V->tau) continue;
+                double phi = eta / V->tau;
+                if (phi > 1.0) phi = 1.0;
+                double w = V->W[idx];
+                V->T[idx] = (V->T[idx] * w + phi) / (w + 1.0);
+                V->W[idx] = (w + 1.0 < (double)V->w_max) ? w + 1.0 : (double)V->w_max;
+                total += 1;
+            }
+    }
+    return total;
+}
+
+/* ----------------------------------------------------------------------------------------
+ * TSDF query at a world point (Sec. III-B, fitness equation; valid grids). Reading: the query
+ * is trilinear over the 8 voxel centres around the point (lerp in x, then y, then z); the
+ * point is in X_k iff the whole stencil is inside the grid and all 8 corners satisfy |T| < 1
+ * (observed and within the truncation distance; the +1 sentinel marks unobserved voxels).
+ * `cell` optionally forces the lower stencil corner (used for the near-face interval rule).
+ * ---------------------------------------------------------------------------------------- */
+static int sample_cell(const orc_vol* V, const double g[3], const int64_t c[3], double* val) {
+    if (c[0] < 0 || c[1] < 0 || c[2] < 0 || c[0] > V->nx - 2 || c[1] > V->ny - 2 || c[2] > V->nz - 2) return 0;
+    double f[3] = {g[0] - (double)c[0], g[1] - (double)c[1], g[2] - (double)c[2]};
+    double t[2][2][2];
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                int64_t idx = ((c[2] + dz) * V->ny + (c[1] + dy)) * V->nx + (c[0] + dx);
+                double x = V->T[idx];
+                if (!(fabs(x) < 1.0)) return 0;
+                t[dz][dy][dx] = x;
+            }
+    double a00 = t[0][0][0] + f[0] * (t[0][0][1] - t[0][0][0]);
+    double a10 = t[0][1][0] + f[0] * (t[0][1][1] - t[0][1][0]);
+    double a01 = t[1][0][0] + f[0] * (t[1][0][1] - t[1][0][0]);
+    double a11 = t[1][1][0] + f[0] * (t[1][1][1] - t[1][1][0]);
+    double b0 = a00 + f[1] * (a10 - a00);
+    double b1 = a01 + f[1] * (a11 - a01);
+    *val = b0 + f[2] * (b1 - b0);
+    return 1;
+}
+
+static void grid_coord(const orc_vol* V, const double y[3], double g[3]) {
+    for (int a = 0; a < 3; ++a) g[a] = (y[a] - V->origin[a]) / V->vs;
+}
+
+int orc_sample(const orc_vol* V, const double y[3], double* val) {
+    double g[3];
+    grid_coord(V, y, g);
+    int64_t c[3] = {(int64_t)floor(g[0]), (int64_t)floor(g[1]), (int64_t)floor(g[2])};
+    return sample_cell(V, g, c, val);
+}
+
+static void transform(const orc_pose* P, const double x[3], double y[3]) {
+    mat3_vec(P->R, x, y);
+    for (int a = 0; a < 3; ++a) y[a] += P->t[a];
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Fitness E(P) = (1/|X|) sum_{x in X} |TSDF(P x)| / tau (Sec. III-B equation); T is stored
+ * already divided by tau. Reading: E = 1 (the worst value) when X is empty.
+ * ---------------------------------------------------------------------------------------- */
+void orc_fitness(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, double* E, int64_t* nvalid) {
+    double s = 0.0;
+    int64_t c = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        double y[3], v;
+        transform(P, xyz + 3 * j, y);
+        if (orc_sample(V, y, &v)) {
+            s += fabs(v);
+            c += 1;
+        }
+    }
+    *E = c > 0 ? s / (double)c : 1.0;
+    if (nvalid) *nvalid = c;
+}
+
+void orc_fitness_many(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t K,
+                      double* E, int64_t* nvalid) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t k = 0; k < K; ++k) orc_fitness(V, xyz, n, P + k, E + k, nvalid ? nvalid + k : NULL);
+}
+
+/* Interval form for comparison with a float32 evaluation. Samples whose grid coordinate lies
+ * within `eps` voxels of a cell face are evaluated with every admissible lower-corner choice;
+ * the bounds take, per ambiguous sample, the smallest/largest |value| contribution and the
+ * largest/smallest count, so [E_lo, E_hi] contains every outcome of such choices. */
+void orc_fitness_interval(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, double eps,
+                          double* E_lo, double* E_hi, int64_t* n_amb) {
+    double s_lo = 0.0, s_hi = 0.0;
+    int64_t c_lo = 0, c_hi = 0, amb = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        double y[3], g[3];
+        transform(P, xyz + 3 * j, y);
+        grid_coord(V, y, g);
+        int64_t opts[3][2];
+        int nopt[3];
+        int any = 0;
+        for (int a = 0; a < 3; ++a) {
+            double fl = floor(g[a]);
+            opts[a][0] = (int64_t)fl;
+            nopt[a] = 1;
+            double fr = g[a] - fl;
+            if (fr < eps) { opts[a][1] = (int64_t)fl - 1; nopt[a] = 2; any = 1; }
+            else if (fr > 1.0 - eps) { opts[a][1] = (int64_t)fl + 1; nopt[a] = 2; any = 1; }
+        }
+        double amin = 2.0, amax = -1.0;
+        int cmin = 1, cmax = 0;
+        for (int ox = 0; ox < nopt[0]; ++ox)
+            for (int oy = 0; oy < nopt[1]; ++oy)
+                for (int oz = 0; oz < nopt[2]; ++oz) {
+                    int64_t c[3] = {opts[0][ox], opts[1][oy], opts[2][oz]};
+                    double v = 0.0;
+                    int ok = sample_cell(V, g, c, &v);
+                    double a = ok ? fabs(v) : 0.0;
+                    if (a < amin) amin = a;
+                    if (a > amax) amax = a;
+                    if (ok < cmin) cmin = ok;
+                    if (ok > cmax) cmax = ok;
+                }
+        amb += any;
+        s_lo += amin;
+        s_hi += amax;
+        c_lo += cmin;
+        c_hi += cmax;
+    }
+    /* E_lo: smallest numerator over largest count; E_hi: largest numerator over smallest count. */
+    *E_lo = c_hi > 0 ? s_lo / (double)c_hi : 1.0;
+    *E_hi = c_lo > 0 ? s_hi / (double)c_lo : 1.0;
+    if (c_lo == 0) *E_hi = 1.0 > *E_hi ? 1.0 : *E_hi;
+    if (n_amb) *n_amb = amb;
+}
+
+void orc_fitness_interval_many(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t K,
+                               double eps, double* E_lo, double* E_hi, int64_t* n_amb) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t k = 0; k < K; ++k) orc_fitness_interval(V, xyz, n, P + k, eps, E_lo + k, E_hi + k, n_amb + k);
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Randomized optimization of one frame (Sec. III-B; schedule of Sec. IV-A).
+ * ---------------------------------------------------------------------------------------- */
+typedef struct {
+    uint64_t seed;
+    int32_t frame_index, n_iters, K, n_rates;
+    int32_t rates[3];
+    int32_t pixel_stride;
+    double s1_deg, s1_m, beta;
+    int32_t compose_mode, polish_steps, min_valid;
+} orc_params;
+
+typedef struct {      /* per-iteration record, filled for i = 1..n_iters */
+    double E0, Estar, s_rad, s_m;
+    int64_t n_adv, n_pts, nvalid0;
+    orc_pose pose;
+} orc_iter_rec;
+
+/* Subsample view S_r of the compacted cloud: S_r[j] = M[j r], j = 0 .. ceil(n/r) - 1
+ * (reading of the alternating sampling rates; phase 0). */
+static int64_t view(const double* xyz, int64_t n, int32_t r, double* out) {
+    int64_t m = 0;
+    for (int64_t j = 0; j * r < n; ++j, ++m)
+        for (int a = 0; a < 3; ++a) out[3 * m + a] = xyz[3 * j * r + a];
+    return m;
+}
+
+/* Particle k of iteration i: a_k uniform in [-1, 1)^6 (counter RNG), rotation vector
+ * omega * a[0:3] (radians) and translation v * a[3:6] (metres): the "uniform sampling
+ * according to s" read as a 6-D box. */
+void orc_draw_delta(uint64_t seed, int32_t t, int32_t i, int32_t k, double s_rad, double s_m, double r[3], double tau[3]) {
+    for (int d = 0; d < 3; ++d) r[d] = s_rad * orc_uniform_pm1(seed, t, i, k, d);
+    for (int d = 0; d < 3; ++d) tau[d] = s_m * orc_uniform_pm1(seed, t, i, k, 3 + d);
+}
+
+/* One iteration i (1-based) from pose P and search size (s_rad, s_m) on the point set S.
+ * E_0 = E(P; S), E_k = E(compose(delta_k, P); S); advantage set A = {k >= 1 : E_k < E_0}
+ * (strict); the mean rotation vector and mean translation over A (ascending k) form the
+ * averaged delta (reading: arithmetic mean of rotation vectors, then exp); P <- compose(mean,
+ * P) if A is non-empty; E* = E(P; S); s <- s (beta + (1 - beta) E*), the same factor on both
+ * components. If `Ek_out` is non-null the K+1 fitness values are stored (slot 0 = E_0). */
+void orc_ro_iteration(const orc_vol* V, const double* S, int64_t n, const orc_params* prm, int32_t i,
+                      orc_pose* P, double* s_rad, double* s_m, double* Ek_out, int64_t* nv_out, orc_iter_rec* rec) {
+    int32_t K = prm->K;
+    orc_pose* poses = (orc_pose*)malloc(sizeof(orc_pose) * (size_t)(K + 1));
+    double* dr = (double*)malloc(sizeof(double) * 6 * (size_t)(K + 1));
+    double* E = (double*)malloc(sizeof(double) * (size_t)(K + 1));
+    int64_t* nv = (int64_t*)malloc(sizeof(int64_t) * (size_t)(K + 1));
+    poses[0] = *P;
+    for (int32_t k = 1; k <= K; ++k) {
+        orc_draw_delta(prm->seed, prm->frame_index, i, k, *s_rad, *s_m, dr + 6 * k, dr + 6 * k + 3);
+        orc_compose(prm->compose_mode, dr + 6 * k, dr + 6 * k + 3, P, poses + k);
+    }
+    orc_fitness_many(V, S, n, poses, K + 1, E, nv);
+    double sr[3] = {0, 0, 0}, st[3] = {0, 0, 0};
+    int64_t na = 0;
+    for (int32_t k = 1; k <= K; ++k)
+        if (E[k] < E[0]) {
+            for (int a = 0; a < 3; ++a) {
+                sr[a] += dr[6 * k + a];
+                st[a] += dr[6 * k + 3 + a];
+            }
+            na += 1;
+        }
+    if (na > 0) {
+        double mr[3], mt[3];
+        for (int a = 0; a < 3; ++a) {
+            mr[a] = sr[a] / (double)na;
+            mt[a] = st[a] / (double)na;
+        }
+        orc_pose Pn;
+        orc_compose(prm->compose_mode, mr, mt, P, &Pn);
+        *P = Pn;
+    }
+    double Es;
+    int64_t nvs;
+    orc_fitness(V, S, n, P, &Es, &nvs);
+    double f = prm->beta + (1.0 - prm->beta) * Es;
+    if (rec) {
+        rec->E0 = E[0];
+        rec->Estar = Es;
+        rec->n_adv = na;
+        rec->n_pts = n;
+        rec->nvalid0 = nv[0];
+        rec->s_rad = *s_rad;
+        rec->s_m = *s_m;
+        rec->pose = *P;
+    }
+    *s_rad *= f;
+    *s_m *= f;
+    if (Ek_out) memcpy(Ek_out, E, sizeof(double) * (size_t)(K + 1));
+    if (nv_out) memcpy(nv_out, nv, sizeof(int64_t) * (size_t)(K + 1));
+    free(poses);
+    free(dr);
+    free(E);
+    free(nv);
+}
+
+/* Advantage set and averaged update on given fitness values (no scoring): returns |A| and
+ * writes the updated pose. Lets the selection be checked on identical fitness inputs. */
+int64_t orc_advantage_update(const double* E, const double* deltas /*[K+1][6], slot 0 unused*/, int32_t K,
+                             int32_t mode, const orc_pose* P, orc_pose* out, double mean_out[6]) {
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    int64_t na = 0;
+    for (int32_t k = 1; k <= K; ++k)
+        if (E[k] < E[0]) {
+            for (int a = 0; a < 6; ++a) s[a] += deltas[6 * k + a];
+            na += 1;
+        }
+    *out = *P;
+    for (int a = 0; a < 6; ++a) mean_out[a] = 0.0;
+    if (na > 0) {
+        for (int a = 0; a < 6; ++a) mean_out[a] = s[a] / (double)na;
+        orc_compose(mode, mean_out, mean_out + 3, P, out);
+    }
+    return na;
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Gradient of the fitness with respect to a left twist xi = (rho, phi) applied by the same
+ * composition as the delta poses, at xi = 0, with the valid set, the stencil cells and the
+ * signs frozen (not in the paper, which uses no gradients; it differentiates the fitness
+ * equation of Sec. III-B):
+ *   dE/drho = (1/|X|) sum_j s_j grad T(y_j),   dE/dphi = (1/|X|) sum_j (y_j - c) x s_j grad T(y_j)
+ * with s_j = sign(T(y_j)) (sign(0) = 0), grad T the analytic trilinear gradient / vs, and c the
+ * camera centre t (decoupled) or 0 (literal). grad6 = (rho[3], phi[3]).
+ * ---------------------------------------------------------------------------------------- */
+static void trilinear_grad(const orc_vol* V, const int64_t c[3], const double f[3], double gT[3]) {
+    double t[2][2][2];
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx)
+                t[dz][dy][dx] = V->T[((c[2] + dz) * V->ny + (c[1] + dy)) * V->nx + (c[0] + dx)];
+    double gx = 0, gy = 0, gz = 0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy) {
+            double wy = dy ? f[1] : 1.0 - f[1], wz = dz ? f[2] : 1.0 - f[2];
+            gx += (t[dz][dy][1] - t[dz][dy][0]) * wy * wz;
+        }
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dx = 0; dx < 2; ++dx) {
+            double wx = dx ? f[0] : 1.0 - f[0], wz = dz ? f[2] : 1.0 - f[2];
+            gy += (t[dz][1][dx] - t[dz][0][dx]) * wx * wz;
+        }
+    for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+            double wx = dx ? f[0] : 1.0 - f[0], wy = dy ? f[1] : 1.0 - f[1];
+            gz += (t[1][dy][dx] - t[0][dy][dx]) * wx * wy;
+        }
+    gT[0] = gx / V->vs;
+    gT[1] = gy / V->vs;
+    gT[2] = gz / V->vs;
+}
+
+void orc_fitness_grad(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t mode,
+                      double* E, double grad6[6], int64_t* nvalid) {
+    double s = 0.0, g[6] = {0, 0, 0, 0, 0, 0};
+    int64_t cnt = 0;
+    double cc[3] = {0, 0, 0};
+    if (mode == 0)
+        for (int a = 0; a < 3; ++a) cc[a] = P->t[a];
+    for (int64_t j = 0; j < n; ++j) {
+        double y[3], gg[3], v;
+        transform(P, xyz + 3 * j, y);
+        grid_coord(V, y, gg);
+        int64_t c[3] = {(int64_t)floor(gg[0]), (int64_t)floor(gg[1]), (int64_t)floor(gg[2])};
+        if (!sample_cell(V, gg, c, &v)) continue;
+        double f[3] = {gg[0] - c[0], gg[1] - c[1], gg[2] - c[2]};
+        double gT[3];
+        trilinear_grad(V, c, f, gT);
+        double sg = v > 0 ? 1.0 : (v < 0 ? -1.0 : 0.0);
+        double u[3] = {y[0] - cc[0], y[1] - cc[1], y[2] - cc[2]};
+        s += fabs(v);
+        cnt += 1;
+        for (int a = 0; a < 3; ++a) g[a] += sg * gT[a];
+        g[3] += sg * (u[1] * gT[2] - u[2] * gT[1]);
+        g[4] += sg * (u[2] * gT[0] - u[0] * gT[2]);
+        g[5] += sg * (u[0] * gT[1] - u[1] * gT[0]);
+    }
+    if (cnt > 0) {
+        *E = s / (double)cnt;
+        for (int a = 0; a < 6; ++a) grad6[a] = g[a] / (double)cnt;
+    } else {
+        *E = 1.0;
+        for (int a = 0; a < 6; ++a) grad6[a] = 0.0;
+    }
+    if (nvalid) *nvalid = cnt;
+}
+
+void orc_fitness_grad_many(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t B,
+                           int32_t mode, double* E, double* grad, int64_t* nvalid) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t b = 0; b < B; ++b) orc_fitness_grad(V, xyz, n, P + b, mode, E + b, grad + 6 * b, nvalid ? nvalid + b : NULL);
+}
+
+/* Frozen objective E_f(xi) = (1/|X0|) sum_{j in X0} s_j T_cell_j(y_j(xi)): the valid set X0, the
+ * cells and the signs are those of xi = 0, and T_cell_j is the trilinear polynomial of the
+ * cell (extended beyond it if y moves out). Its derivative at 0 is orc_fitness_grad; it is a
+ * polynomial in y, so central differences converge at O(h^2). */
+double orc_fitness_frozen(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t mode,
+                          const double xi[6]) {
+    orc_pose Px;
+    orc_compose(mode, xi + 3, xi, P, &Px);
+    double s = 0.0;
+    int64_t cnt = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        double y0[3], g0[3], v0;
+        transform(P, xyz + 3 * j, y0);
+        grid_coord(V, y0, g0);
+        int64_t c[3] = {(int64_t)floor(g0[0]), (int64_t)floor(g0[1]), (int64_t)floor(g0[2])};
+        if (!sample_cell(V, g0, c, &v0)) continue;
+        double sg = v0 > 0 ? 1.0 : (v0 < 0 ? -1.0 : 0.0);
+        double y[3], g[3], v;
+        transform(&Px, xyz + 3 * j, y);
+        grid_coord(V, y, g);
+        /* evaluate the frozen cell's polynomial at the moved point (stencil values already checked) */
+        double f[3] = {g[0] - c[0], g[1] - c[1], g[2] - c[2]};
+        double t[2][2][2];
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx)
+                    t[dz][dy][dx] = V->T[((c[2] + dz) * V->ny + (c[1] + dy)) * V->nx + (c[0] + dx)];
+        double a00 = t[0][0][0] + f[0] * (t[0][0][1] - t[0][0][0]);
+        double a10 = t[0][1][0] + f[0] * (t[0][1][1] - t[0][1][0]);
+        double a01 = t[1][0][0] + f[0] * (t[1][0][1] - t[1][0][0]);
+        double a11 = t[1][1][0] + f[0] * (t[1][1][1] - t[1][1][0]);
+        double b0 = a00 + f[1] * (a10 - a00);
+        double b1 = a01 + f[1] * (a11 - a01);
+        v = b0 + f[2] * (b1 - b0);
+        s += sg * v;
+        cnt += 1;
+    }
+    return cnt > 0 ? s / (double)cnt : 1.0;
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Gradient polish of a pose (not in the paper; a deterministic rule stated here):
+ * `steps` steps of xi = -alpha grad E (grad from orc_fitness_grad). The first alpha of each
+ * step makes the largest point displacement bound alpha (|g_rho| + |g_phi| Rmax) equal to half
+ * a voxel, Rmax = max_j |y_j - c|; Armijo: accept if E(new) <= E - 1e-4 alpha |g|^2, else halve,
+ * at most 5 halvings; stop when no halving is accepted. Returns the number of accepted steps.
+ * ---------------------------------------------------------------------------------------- */
+int32_t orc_polish(const orc_vol* V, const double* xyz, int64_t n, orc_pose* P, int32_t mode, int32_t steps,
+                   double* E_out) {
+    int32_t acc = 0;
+    double E, g[6];
+    int64_t nv;
+    orc_fitness_grad(V, xyz, n, P, mode, &E, g, &nv);
+    for (int32_t it = 0; it < steps; ++it) {
+        if (nv == 0) break;
+        double cc[3] = {0, 0, 0};
+        if (mode == 0)
+            for (int a = 0; a < 3; ++a) cc[a] = P->t[a];
+        double rmax = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double y[3];
+            transform(P, xyz + 3 * j, y);
+            double d = sqrt((y[0] - cc[0]) * (y[0] - cc[0]) + (y[1] - cc[1]) * (y[1] - cc[1]) + (y[2] - cc[2]) * (y[2] - cc[2]));
+            if (d > rmax) rmax = d;
+        }
+        double nr = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        double nphi = sqrt(g[3] * g[3] + g[4] * g[4] + g[5] * g[5]);
+        double gg = nr * nr + nphi * nphi;
+        double denom = nr + nphi * rmax;
+        if (!(denom > 0.0)) break;
+        double alpha = 0.5 * V->vs / denom;
+        int ok = 0;
+        orc_pose Pn;
+        double En = E;
+        for (int h = 0; h <= 5; ++h) {
+            double xi[6];
+            for (int a = 0; a < 6; ++a) xi[a] = -alpha * g[a];
+            orc_compose(mode, xi + 3, xi, P, &Pn);
+            int64_t nvn;
+            orc_fitness(V, xyz, n, &Pn, &En, &nvn);
+            if (En <= E - 1e-4 * alpha * gg) {
+                ok = 1;
+                break;
+            }
+            alpha *= 0.5;
+        }
+        if (!ok) break;
+        *P = Pn;
+        acc += 1;
+        orc_fitness_grad(V, xyz, n, P, mode, &E, g, &nv);
+    }
+    if (E_out) *E_out = E;
+    return acc;
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Tracking of one frame: back-project with the pixel stride, then n_iters iterations with the
+ * rate cycle rates[(i-1) mod n_rates] and s^(1) = (s1_deg, s1_m) (Sec. IV-A), then optional
+ * polish of the best of {P^(I)} and the last iteration's particles on the densest view.
+ * Returns the number of points of the full cloud; -1 on allocation failure.
+ * ---------------------------------------------------------------------------------------- */
+int64_t orc_track_frame(const orc_vol* V, const float* depth, const orc_intr* Kin, const orc_pose* init,
+                        const orc_params* prm, orc_pose* out, orc_iter_rec* recs) {
+    int64_t npix = (int64_t)Kin->width * Kin->height;
+    double* xyz = (double*)malloc(sizeof(double) * 3 * (size_t)npix);
+    double* S = (double*)malloc(sizeof(double) * 3 * (size_t)npix);
+    if (!xyz || !S) { free(xyz); free(S); return -1; }
+    int64_t n = orc_backproject(depth, Kin, prm->pixel_stride, xyz, NULL);
+    orc_pose P = *init;
+    double s_rad = prm->s1_deg * M_PI / 180.0, s_m = prm->s1_m;
+    double* Ek = (double*)malloc(sizeof(double) * (size_t)(prm->K + 1));
+    orc_pose best = P;
+    for (int32_t i = 1; i <= prm->n_iters; ++i) {
+        int32_t r = prm->rates[(i - 1) % prm->n_rates];
+        int64_t m = view(xyz, n, r, S);
+        orc_pose Pprev = P;
+        double sr_prev = s_rad, sm_prev = s_m;
+        orc_iter_rec rec;
+        orc_ro_iteration(V, S, m, prm, i, &P, &s_rad, &s_m, Ek, NULL, &rec);
+        if (recs) recs[i - 1] = rec;
+        if (i == prm->n_iters) {
+            /* best of {P^(I)} (fitness E*) and the particles of iteration I (fitness E_k), all on
+             * S_I; ties go to P^(I), then to the lowest particle index */
+            double Eb = rec.Estar;
+            best = P;
+            for (int32_t k = 1; k <= prm->K; ++k)
+                if (Ek[k] < Eb) {
+                    double dr[3], dt[3];
+                    orc_draw_delta(prm->seed, prm->frame_index, i, k, sr_prev, sm_prev, dr, dt);
+                    orc_compose(prm->compose_mode, dr, dt, &Pprev, &best);
+                    Eb = Ek[k];
+                }
+        }
+    }
+    free(Ek);
+    if (prm->polish_steps > 0 && n > 0 && prm->n_iters > 0) {
+        /* polish the best candidate on the densest view */
+        int32_t rmin = prm->rates[0];
+        for (int q = 1; q < prm->n_rates; ++q) rmin = prm->rates[q] < rmin ? prm->rates[q] : rmin;
+        int64_t m = view(xyz, n, rmin, S);
+        double E;
+        P = best;
+        orc_polish(V, S, m, &P, prm->compose_mode, prm->polish_steps, &E);
+    }
+    *out = P;
+    free(xyz);
+    free(S);
+    return n;
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Exhaustive search over a 6-D grid of deltas around `centre`: m points per axis on
+ * {-(m-1)/2 .. (m-1)/2} times (rot_step rad, trans_step m) in the order
+ * index = ((((r0*m + r1)*m + r2)*m + t0)*m + t1)*m + t2. Returns the argmin (ties to the lowest
+ * index) and writes every fitness to E (m^6 values).
+ * ---------------------------------------------------------------------------------------- */
+int64_t orc_grid_search(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* centre, int32_t m,
+                        double rot_step, double trans_step, int32_t mode, double* E) {
+    int64_t total = 1;
+    for (int a = 0; a < 6; ++a) total *= m;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < total; ++q) {
+        int64_t rem = q;
+        int idx[6];
+        for (int a = 5; a >= 0; --a) {
+            idx[a] = (int)(rem % m);
+            rem /= m;
+        }
+        double r[3], tau[3];
+        for (int a = 0; a < 3; ++a) {
+            r[a] = (idx[a] - 0.5 * (m - 1)) * rot_step;
+            tau[a] = (idx[3 + a] - 0.5 * (m - 1)) * trans_step;
+        }
+        orc_pose P;
+        orc_compose(mode, r, tau, centre, &P);
+        orc_fitness(V, xyz, n, &P, E + q, NULL);
+    }
+    int64_t best = 0;
+    for (int64_t q = 1; q < total; ++q)
+        if (E[q] < E[best]) best = q;
+    return best;
+}

@@ -1,0 +1,275 @@
+/*
+ * profusion.h - C ABI of the MI355X (gfx950) library for the data-parallel hot path of
+ * PROFusion (arXiv 2509.24236): the randomized, particle-based 6-DoF pose optimization that
+ * aligns a depth frame to the scene TSDF (Sec. III-B), and the per-frame TSDF fusion
+ * (Sec. III, "Method overview"; Fig. 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status:   every int32_t-returning call returns PF_OK (0) or a negative PF_E* code and never
+ *           throws. pf_last_error() returns a thread-local message for the last failure.
+ *           Arguments are validated before any launch; on PF_EINVAL nothing was enqueued.
+ * Memory:   every pointer documented as "device" is caller-owned device memory of the current
+ *           HIP device (for example torch tensors). The library never allocates or frees
+ *           device memory in these calls; scratch space is passed in as `workspace`.
+ *           "host" pointers are read during the call only.
+ * Streams:  `stream` is a hipStream_t (NULL = the default stream). All work is enqueued on it
+ *           and the calls return without waiting, except where a call says it synchronises.
+ * Poses:    camera -> world, x_world = R x_cam + t, R row-major (Sec. III: the camera pose "in
+ *           the world coordinate system"); the world frame is the first frame's camera frame.
+ * Units:    metres and radians inside; the search size parameters are given in degrees and
+ *           metres (the paper states s = (omega degrees, v cm), Sec. III-B).
+ * Volume:   voxel (i, j, k) has its centre at origin + voxel_size * (i, j, k); storage is
+ *           x-fastest, T[(k*ny + j)*nx + i]. T is the TSDF divided by the truncation distance
+ *           tau (so the fitness equation's 1/tau is folded into storage) and +1 marks a voxel
+ *           that is unobserved or free beyond the band.
+ */
+#ifndef PROFUSION_H
+#define PROFUSION_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------------------ status */
+#define PF_OK 0
+#define PF_EINVAL (-1)       /* bad argument: null pointer, bad size, non-orthonormal R ... */
+#define PF_ENOMEM (-2)       /* workspace smaller than the size query returned */
+#define PF_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
+#define PF_EUNSUPPORTED (-4) /* a valid request this build does not implement */
+
+/* ------------------------------------------------------------------------------ formats */
+#define PF_F32_W_F32 0   /* T float32, W float32 (integer-valued) */
+#define PF_F16_W_U8 1    /* T float16 (+1 sentinel), W uint8 */
+#define PF_I16_W_U8 2    /* T int16 = RNE(T * 32767), 32767 sentinel, W uint8 */
+
+/* Storage layouts of the T buffer.
+ * LINEAR: T x-fastest only (nx*ny*nz elements).
+ * CELLS:  T x-fastest, then (at byte offset tsdf_cells_offset()) a cell-major replica used by
+ *         particle scoring: cell (i, j, k), i < nx-1, j < ny-1, k < nz-1, stored at index
+ *         (k*(ny-1) + j)*(nx-1) + i as its 8 corner values in the order (dx, dy, dz) =
+ *         (0,0,0) (1,0,0) (0,1,0) (1,1,0) (0,0,1) (1,0,1) (0,1,1) (1,1,1). A sample then reads
+ *         one contiguous 32-byte (FP32) or 16-byte block instead of four rows; the replica is 8x
+ *         the size of T and is kept equal to T by tsdf_init, tsdf_import_linear and
+ *         tsdf_integrate (which rewrites only the cells of voxels whose stored value changed). */
+#define PF_LAYOUT_LINEAR 0
+#define PF_LAYOUT_CELLS 1
+
+/* Delta-pose composition, the reading of "Delta P_k P^(i-1)" (Sec. III-B):
+ * DECOUPLED: (exp(r) R, t + tau) - rotate about the camera centre, then shift;
+ * LITERAL:   (exp(r) R, exp(r) t + tau) - the left matrix product [exp(r) | tau] P. */
+#define PF_COMPOSE_DECOUPLED 0
+#define PF_COMPOSE_LITERAL 1
+
+#define PF_MAX_ITERS 64
+#define PF_MAX_K 65536
+
+typedef struct pf_pose {
+    double R[9]; /* row-major rotation, camera -> world */
+    double t[3]; /* camera centre in world coordinates, metres */
+} pf_pose;
+
+typedef struct pf_intrinsics {
+    double fx, fy, cx, cy; /* pinhole: u = fx x/z + cx, v = fy y/z + cy (pixels) */
+    int32_t width, height;
+} pf_intrinsics;
+
+typedef struct pf_tsdf {
+    int32_t nx, ny, nz;  /* voxels per axis, each >= 2; nx*ny*nz < 2^31 */
+    int32_t format;      /* PF_F32_W_F32, PF_F16_W_U8 or PF_I16_W_U8 */
+    double voxel_size;   /* metres, > 0 */
+    double trunc;        /* truncation distance tau, metres, > 0 */
+    double origin[3];    /* centre of voxel (0,0,0), world metres */
+    int32_t w_max;       /* weight cap, 1..255 */
+    int32_t layout;      /* PF_LAYOUT_LINEAR or PF_LAYOUT_CELLS */
+    void* tsdf;          /* device, tsdf_bytes() bytes */
+    void* weight;        /* device, *weight_bytes bytes */
+} pf_tsdf;
+
+/* Parameters of one frame's randomized optimization (Sec. III-B; schedule of Sec. IV-A). */
+typedef struct pf_track_params {
+    uint64_t seed;          /* key of the counter-based random stream */
+    int32_t frame_index;    /* t, part of the random-stream counter, 0 .. 2^24-1 */
+    int32_t n_iters;        /* I, 1 .. PF_MAX_ITERS (the paper caps it at 20) */
+    int32_t K;              /* particles per iteration, 1 .. PF_MAX_K */
+    int32_t n_rates;        /* 1 .. 3 */
+    int32_t rates[3];       /* point sub-sampling strides; iteration i uses rates[(i-1) mod n_rates] */
+    int32_t pixel_stride;   /* keep pixels with u, v multiples of it (1 = every pixel) */
+    double s1_deg, s1_m;    /* initial search size s^(1) (the paper uses 10 deg, 10 cm) */
+    double beta;            /* search-size momentum (the paper uses 0.1) */
+    int32_t compose_mode;   /* PF_COMPOSE_* */
+    int32_t polish_steps;   /* gradient polish steps after the last iteration (0 = none) */
+    int32_t min_valid;      /* stats.lost is set when the final pose has fewer valid samples */
+    int32_t reserved;       /* must be 0 */
+} pf_track_params;
+
+/* Per-frame record written by track_frame (host). */
+typedef struct pf_track_stats {
+    int32_t n_points;               /* valid back-projected points at the pixel stride */
+    int32_t n_iters;
+    int32_t lost;                   /* 1 if the final valid count < min_valid */
+    int32_t polish_accepted;        /* accepted polish steps */
+    float E0[PF_MAX_ITERS];         /* E(P^(i-1)) on S_i */
+    float Estar[PF_MAX_ITERS];      /* E(P^(i)) on S_i */
+    int32_t n_adv[PF_MAX_ITERS];    /* |advantage set| */
+    int32_t n_sub[PF_MAX_ITERS];    /* |S_i| */
+    int32_t n_valid[PF_MAX_ITERS];  /* |X| of P^(i) on S_i */
+    double s_rad[PF_MAX_ITERS];     /* s^(i), rotation part */
+    double s_m[PF_MAX_ITERS];       /* s^(i), translation part */
+    float E_final;                  /* fitness of the returned pose on the densest view */
+    int32_t n_valid_final;
+} pf_track_stats;
+
+/* Device-resident optimizer state used by particles_update. The layout is public so callers
+ * can read it back. The same buffer holds, at byte offset PF_STATE_DELTAS_OFFSET, the deltas of
+ * the pending particles as FP64 [K+1][6] (rotation vector, translation; slot 0 is zero), and
+ * after them scratch for per-workgroup partial sums. */
+typedef struct pf_track_state {
+    /* the pending iteration: particles drawn around P^(i-1) with search size s^(i) */
+    double R[9], t[3];     /* P^(i-1) */
+    double s_rad, s_m;     /* s^(i) */
+    /* the last completed iteration */
+    double R_new[9], t_new[3]; /* P^(i) */
+    double s_rad_done, s_m_done; /* s^(i) of that iteration */
+    double E0, Estar;      /* E(P^(i-1)) and E(P^(i)) on S_i */
+    double mean[6];        /* averaged delta (r, tau) */
+    double beta;
+    uint64_t seed;
+    int32_t frame_index;
+    int32_t iter;          /* i of the pending particles (1-based) */
+    int32_t iter_done;     /* i of the last completed iteration (0 = none) */
+    int32_t K;
+    int32_t compose_mode;
+    int32_t n_adv;         /* |A| of the last completed iteration */
+    int32_t n_sub;         /* |S_i| of the last completed iteration */
+    int32_t n_valid_star;  /* |X| of P^(i) */
+    int32_t flags;         /* bit 0: particles_update called with a K other than the state's */
+    int32_t reserved;
+} pf_track_state;
+
+#define PF_STATE_DELTAS_OFFSET 512
+
+/* ------------------------------------------------------------------------------ errors */
+
+/* Message of the last failed call on this thread ("" if none). Owned by the library. */
+const char* pf_last_error(void);
+
+/* ------------------------------------------------------------------------------ volume */
+
+/* Bytes the caller must allocate for v->tsdf (returned) and v->weight (*weight_bytes, may be
+ * NULL). Reads only nx, ny, nz, format and layout; returns 0 for an invalid description. */
+size_t tsdf_bytes(const pf_tsdf* v, size_t* weight_bytes);
+
+/* Byte offset of the cell-major replica inside v->tsdf (PF_LAYOUT_CELLS), 0 otherwise. */
+size_t tsdf_cells_offset(const pf_tsdf* v);
+
+/* Sets every voxel to the initial state T = +1 (unobserved), W = 0 (Sec. III overview: the
+ * scene is a dense tensor of distance values; the first frame fills it). */
+int32_t tsdf_init(const pf_tsdf* v, void* stream);
+
+/* Fuses one aligned depth frame, "the same as KinectFusion" (Sec. III overview; Fig. 2:
+ * known grids are modified and new ones filled). For each voxel centre p:
+ *   q = R^T (p - t); skip if q_z <= 0; (u, v) = (fx q_x/q_z + cx, fy q_y/q_z + cy);
+ *   nearest pixel (floor(u + 1/2), floor(v + 1/2)), skip if outside the image or if its depth
+ *   is not finite and > 0; eta = D - q_z; skip if eta < -tau; phi = min(1, eta/tau);
+ *   T <- (T W + phi)/(W + 1); W <- min(W + 1, w_max).
+ * The projection runs in FP64 (so the update decisions match an FP64 reference exactly) and
+ * the running average in the storage format's arithmetic (FP32).
+ * depth: device, float32 [height][width], metres; 0, negative or non-finite = invalid.
+ * K, cam_to_world: host. R must be orthonormal to 1e-9, else PF_EINVAL. */
+int32_t tsdf_integrate(const pf_tsdf* v, const float* depth, const pf_intrinsics* K,
+                       const pf_pose* cam_to_world, void* stream);
+
+/* Copies the volume out as FP32 x-fastest arrays (T_out, W_out: device, nx*ny*nz floats;
+ * W_out may be NULL). For the int16 format T = q/32767; for fp16, T = (float)half. */
+int32_t tsdf_export_linear(const pf_tsdf* v, float* T_out, float* W_out, void* stream);
+
+/* Loads the volume from FP32 x-fastest arrays (device; W_in may be NULL = all 0), converting
+ * to the storage format (int16: RNE(T*32767) clamped to +-32767; uint8: RNE, clamped). */
+int32_t tsdf_import_linear(const pf_tsdf* v, const float* T_in, const float* W_in, void* stream);
+
+/* ------------------------------------------------------------------------------ points */
+
+/* Back-projects a depth image to the metric point cloud M_t (Sec. III, problem setting):
+ * pixel (u, v) with finite depth z > 0 and u, v multiples of pixel_stride gives
+ * (x, y, z) = ((u - cx) z/fx, (v - cy) z/fy, z). Points are compacted in raster order
+ * (v-major) into px, py, pz (device, width*height floats each). n_out: device int32 buffer of
+ * at least 1 + ceil(width*height / 1024) values; n_out[0] receives the count, the rest is
+ * scratch for the per-workgroup counts of the compaction. */
+int32_t backproject(const float* depth, const pf_intrinsics* K, int32_t pixel_stride, float* px,
+                    float* py, float* pz, int32_t* n_out, void* stream);
+
+/* ------------------------------------------------------------------------------ particles */
+
+/* Fitness of K poses against the TSDF (Sec. III-B, fitness equation):
+ *   E_k = (1/|X_k|) sum_{x in X_k} |T(R_k x + t_k)|,
+ * where T(.) is the trilinear interpolation of the 8 voxel centres around the point and x is
+ * in X_k iff that stencil lies inside the grid and all 8 stored values satisfy |T| < 1
+ * (observed and within the truncation distance: the "valid grids"). E_k = 1 if X_k is empty.
+ * px, py, pz: device, n_pts floats (camera coordinates, metres), n_pts >= 1.
+ * poses: device, [K][12] float32, row-major 3x4 [R | t] camera -> world.
+ * fitness: device, K floats; n_valid: device, K int32 (|X_k|).
+ * Sums are FP32 in a fixed order, so results are bitwise reproducible. */
+int32_t particles_score(const pf_tsdf* v, const float* px, const float* py, const float* pz,
+                        int32_t n_pts, const float* poses, int32_t K, float* fitness,
+                        int32_t* n_valid, void* stream);
+
+/* Bytes of the device state buffer for K particles (pf_track_state + (K+1)*6 doubles). */
+size_t particles_state_bytes(int32_t K);
+
+/* Initialises the device state for one frame: P^(0) = init (host), s^(1) from p (degrees are
+ * converted to radians), iteration 1, and draws the K particles of iteration 1 into
+ * next_poses (device, [K+1][12] float32; slot 0 = P^(0)). */
+int32_t particles_state_init(void* state, const pf_pose* init, const pf_track_params* p,
+                             float* next_poses, void* stream);
+
+/* One step of the randomized optimization (Sec. III-B) after the pending particles of
+ * iteration i were scored on the point set S_i (px, py, pz, n_pts) into fitness / n_valid
+ * ([K+1], slot 0 = the current pose P^(i-1)):
+ *   A = {k >= 1 : E_k < E_0} (strict); if A is non-empty, P^(i) = compose(mean over A of the
+ *   rotation vectors and of the translations, P^(i-1)), else P^(i) = P^(i-1);
+ *   E* = E(P^(i); S_i); s^(i+1) = s^(i) (beta + (1 - beta) E*);
+ * then draws the K particles of iteration i+1: a in [-1,1)^6 from SplitMix64 at counter
+ * t<<40 | (i+1)<<32 | k<<3 | d, rotation vector omega a[0:3], translation v a[3:6], composed
+ * with P^(i) in FP64 and rounded to float32 into next_poses (slot 0 = P^(i)).
+ * state: device buffer of particles_state_bytes(K) bytes; K must equal the K the state was
+ * initialised with (a mismatch sets bit 0 of state->flags and leaves the state unchanged). */
+int32_t particles_update(const pf_tsdf* v, const float* px, const float* py, const float* pz,
+                         int32_t n_pts, const float* fitness, const int32_t* n_valid,
+                         void* state, int32_t K, float* next_poses, void* stream);
+
+/* ------------------------------------------------------------------------------ frame */
+
+/* Workspace bytes for track_frame with these intrinsics and parameters. */
+size_t track_workspace_bytes(const pf_intrinsics* K, const pf_track_params* p);
+
+/* Randomized optimization of one frame (Sec. III-B, schedule of Sec. IV-A): back-projects
+ * the depth at the pixel stride, builds the sub-sampled views S_r[j] = M[j r], runs n_iters
+ * iterations of particles_score + particles_update on the device, optionally polishes the best
+ * candidate (polish_steps > 0, see particles_score_grad), then synchronises the stream and
+ * writes the final pose to *out (host) and the per-iteration record to *stats (host,
+ * nullable). It does not fuse the frame: call tsdf_integrate with *out afterwards.
+ * depth: device float32 [height][width]; init: host; workspace: device, >= ws_bytes. */
+int32_t track_frame(const pf_tsdf* v, const float* depth, const pf_intrinsics* K,
+                    const pf_pose* init, const pf_track_params* p, pf_pose* out,
+                    pf_track_stats* stats, void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------ timing */
+
+/* Kernel timing of the particle-scoring launches made by track_frame: when enabled, each such
+ * launch is bracketed by HIP events on the call's stream and, once track_frame has synchronised,
+ * the elapsed times, the number of launches and the number of evaluated (pose, point) samples
+ * (sum of poses x points per launch) are accumulated in process-wide counters. */
+int32_t pf_timing_enable(int32_t on);
+
+/* Reads the counters (any pointer may be NULL) and optionally resets them. */
+int32_t pf_timing_read(double* score_ms, int64_t* score_launches, int64_t* score_evals, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROFUSION_H */

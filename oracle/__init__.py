@@ -89,6 +89,7 @@ def lib():
         L = C.CDLL(_LIB)
         P = C.POINTER
         dp, i64p = P(C.c_double), P(C.c_int64)
+        L.orc_num_threads.restype = C.c_int32
         L.orc_splitmix64.restype = C.c_uint64
         L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_counter.restype = C.c_uint64
@@ -132,6 +133,11 @@ def _dp(a: np.ndarray):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(lib().orc_num_threads())
 
 
 # ----------------------------------------------------------------------------- RNG and SO(3)

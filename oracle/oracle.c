@@ -19,6 +19,9 @@
  * equation is folded into storage); T = +1 means unobserved or free beyond the band.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -32,6 +35,15 @@ typedef struct {
     double* T;
     double* W;
 } orc_vol;
+
+/* Threads the OpenMP loops of this oracle use (1 without OpenMP). */
+int32_t orc_num_threads(void) {
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ----------------------------------------------------------------------------------------
  * Counter-based random numbers (reading: the paper does not name a generator).

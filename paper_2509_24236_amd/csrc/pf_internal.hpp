@@ -1,0 +1,128 @@
+// Internal declarations of the gfx950 library: device helpers shared by the kernels and the
+// launchers the C ABI calls. Nothing here is part of the public ABI (include/profusion.h).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/profusion.h"
+
+namespace pf {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ error plumbing (pf_capi.hip)
+int32_t set_error(int32_t code, const char* fmt, ...);
+int32_t check_launch(const char* what);
+
+// ------------------------------------------------------------------ device helpers
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): n-th output of the generator whose state
+// starts at `seed` is mix(seed + (n + 1) * 0x9E3779B97F4A7C15).
+__device__ __host__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t n) {
+    uint64_t z = seed + (n + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Draw for (frame t, iteration i, particle k, dimension d): counter t<<40 | i<<32 | k<<3 | d,
+// top 53 bits scaled to [0, 1), then 2u - 1 in [-1, 1); every step is exact in FP64.
+__device__ inline double draw_pm1(uint64_t seed, uint32_t t, uint32_t i, uint32_t k, uint32_t d) {
+    uint64_t n = ((uint64_t)t << 40) | ((uint64_t)i << 32) | ((uint64_t)k << 3) | (uint64_t)d;
+    uint64_t x = splitmix64_at(seed, n);
+    double u = (double)(x >> 11) * 0x1.0p-53;
+    return 2.0 * u - 1.0;
+}
+
+// Rotation matrix of a rotation vector w (radians), row-major: I + a [w]x + b [w]x^2 with
+// a = sin(th)/th and b = (1 - cos th)/th^2, series a = 1 - th^2/6, b = 1/2 - th^2/24 below 1e-6.
+__device__ inline void rotvec_to_matrix(const double w[3], double M[9]) {
+    double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double th = sqrt(th2);
+    double a, b;
+    if (th < 1e-6) {
+        a = 1.0 - th2 / 6.0;
+        b = 0.5 - th2 / 24.0;
+    } else {
+        double s, c;
+        sincos(th, &s, &c);
+        a = s / th;
+        b = (1.0 - c) / th2;
+    }
+    // [w]x^2 = w w^T - th^2 I
+    M[0] = 1.0 + b * (w[0] * w[0] - th2);
+    M[4] = 1.0 + b * (w[1] * w[1] - th2);
+    M[8] = 1.0 + b * (w[2] * w[2] - th2);
+    M[1] = -a * w[2] + b * w[0] * w[1];
+    M[3] = a * w[2] + b * w[0] * w[1];
+    M[2] = a * w[1] + b * w[0] * w[2];
+    M[6] = -a * w[1] + b * w[0] * w[2];
+    M[5] = -a * w[0] + b * w[1] * w[2];
+    M[7] = a * w[0] + b * w[1] * w[2];
+}
+
+// Delta pose (rotation vector r, translation tau) applied to (R, t); see PF_COMPOSE_*.
+__device__ inline void apply_delta(int mode, const double r[3], const double tau[3], const double R[9],
+                                   const double t[3], double Ro[9], double to[3]) {
+    double D[9];
+    rotvec_to_matrix(r, D);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            Ro[a * 3 + b] = D[a * 3 + 0] * R[0 * 3 + b] + D[a * 3 + 1] * R[1 * 3 + b] + D[a * 3 + 2] * R[2 * 3 + b];
+    if (mode == PF_COMPOSE_LITERAL) {
+        for (int a = 0; a < 3; ++a) to[a] = D[a * 3 + 0] * t[0] + D[a * 3 + 1] * t[1] + D[a * 3 + 2] * t[2] + tau[a];
+    } else {
+        for (int a = 0; a < 3; ++a) to[a] = t[a] + tau[a];
+    }
+}
+
+__device__ inline void store_pose12(float* dst, const double R[9], const double t[3]) {
+    dst[0] = (float)R[0]; dst[1] = (float)R[1]; dst[2] = (float)R[2];  dst[3] = (float)t[0];
+    dst[4] = (float)R[3]; dst[5] = (float)R[4]; dst[6] = (float)R[5];  dst[7] = (float)t[1];
+    dst[8] = (float)R[6]; dst[9] = (float)R[7]; dst[10] = (float)R[8]; dst[11] = (float)t[2];
+}
+
+// ------------------------------------------------------------------ volume view for kernels
+struct VolView {
+    const void* T;       // x-fastest storage
+    const void* cells;   // cell-major replica (PF_LAYOUT_CELLS), else nullptr
+    int nx, ny, nz, format, layout;
+    float inv_vs;        // 1 / voxel_size
+    float gx0, gy0, gz0; // -origin / voxel_size: grid coordinate of the world origin
+};
+
+VolView make_view(const pf_tsdf* v);
+
+// Element size of T and W for a format, and the byte offset of the cell replica in the T buffer.
+size_t t_elem_bytes(int format);
+size_t cells_offset_bytes(const pf_tsdf* v);
+
+// Per-lane point block used by the scoring launchers: SoA camera coordinates.
+struct Points {
+    const float* x;
+    const float* y;
+    const float* z;
+    int n;              // used when n_dev == nullptr
+    const int* n_dev;   // device count (track_frame's compacted views)
+};
+
+// ------------------------------------------------------------------ launchers
+int32_t launch_tsdf_init(const pf_tsdf* v, hipStream_t s);
+int32_t launch_tsdf_integrate(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* P,
+                              hipStream_t s);
+int32_t launch_tsdf_export(const pf_tsdf* v, float* T, float* W, hipStream_t s);
+int32_t launch_tsdf_import(const pf_tsdf* v, const float* T, const float* W, hipStream_t s);
+
+// Scores poses [K][12] (camera -> world float32) into fitness / n_valid.
+int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
+                     hipStream_t s);
+
+// Largest number of per-workgroup partial sums the single-pose passes use.
+constexpr int kMaxPartials = 256;
+
+int32_t launch_backproject(const float* depth, const pf_intrinsics* K, int stride, float* px, float* py, float* pz,
+                           int* n_out, int* block_counts, hipStream_t s);
+size_t backproject_scratch_ints(const pf_intrinsics* K);
+
+}  // namespace pf

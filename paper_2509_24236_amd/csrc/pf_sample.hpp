@@ -1,0 +1,216 @@
+// Per-sample evaluation of the fitness equation (Sec. III-B) for the three storage formats and
+// the two layouts, and the deterministic workgroup reduction of (sum, count) pairs. Shared by
+// the scoring, update and gradient kernels so every path evaluates a pose identically.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <math.h>
+
+#include "pf_internal.hpp"
+
+namespace pf {
+
+// Storage element of each format and its band test (|T| < 1 in stored units: the +1 sentinel
+// of unobserved voxels, and its negative, fail it).
+template <int FMT>
+struct Fmt;
+
+template <>
+struct Fmt<PF_F32_W_F32> {
+    using T = float;
+    __device__ static inline float val(float a) { return a; }
+    __device__ static inline bool in_band(float a) { return fabsf(a) < 1.0f; }
+    static constexpr float scale = 1.0f;
+};
+
+template <>
+struct Fmt<PF_F16_W_U8> {
+    using T = __half;
+    __device__ static inline float val(__half a) { return __half2float(a); }
+    __device__ static inline bool in_band(float a) { return fabsf(a) < 1.0f; }
+    static constexpr float scale = 1.0f;
+};
+
+template <>
+struct Fmt<PF_I16_W_U8> {
+    using T = int16_t;
+    __device__ static inline float val(int16_t a) { return (float)a; }
+    __device__ static inline bool in_band(float a) { return fabsf(a) < 32767.0f; }
+    static constexpr float scale = 1.0f / 32767.0f;
+};
+
+// Gathers the 8 stencil corners of cell (cx, cy, cz) (already clamped into the grid) in the order
+// (dx, dy, dz) = 000 100 010 110 001 101 011 111.
+template <int FMT, int LAYOUT>
+struct Gather;
+
+template <int FMT>
+struct Gather<FMT, PF_LAYOUT_LINEAR> {
+    using ST = typename Fmt<FMT>::T;
+    const ST* __restrict__ T;
+    int nx, nxy;
+    __device__ inline const ST* addr(int cx, int cy, int cz) const { return T + ((cz * nxy) + cy * nx + cx); }
+    __device__ inline void load(const ST* p, float (&c)[8]) const {
+        c[0] = Fmt<FMT>::val(p[0]);
+        c[1] = Fmt<FMT>::val(p[1]);
+        c[2] = Fmt<FMT>::val(p[nx]);
+        c[3] = Fmt<FMT>::val(p[nx + 1]);
+        c[4] = Fmt<FMT>::val(p[nxy]);
+        c[5] = Fmt<FMT>::val(p[nxy + 1]);
+        c[6] = Fmt<FMT>::val(p[nxy + nx]);
+        c[7] = Fmt<FMT>::val(p[nxy + nx + 1]);
+    }
+};
+
+// Cell-major replica: the 8 corners of a cell are one aligned block (32 B in FP32, 16 B otherwise).
+template <int FMT>
+struct Gather<FMT, PF_LAYOUT_CELLS> {
+    using ST = typename Fmt<FMT>::T;
+    const ST* __restrict__ C;   // cells
+    int cnx, cnxy;              // (nx-1), (nx-1)*(ny-1)
+    __device__ inline const ST* addr(int cx, int cy, int cz) const {
+        return C + ((size_t)((cz * cnxy) + cy * cnx + cx) << 3);
+    }
+    __device__ inline void load(const ST* p, float (&c)[8]) const {
+        if constexpr (FMT == PF_F32_W_F32) {
+            const float4 a = reinterpret_cast<const float4*>(p)[0];
+            const float4 b = reinterpret_cast<const float4*>(p)[1];
+            c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
+            c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
+        } else {
+            const uint4 w = reinterpret_cast<const uint4*>(p)[0];
+            const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                ST lo, hi;
+                const uint16_t l16 = (uint16_t)(q[e] & 0xffffu), h16 = (uint16_t)(q[e] >> 16);
+                __builtin_memcpy(&lo, &l16, 2);
+                __builtin_memcpy(&hi, &h16, 2);
+                c[2 * e] = Fmt<FMT>::val(lo);
+                c[2 * e + 1] = Fmt<FMT>::val(hi);
+            }
+        }
+    }
+};
+
+// Folds a float32 row-major 3x4 pose [R | t] into grid units: g = R (x / vs) + (t / vs + g0).
+struct GridPose {
+    float r[9];
+    float t[3];
+};
+
+__device__ inline GridPose fold_pose(const float* P, float inv_vs, float gx0, float gy0, float gz0) {
+    GridPose g;
+    g.r[0] = P[0]; g.r[1] = P[1]; g.r[2] = P[2];
+    g.r[3] = P[4]; g.r[4] = P[5]; g.r[5] = P[6];
+    g.r[6] = P[8]; g.r[7] = P[9]; g.r[8] = P[10];
+    g.t[0] = fmaf(P[3], inv_vs, gx0);
+    g.t[1] = fmaf(P[7], inv_vs, gy0);
+    g.t[2] = fmaf(P[11], inv_vs, gz0);
+    return g;
+}
+
+// Evaluates one point (already divided by the voxel size) against NP poses in three phases:
+// the cell of every pose, then all gathers, then validity and interpolation, so that the gathers
+// of all poses are in flight together. Branch-free: the cell is clamped into the grid so every
+// gather is in bounds, and an out-of-grid sample is rejected afterwards. Adds |value| (in stored
+// units) and 1 to (sum[j], cnt[j]) for every valid sample.
+template <int FMT, int LAYOUT, int NP>
+__device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, unsigned ly, unsigned lz,
+                                  const GridPose (&g)[NP], float x, float y, float z, float (&sum)[NP],
+                                  int (&cnt)[NP]) {
+    using ST = typename Fmt<FMT>::T;
+    const ST* p[NP];
+    float f[NP][3];
+    bool inb[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const float gx = fmaf(g[j].r[0], x, fmaf(g[j].r[1], y, fmaf(g[j].r[2], z, g[j].t[0])));
+        const float gy = fmaf(g[j].r[3], x, fmaf(g[j].r[4], y, fmaf(g[j].r[5], z, g[j].t[1])));
+        const float gz = fmaf(g[j].r[6], x, fmaf(g[j].r[7], y, fmaf(g[j].r[8], z, g[j].t[2])));
+        const float fx0 = floorf(gx), fy0 = floorf(gy), fz0 = floorf(gz);
+        const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
+        inb[j] = ((unsigned)ix < lx) & ((unsigned)iy < ly) & ((unsigned)iz < lz);
+        const int cx = min(max(ix, 0), (int)lx - 1);
+        const int cy = min(max(iy, 0), (int)ly - 1);
+        const int cz = min(max(iz, 0), (int)lz - 1);
+        f[j][0] = gx - fx0;
+        f[j][1] = gy - fy0;
+        f[j][2] = gz - fz0;
+        p[j] = G.addr(cx, cy, cz);
+    }
+    // keep the phases apart: the scheduler would otherwise interleave them pose by pose and
+    // leave only one pose's gathers in flight
+    __builtin_amdgcn_sched_barrier(0);
+    float c[NP][8];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) G.load(p[j], c[j]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        bool ok = inb[j];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ok &= Fmt<FMT>::in_band(c[j][q]);
+        const float a00 = fmaf(f[j][0], c[j][1] - c[j][0], c[j][0]);
+        const float a10 = fmaf(f[j][0], c[j][3] - c[j][2], c[j][2]);
+        const float a01 = fmaf(f[j][0], c[j][5] - c[j][4], c[j][4]);
+        const float a11 = fmaf(f[j][0], c[j][7] - c[j][6], c[j][6]);
+        const float b0 = fmaf(f[j][1], a10 - a00, a00);
+        const float b1 = fmaf(f[j][1], a11 - a01, a01);
+        const float v = fmaf(f[j][2], b1 - b0, b0);
+        sum[j] += ok ? fabsf(v) : 0.0f;
+        cnt[j] += ok ? 1 : 0;
+    }
+}
+
+// Deterministic workgroup reduction of TK (sum, count) pairs; thread j < TK returns pair j in
+// s[0], c[0]. Order: per-lane sums, a fixed butterfly across the wave, then waves in order.
+template <int TK, int BLOCK>
+__device__ inline void block_reduce(float (&s)[TK], int (&c)[TK]) {
+    __shared__ float ls[TK][BLOCK / kWave];
+    __shared__ int lc[TK][BLOCK / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < TK; ++j) {
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            s[j] += __shfl_xor(s[j], off);
+            c[j] += __shfl_xor(c[j], off);
+        }
+        if (lane == 0) {
+            ls[j][wid] = s[j];
+            lc[j][wid] = c[j];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < TK) {
+        const int j = threadIdx.x;
+        float a = 0.0f;
+        int b = 0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / kWave; ++w) {
+            a += ls[j][w];
+            b += lc[j][w];
+        }
+        s[0] = a;
+        c[0] = b;
+    }
+}
+
+// Volume accessor for a launch: the layout-specific gather and the cell limits.
+template <int FMT, int LAYOUT>
+__host__ __device__ inline Gather<FMT, LAYOUT> make_gather(const VolView& vv) {
+    Gather<FMT, LAYOUT> G;
+    if constexpr (LAYOUT == PF_LAYOUT_LINEAR) {
+        G.T = static_cast<const typename Fmt<FMT>::T*>(vv.T);
+        G.nx = vv.nx;
+        G.nxy = vv.nx * vv.ny;
+    } else {
+        G.C = static_cast<const typename Fmt<FMT>::T*>(vv.cells);
+        G.cnx = vv.nx - 1;
+        G.cnxy = (vv.nx - 1) * (vv.ny - 1);
+    }
+    return G;
+}
+
+}  // namespace pf

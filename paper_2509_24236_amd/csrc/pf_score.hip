@@ -1,0 +1,94 @@
+// Particle scoring for gfx950: the fitness equation of Sec. III-B evaluated for many poses.
+//
+// E_k = (1/|X_k|) sum_{x in X_k} |T(R_k x + t_k)|, T the trilinear interpolation of the 8 voxel
+// centres around the point, x in X_k iff the stencil is inside the grid and all 8 stored values
+// have |T| < 1 ("valid grids": observed and within the truncation band), E_k = 1 if X_k = {}.
+//
+// Work decomposition: a workgroup owns TK consecutive poses and sweeps every point; each lane
+// keeps one point's camera coordinates in registers and evaluates it against the TK poses, so
+// the point load is amortised over TK gathers and the poses are uniform across the wave
+// (scalar registers). All lanes of a wave touch 64 consecutive points of the raster-ordered
+// cloud, so their 8-corner stencils fall in nearby voxels. A workgroup covers all points of its
+// poses, so the (sum, count) of each pose is reduced once, inside the workgroup, in a fixed
+// order: results are bitwise reproducible and no cross-workgroup pass is needed.
+//
+// The point set is HBM/L2-bound gather work (8 x 4 B per sample for FP32 storage), not a
+// contraction, so it runs on the vector ALUs, not on the matrix cores.
+#include <math.h>
+
+#include "pf_sample.hpp"
+
+namespace pf {
+namespace {
+
+template <int FMT, int LAYOUT, int TK, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_score(VolView vv, const float* __restrict__ px, const float* __restrict__ py,
+                                                 const float* __restrict__ pz, int n_host, const int* __restrict__ n_dev,
+                                                 const float* __restrict__ poses, int K, float* __restrict__ fitness,
+                                                 int* __restrict__ n_valid) {
+    const Gather<FMT, LAYOUT> G = make_gather<FMT, LAYOUT>(vv);
+    const int k0 = blockIdx.x * TK;
+    // poses in grid units, uniform across the workgroup (scalar registers)
+    GridPose g[TK];
+#pragma unroll
+    for (int j = 0; j < TK; ++j)
+        g[j] = fold_pose(poses + (size_t)min(k0 + j, K - 1) * 12, vv.inv_vs, vv.gx0, vv.gy0, vv.gz0);
+    const int n = n_dev ? *n_dev : n_host;
+    const unsigned lx = (unsigned)(vv.nx - 1), ly = (unsigned)(vv.ny - 1), lz = (unsigned)(vv.nz - 1);
+    float sum[TK];
+    int cnt[TK];
+#pragma unroll
+    for (int j = 0; j < TK; ++j) {
+        sum[j] = 0.0f;
+        cnt[j] = 0;
+    }
+    const float s = vv.inv_vs;
+    for (int q = threadIdx.x; q < n; q += BLOCK)
+        eval_poses<FMT, LAYOUT, TK>(G, lx, ly, lz, g, px[q] * s, py[q] * s, pz[q] * s, sum, cnt);
+    block_reduce<TK, BLOCK>(sum, cnt);
+    if (threadIdx.x < TK) {
+        const int k = k0 + threadIdx.x;
+        if (k < K) {
+            fitness[k] = cnt[0] > 0 ? (sum[0] * Fmt<FMT>::scale) / (float)cnt[0] : 1.0f;
+            n_valid[k] = cnt[0];
+        }
+    }
+}
+
+template <int FMT, int LAYOUT, int TK, int BLOCK>
+int32_t launch_t(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
+                 hipStream_t s) {
+    const int blocks = (K + TK - 1) / TK;
+    hipLaunchKernelGGL((k_score<FMT, LAYOUT, TK, BLOCK>), dim3(blocks), dim3(BLOCK), 0, s, vv, p.x, p.y, p.z, p.n,
+                       p.n_dev, poses, K, fitness, n_valid);
+    return check_launch("particles_score");
+}
+
+template <int FMT, int LAYOUT>
+int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
+                  hipStream_t s) {
+    // few poses: spread the points over a wide workgroup; many poses: 4 poses per workgroup
+    if (K <= 64) return launch_t<FMT, LAYOUT, 1, 1024>(vv, p, poses, K, fitness, n_valid, s);
+    return launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, s);
+}
+
+template <int FMT>
+int32_t launch_fmt(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
+                   hipStream_t s) {
+    if (vv.layout == PF_LAYOUT_CELLS) return launch_fl<FMT, PF_LAYOUT_CELLS>(vv, p, poses, K, fitness, n_valid, s);
+    return launch_fl<FMT, PF_LAYOUT_LINEAR>(vv, p, poses, K, fitness, n_valid, s);
+}
+
+}  // namespace
+
+int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
+                     hipStream_t s) {
+    switch (vv.format) {
+        case PF_F32_W_F32: return launch_fmt<PF_F32_W_F32>(vv, p, poses, K, fitness, n_valid, s);
+        case PF_F16_W_U8: return launch_fmt<PF_F16_W_U8>(vv, p, poses, K, fitness, n_valid, s);
+        case PF_I16_W_U8: return launch_fmt<PF_I16_W_U8>(vv, p, poses, K, fitness, n_valid, s);
+        default: return set_error(PF_EUNSUPPORTED, "particles_score: unsupported format %d", vv.format);
+    }
+}
+
+}  // namespace pf

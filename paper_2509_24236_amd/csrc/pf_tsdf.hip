@@ -1,0 +1,313 @@
+// TSDF volume kernels for gfx950: initialisation, KinectFusion-style fusion of one depth frame
+// (Sec. III "Method overview"; Fig. 2), conversion to / from a linear FP32 form, and upkeep of the
+// cell-major replica that particle scoring reads (PF_LAYOUT_CELLS).
+//
+// Layout: x-fastest dense grid, T[(k*ny + j)*nx + i]. One thread owns one voxel, so the
+// read-modify-write of fusion needs no atomics. Consecutive threads own consecutive x, so the
+// T/W traffic of updated voxels is coalesced; voxels that are not updated are never read,
+// because the decision depends only on the voxel index, the pose and the depth image. A voxel is
+// corner (dx, dy, dz) of the cells (i-dx, j-dy, k-dz); its replica entries are rewritten only
+// when its stored value changes, which outside the truncation band (free space stays at +1) is
+// rare, so the replica costs little fusion traffic.
+#include <math.h>
+
+#include "pf_sample.hpp"
+
+namespace pf {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <int FMT>
+struct Store;
+
+template <>
+struct Store<PF_F32_W_F32> {
+    using T = float;
+    using W = float;
+    __device__ static inline T enc(float v) { return v; }
+    __device__ static inline float dec(T v) { return v; }
+    __device__ static inline W encw(float w) { return w; }
+    __device__ static inline float decw(W w) { return w; }
+    __device__ static inline bool same(T a, T b) { return __float_as_uint(a) == __float_as_uint(b); }
+};
+
+template <>
+struct Store<PF_F16_W_U8> {
+    using T = __half;
+    using W = uint8_t;
+    __device__ static inline T enc(float v) { return __float2half_rn(v); }
+    __device__ static inline float dec(T v) { return __half2float(v); }
+    __device__ static inline W encw(float w) { return (uint8_t)fminf(255.0f, fmaxf(0.0f, rintf(w))); }
+    __device__ static inline float decw(W w) { return (float)w; }
+    __device__ static inline bool same(T a, T b) { return __half_as_ushort(a) == __half_as_ushort(b); }
+};
+
+template <>
+struct Store<PF_I16_W_U8> {
+    using T = int16_t;
+    using W = uint8_t;
+    // RNE(T * 32767) clamped to +-32767; +-32767 are the out-of-band values
+    __device__ static inline T enc(float v) { return (int16_t)fminf(32767.0f, fmaxf(-32767.0f, rintf(v * 32767.0f))); }
+    __device__ static inline float dec(T v) { return (float)v * (1.0f / 32767.0f); }
+    __device__ static inline W encw(float w) { return (uint8_t)fminf(255.0f, fmaxf(0.0f, rintf(w))); }
+    __device__ static inline float decw(W w) { return (float)w; }
+    __device__ static inline bool same(T a, T b) { return a == b; }
+};
+
+struct Dims {
+    int nx, ny, nz;
+    int64_t n;        // voxels
+    int64_t ncells;   // (nx-1)(ny-1)(nz-1)
+};
+
+Dims dims_of(const pf_tsdf* v) {
+    Dims d;
+    d.nx = v->nx;
+    d.ny = v->ny;
+    d.nz = v->nz;
+    d.n = (int64_t)v->nx * v->ny * v->nz;
+    d.ncells = (int64_t)(v->nx - 1) * (v->ny - 1) * (v->nz - 1);
+    return d;
+}
+
+// Writes voxel (i, j, k)'s stored value into every cell that has it as a corner.
+template <typename T>
+__device__ inline void write_corners(T* cells, const Dims& d, int i, int j, int k, T val) {
+    const int cnx = d.nx - 1, cny = d.ny - 1, cnz = d.nz - 1;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int ci = i - dx, cj = j - dy, ck = k - dz;
+                if (ci < 0 || cj < 0 || ck < 0 || ci >= cnx || cj >= cny || ck >= cnz) continue;
+                const int64_t c = ((int64_t)ck * cny + cj) * cnx + ci;
+                cells[(c << 3) + (dx + 2 * dy + 4 * dz)] = val;
+            }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_init(void* Tv, void* Wv, void* Cv, Dims d) {
+    using S = Store<FMT>;
+    auto* T = static_cast<typename S::T*>(Tv);
+    auto* W = static_cast<typename S::W*>(Wv);
+    auto* C = static_cast<typename S::T*>(Cv);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const typename S::T one = S::enc(1.0f);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < d.n; i += stride) {
+        T[i] = one;
+        W[i] = S::encw(0.0f);
+    }
+    if (C)
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (d.ncells << 3); i += stride) C[i] = one;
+}
+
+struct FuseArgs {
+    void* T;
+    void* W;
+    void* C;
+    Dims d;
+    double vs, tau, ox, oy, oz;
+    double R[9], t[3];
+    double fx, fy, cx, cy;
+    int width, height;
+    float w_max;
+    const float* depth;
+};
+
+// The projection is evaluated in FP64 with the same operation order as the plain definition
+// and with contraction disabled, so the per-voxel decisions (updated or not, which pixel)
+// are those of an FP64 evaluation of the formula as written; the running average is FP32.
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
+#pragma clang fp contract(off)
+    using S = Store<FMT>;
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t nxy = (int64_t)a.d.nx * a.d.ny;
+    if (idx >= a.d.n) return;
+    const int k = (int)(idx / nxy);
+    const int64_t rem = idx - (int64_t)k * nxy;
+    const int j = (int)(rem / a.d.nx);
+    const int i = (int)(rem - (int64_t)j * a.d.nx);
+    const double px = a.ox + a.vs * (double)i;
+    const double py = a.oy + a.vs * (double)j;
+    const double pz = a.oz + a.vs * (double)k;
+    const double dx = px - a.t[0], dy = py - a.t[1], dz = pz - a.t[2];
+    const double qz = a.R[2] * dx + a.R[5] * dy + a.R[8] * dz;
+    if (!(qz > 0.0)) return;
+    const double qx = a.R[0] * dx + a.R[3] * dy + a.R[6] * dz;
+    const double qy = a.R[1] * dx + a.R[4] * dy + a.R[7] * dz;
+    const double u = a.fx * qx / qz + a.cx;
+    const double v = a.fy * qy / qz + a.cy;
+    const double uf = floor(u + 0.5), vf = floor(v + 0.5);
+    if (uf < 0.0 || uf >= (double)a.width || vf < 0.0 || vf >= (double)a.height) return;
+    const int ui = (int)uf, vi = (int)vf;
+    const double D = (double)a.depth[(int64_t)vi * a.width + ui];
+    if (!(isfinite(D) && D > 0.0)) return;
+    const double eta = D - qz;
+    if (eta < -a.tau) return;
+    double phi = eta / a.tau;
+    if (phi > 1.0) phi = 1.0;
+    auto* T = static_cast<typename S::T*>(a.T);
+    auto* W = static_cast<typename S::W*>(a.W);
+    const typename S::T told = T[idx];
+    const float w = S::decw(W[idx]);
+    const float tn = (S::dec(told) * w + (float)phi) / (w + 1.0f);
+    const typename S::T tnew = S::enc(tn);
+    T[idx] = tnew;
+    W[idx] = S::encw(fminf(w + 1.0f, a.w_max));
+    if (a.C && !S::same(told, tnew)) write_corners(static_cast<typename S::T*>(a.C), a.d, i, j, k, tnew);
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_export(const void* Tv, const void* Wv, Dims d, float* To, float* Wo) {
+    using S = Store<FMT>;
+    const auto* T = static_cast<const typename S::T*>(Tv);
+    const auto* W = static_cast<const typename S::W*>(Wv);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < d.n; i += stride) {
+        To[i] = S::dec(T[i]);
+        if (Wo) Wo[i] = S::decw(W[i]);
+    }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_import(void* Tv, void* Wv, Dims d, const float* Ti, const float* Wi) {
+    using S = Store<FMT>;
+    auto* T = static_cast<typename S::T*>(Tv);
+    auto* W = static_cast<typename S::W*>(Wv);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < d.n; i += stride) {
+        T[i] = S::enc(Ti[i]);
+        W[i] = S::encw(Wi ? Wi[i] : 0.0f);
+    }
+}
+
+// Rebuilds the whole cell replica from the x-fastest storage.
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_build_cells(const void* Tv, void* Cv, Dims d) {
+    using S = Store<FMT>;
+    const auto* T = static_cast<const typename S::T*>(Tv);
+    auto* C = static_cast<typename S::T*>(Cv);
+    const int cnx = d.nx - 1, cny = d.ny - 1;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < d.ncells; c += stride) {
+        const int ck = (int)(c / ((int64_t)cnx * cny));
+        const int64_t rem = c - (int64_t)ck * cnx * cny;
+        const int cj = (int)(rem / cnx), ci = (int)(rem - (int64_t)cj * cnx);
+        const int64_t b = ((int64_t)ck * d.ny + cj) * d.nx + ci;
+        const int64_t nxy = (int64_t)d.nx * d.ny;
+        typename S::T* o = C + (c << 3);
+        o[0] = T[b];
+        o[1] = T[b + 1];
+        o[2] = T[b + d.nx];
+        o[3] = T[b + d.nx + 1];
+        o[4] = T[b + nxy];
+        o[5] = T[b + nxy + 1];
+        o[6] = T[b + nxy + d.nx];
+        o[7] = T[b + nxy + d.nx + 1];
+    }
+}
+
+int grid_for(int64_t n) {
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    return (int)(b < 65536 ? b : 65536);
+}
+
+void* cells_ptr(const pf_tsdf* v) {
+    return v->layout == PF_LAYOUT_CELLS ? static_cast<char*>(v->tsdf) + cells_offset_bytes(v) : nullptr;
+}
+
+template <int FMT>
+int32_t init_t(const pf_tsdf* v, hipStream_t s) {
+    const Dims d = dims_of(v);
+    hipLaunchKernelGGL(k_init<FMT>, dim3(grid_for(d.n * 8)), dim3(kBlock), 0, s, v->tsdf, v->weight, cells_ptr(v), d);
+    return check_launch("tsdf_init");
+}
+
+template <int FMT>
+int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* P, hipStream_t s) {
+    FuseArgs a;
+    a.T = v->tsdf;
+    a.W = v->weight;
+    a.C = cells_ptr(v);
+    a.d = dims_of(v);
+    a.vs = v->voxel_size;
+    a.tau = v->trunc;
+    a.ox = v->origin[0];
+    a.oy = v->origin[1];
+    a.oz = v->origin[2];
+    for (int q = 0; q < 9; ++q) a.R[q] = P->R[q];
+    for (int q = 0; q < 3; ++q) a.t[q] = P->t[q];
+    a.fx = K->fx;
+    a.fy = K->fy;
+    a.cx = K->cx;
+    a.cy = K->cy;
+    a.width = K->width;
+    a.height = K->height;
+    a.w_max = (float)v->w_max;
+    a.depth = depth;
+    const int64_t blocks = (a.d.n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_integrate<FMT>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    return check_launch("tsdf_integrate");
+}
+
+template <int FMT>
+int32_t export_t(const pf_tsdf* v, float* T, float* W, hipStream_t s) {
+    const Dims d = dims_of(v);
+    hipLaunchKernelGGL(k_export<FMT>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, v->tsdf, v->weight, d, T, W);
+    return check_launch("tsdf_export_linear");
+}
+
+template <int FMT>
+int32_t import_t(const pf_tsdf* v, const float* T, const float* W, hipStream_t s) {
+    const Dims d = dims_of(v);
+    hipLaunchKernelGGL(k_import<FMT>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, v->tsdf, v->weight, d, T, W);
+    int32_t rc = check_launch("tsdf_import_linear");
+    if (rc || v->layout != PF_LAYOUT_CELLS) return rc;
+    hipLaunchKernelGGL(k_build_cells<FMT>, dim3(grid_for(d.ncells)), dim3(kBlock), 0, s, v->tsdf, cells_ptr(v), d);
+    return check_launch("tsdf_import_linear (cells)");
+}
+
+}  // namespace
+
+int32_t launch_tsdf_init(const pf_tsdf* v, hipStream_t s) {
+    switch (v->format) {
+        case PF_F32_W_F32: return init_t<PF_F32_W_F32>(v, s);
+        case PF_F16_W_U8: return init_t<PF_F16_W_U8>(v, s);
+        case PF_I16_W_U8: return init_t<PF_I16_W_U8>(v, s);
+        default: return set_error(PF_EUNSUPPORTED, "unsupported format %d", v->format);
+    }
+}
+
+int32_t launch_tsdf_integrate(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* P,
+                              hipStream_t s) {
+    switch (v->format) {
+        case PF_F32_W_F32: return integrate_t<PF_F32_W_F32>(v, depth, K, P, s);
+        case PF_F16_W_U8: return integrate_t<PF_F16_W_U8>(v, depth, K, P, s);
+        case PF_I16_W_U8: return integrate_t<PF_I16_W_U8>(v, depth, K, P, s);
+        default: return set_error(PF_EUNSUPPORTED, "unsupported format %d", v->format);
+    }
+}
+
+int32_t launch_tsdf_export(const pf_tsdf* v, float* T, float* W, hipStream_t s) {
+    switch (v->format) {
+        case PF_F32_W_F32: return export_t<PF_F32_W_F32>(v, T, W, s);
+        case PF_F16_W_U8: return export_t<PF_F16_W_U8>(v, T, W, s);
+        case PF_I16_W_U8: return export_t<PF_I16_W_U8>(v, T, W, s);
+        default: return set_error(PF_EUNSUPPORTED, "unsupported format %d", v->format);
+    }
+}
+
+int32_t launch_tsdf_import(const pf_tsdf* v, const float* T, const float* W, hipStream_t s) {
+    switch (v->format) {
+        case PF_F32_W_F32: return import_t<PF_F32_W_F32>(v, T, W, s);
+        case PF_F16_W_U8: return import_t<PF_F16_W_U8>(v, T, W, s);
+        case PF_I16_W_U8: return import_t<PF_I16_W_U8>(v, T, W, s);
+        default: return set_error(PF_EUNSUPPORTED, "unsupported format %d", v->format);
+    }
+}
+
+}  // namespace pf

@@ -1,0 +1,168 @@
+"""C-ABI contract checks that need no GPU: the library loads and exports every function the
+header declares, the ctypes mirrors match the C struct layouts, and invalid arguments are
+rejected with PF_EINVAL (and a message) before anything touches a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "profusion.h")
+
+
+@pytest.fixture(scope="module")
+def pf():
+    import paper_2509_24236_amd as pf
+    if not os.path.exists(pf.LIB_PATH):
+        from paper_2509_24236_amd import build
+        build.build()
+    pf.lib()
+    return pf
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w]*\s*\*?\s*([A-Za-z_]\w*)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_exports_every_declared_function(pf):
+    names = declared_functions()
+    assert len(names) >= 13
+    L = C.CDLL(pf.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in profusion.h but not exported"
+    assert set(names) == set(pf.EXPORTS)
+
+
+def test_struct_layouts_match_header(pf):
+    structs = {
+        "pf_pose": pf.pf_pose, "pf_intrinsics": pf.pf_intrinsics, "pf_tsdf": pf.pf_tsdf,
+        "pf_track_params": pf.pf_track_params, "pf_track_stats": pf.pf_track_stats,
+        "pf_track_state": pf.pf_track_state,
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append('printf("PF_STATE_DELTAS_OFFSET %d\\n", PF_STATE_DELTAS_OFFSET);')
+    lines.append("return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        open(c, "w").write("\n".join(lines))
+        exe = os.path.join(d, "layout")
+        subprocess.check_call(["gcc", "-std=c11", "-o", exe, c])
+        out = subprocess.check_output([exe], text=True)
+    got = dict(l.rsplit(" ", 1) for l in out.strip().splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == C.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, f"{name}.{fname}"
+    assert int(got["PF_STATE_DELTAS_OFFSET"]) == pf.STATE_DELTAS_OFFSET
+    assert C.sizeof(pf.pf_track_state) <= pf.STATE_DELTAS_OFFSET
+
+
+def _desc(pf, nx=8, ny=8, nz=8, fmt=0, layout=0):
+    d = pf.pf_tsdf()
+    d.nx, d.ny, d.nz, d.format, d.layout = nx, ny, nz, fmt, layout
+    d.voxel_size, d.trunc = 0.01, 0.04
+    d.origin[:] = [0.0, 0.0, 0.0]
+    d.w_max = 255
+    d.tsdf = 0x1000      # never dereferenced: every call below fails validation first
+    d.weight = 0x2000
+    return d
+
+
+def test_tsdf_bytes(pf):
+    L = pf.lib()
+    wb = C.c_size_t()
+    for fmt, (tb, wbb) in {0: (4, 4), 1: (2, 1), 2: (2, 1)}.items():
+        d = _desc(pf, 16, 8, 4, fmt)
+        assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == 16 * 8 * 4 * tb
+        assert wb.value == 16 * 8 * 4 * wbb
+    for fmt, tb in {0: 4, 1: 2, 2: 2}.items():
+        d = _desc(pf, 16, 8, 4, fmt, layout=1)
+        off = L.tsdf_cells_offset(C.byref(d))
+        assert off >= 16 * 8 * 4 * tb and off % 256 == 0
+        assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == off + 15 * 7 * 3 * 8 * tb
+    assert L.tsdf_cells_offset(C.byref(_desc(pf, 16, 8, 4, 0, layout=0))) == 0
+    assert L.tsdf_bytes(C.byref(_desc(pf, layout=2)), C.byref(wb)) == 0
+    assert L.tsdf_bytes(C.byref(_desc(pf, 1, 8, 8)), C.byref(wb)) == 0
+    assert L.tsdf_bytes(C.byref(_desc(pf, fmt=7)), C.byref(wb)) == 0
+    assert L.tsdf_bytes(None, None) == 0
+    assert L.tsdf_bytes(C.byref(_desc(pf, 2048, 2048, 1024)), None) == 0   # > 2^31 voxels
+
+
+def _rc(pf, rc, needle):
+    assert rc == pf.PF_EINVAL
+    assert needle in pf.last_error(), pf.last_error()
+
+
+def test_validation_rejects_before_launch(pf):
+    L = pf.lib()
+    _rc(pf, L.tsdf_init(None, None), "null volume")
+    _rc(pf, L.tsdf_init(C.byref(_desc(pf, 1, 4, 4)), None), "dims")
+    d = _desc(pf)
+    d.voxel_size = 0.0
+    _rc(pf, L.tsdf_init(C.byref(d), None), "voxel_size")
+    d = _desc(pf)
+    d.trunc = float("nan")
+    _rc(pf, L.tsdf_init(C.byref(d), None), "trunc")
+    d = _desc(pf)
+    d.w_max = 0
+    _rc(pf, L.tsdf_init(C.byref(d), None), "w_max")
+    d = _desc(pf)
+    d.layout = 5
+    _rc(pf, L.tsdf_init(C.byref(d), None), "layout")
+    d = _desc(pf)
+    d.tsdf = None
+    _rc(pf, L.tsdf_init(C.byref(d), None), "null tsdf")
+    K = pf.pf_intrinsics(525.0, 525.0, 319.5, 239.5, 640, 480)
+    bad_R = pf.make_pose(np.diag([1.0, 1.0, 1.001]), np.zeros(3))
+    _rc(pf, L.tsdf_integrate(C.byref(_desc(pf)), C.c_void_p(0x3000), C.byref(K), C.byref(bad_R), None), "rotation")
+    refl = pf.make_pose(np.diag([1.0, 1.0, -1.0]), np.zeros(3))
+    _rc(pf, L.tsdf_integrate(C.byref(_desc(pf)), C.c_void_p(0x3000), C.byref(K), C.byref(refl), None), "rotation")
+    K0 = pf.pf_intrinsics(0.0, 525.0, 319.5, 239.5, 640, 480)
+    good = pf.make_pose(np.eye(3), np.zeros(3))
+    _rc(pf, L.tsdf_integrate(C.byref(_desc(pf)), C.c_void_p(0x3000), C.byref(K0), C.byref(good), None), "focal")
+    _rc(pf, L.tsdf_integrate(C.byref(_desc(pf)), None, C.byref(K), C.byref(good), None), "null depth")
+    p = C.c_void_p(0x4000)
+    _rc(pf, L.particles_score(C.byref(_desc(pf)), p, p, p, 0, p, 4, p, p, None), "n_pts")
+    _rc(pf, L.particles_score(C.byref(_desc(pf)), p, p, p, 10, p, 0, p, p, None), "K")
+    _rc(pf, L.particles_score(C.byref(_desc(pf)), p, None, p, 10, p, 4, p, p, None), "null pointer")
+    _rc(pf, L.particles_update(C.byref(_desc(pf)), p, p, p, 10, p, p, p, 0, p, None), "K")
+
+
+def test_params_validation(pf):
+    L = pf.lib()
+    intr = pf.pf_intrinsics(120.0, 120.0, 80.0, 60.0, 160, 120)
+    good = pf.TrackParams(K=256, n_iters=10, rates=(1,), pixel_stride=2)
+    assert L.track_workspace_bytes(C.byref(intr), C.byref(good.c())) > 0
+    for field, val in [("K", 0), ("n_iters", 0), ("n_iters", 65), ("beta", 1.5), ("compose_mode", 2),
+                       ("pixel_stride", 0), ("s1_deg", -1.0), ("frame_index", -1), ("polish_steps", 99)]:
+        c = good.c()
+        setattr(c, field, val)
+        assert L.track_workspace_bytes(C.byref(intr), C.byref(c)) == 0, field
+    c = good.c()
+    c.n_rates = 0
+    assert L.track_workspace_bytes(C.byref(intr), C.byref(c)) == 0
+    c = good.c()
+    c.rates[0] = 0
+    assert L.track_workspace_bytes(C.byref(intr), C.byref(c)) == 0
+    init = pf.make_pose(np.eye(3), np.zeros(3))
+    out = pf.pf_pose()
+    p = C.c_void_p(0x4000)
+    c = good.c()
+    c.K = -3
+    rc = L.track_frame(C.byref(_desc(pf)), p, C.byref(intr), C.byref(init), C.byref(c), C.byref(out), None, p,
+                       C.c_size_t(1 << 20), None)
+    _rc(pf, rc, "K")
+    assert L.particles_state_bytes(0) == 0
+    # header, then the FP64 deltas at 512, then 256-byte aligned per-workgroup partials
+    assert L.particles_state_bytes(10) == 512 + 768 + 256 * 8

@@ -1,0 +1,323 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on identical seeded inputs.
+
+Bars: bit-exact for integer/index work (compaction order and counts, fusion weights, RNG
+deltas, advantage-set size); FP32 fitness inside the oracle's near-face interval widened by
+1e-4 relative; fused T within FP32 rounding of the FP64 value; tracked poses within 1 mm and
+0.05 degrees of the oracle's with the same random stream."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pf():
+    import paper_2509_24236_amd as pf
+    pf.lib()
+    assert torch.cuda.is_available()
+    return pf
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return synth.cfg1_inputs()
+
+
+@pytest.fixture(scope="module")
+def cfg1_vol(orc, cfg1):
+    """Oracle TSDF after fusing frame 1, and its float32 rounding (the shared scoring input)."""
+    v = orc.Volume(cfg1["vol"])
+    v.integrate(cfg1["depth1"], cfg1["intr"], np.eye(3), np.zeros(3))
+    T32 = v.T.astype(np.float32)
+    v32 = orc.Volume(cfg1["vol"], T=T32.astype(np.float64), W=v.W)
+    return v, v32, T32
+
+
+def upload(pf, spec, T32, W, dev, fmt=0, layout=1):
+    vol = pf.Tsdf(spec, fmt=fmt, device=dev, init=False, layout=layout)
+    vol.import_linear(T32, W.astype(np.float32))
+    return vol
+
+
+def check_fitness(E_gpu, nv_gpu, lo, hi, rel=1e-4):
+    E_gpu = np.asarray(E_gpu, np.float64)
+    lo_w = lo - rel * np.abs(lo) - 1e-7
+    hi_w = hi + rel * np.abs(hi) + 1e-7
+    bad = np.flatnonzero((E_gpu < lo_w) | (E_gpu > hi_w))
+    assert bad.size == 0, f"{bad.size} poses outside the oracle interval, e.g. k={bad[:5]}: " \
+                          f"gpu {E_gpu[bad[:5]]} lo {lo[bad[:5]]} hi {hi[bad[:5]]}"
+
+
+# ----------------------------------------------------------------------------- back-projection
+@pytest.mark.parametrize("case", ["cfg1_stride2", "ragged_invalid", "cfg2_full"])
+def test_backproject_parity(pf, orc, dev, cfg1, case):
+    say(f"[backproject] {case}")
+    if case == "cfg1_stride2":
+        depth, intr, stride = cfg1["depth2"], cfg1["intr"], 2
+    elif case == "ragged_invalid":
+        rng = np.random.default_rng(7)
+        intr = synth.Intrinsics(30.0, 31.0, 18.3, 11.7, 37, 23)
+        depth = rng.uniform(0.2, 4.0, (23, 37)).astype(np.float32)
+        depth[rng.random(depth.shape) < 0.2] = 0.0
+        depth[1, 2], depth[3, 4], depth[5, 6], depth[7, 8] = np.nan, -1.0, np.inf, -np.inf
+        stride = 3
+    else:
+        f = synth.cfg2_frames(2)
+        depth, intr, stride = f["depth"](1), f["intr"], 1
+    xyz, pix = orc.backproject(depth, intr, stride)
+    px, py, pz, n = pf.backproject(torch.as_tensor(depth).to(dev), intr, stride)
+    n = int(n[0].item())
+    assert n == xyz.shape[0]
+    g = np.stack([px[:n].cpu().numpy(), py[:n].cpu().numpy(), pz[:n].cpu().numpy()], 1).astype(np.float64)
+    assert np.array_equal(g[:, 2], xyz[:, 2])                 # z is the depth value itself: order and bits
+    # float32 x = ((u - cx) z) / fx: the rounding of cx itself bounds the error by |cx| z / fx
+    # times 2^-24, plus a few roundings of |x|
+    z = xyz[:, 2]
+    bx = 1.2e-7 * (abs(intr.cx) * z / intr.fx + 5 * np.abs(xyz[:, 0])) + 1e-12
+    by = 1.2e-7 * (abs(intr.cy) * z / intr.fy + 5 * np.abs(xyz[:, 1])) + 1e-12
+    assert np.all(np.abs(g[:, 0] - xyz[:, 0]) <= bx) and np.all(np.abs(g[:, 1] - xyz[:, 1]) <= by)
+
+
+# ----------------------------------------------------------------------------- fusion
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+def test_integrate_parity_cfg1(pf, orc, dev, cfg1, fmt):
+    say(f"[integrate] cfg1 two frames, format {fmt}")
+    spec, intr = cfg1["vol"], cfg1["intr"]
+    ov = orc.Volume(spec)
+    gv = pf.Tsdf(spec, fmt=fmt, device=dev, layout=pf.LAYOUT_CELLS)
+    frames = [(cfg1["depth1"], cfg1["gt1"]), (cfg1["depth2"], cfg1["gt2"])]
+    for depth, (R, t) in frames:
+        ov.integrate(depth, intr, R, t)
+        gv.integrate(torch.as_tensor(depth).to(dev), intr, R, t)
+        T, W = gv.export_linear()
+        T, W = T.cpu().numpy().astype(np.float64), W.cpu().numpy()
+        assert np.array_equal(W, ov.W.astype(np.float32)), "weights must match exactly"
+        upd = ov.W > 0
+        err = np.abs(T - ov.T)
+        tol = {0: 2e-6, 1: 1.5e-3, 2: 1e-4}[fmt]
+        assert err[upd].max() <= tol, (fmt, err[upd].max())
+        assert np.all(T[~upd] == 1.0)
+    assert (ov.W == 2).sum() > 100000
+
+
+def test_integrate_parity_ragged_and_behind(pf, orc, dev):
+    say("[integrate] ragged volume, camera inside, rotated pose")
+    spec = synth.VolumeSpec(37, 29, 23, 0.05, 0.12, (-0.9, -0.7, -0.5))
+    rng = np.random.default_rng(11)
+    intr = synth.Intrinsics(40.0, 41.0, 20.5, 15.5, 41, 31)
+    depth = rng.uniform(0.3, 1.5, (31, 41)).astype(np.float32)
+    depth[rng.random(depth.shape) < 0.1] = 0.0
+    from scipy.spatial.transform import Rotation
+    R = Rotation.from_rotvec([0.3, -0.2, 0.1]).as_matrix()
+    t = np.array([0.05, -0.02, 0.1])
+    ov = orc.Volume(spec)
+    ov.integrate(depth, intr, R, t)
+    gv = pf.Tsdf(spec, device=dev)
+    gv.integrate(torch.as_tensor(depth).to(dev), intr, R, t)
+    T, W = gv.export_linear()
+    assert np.array_equal(W.cpu().numpy(), ov.W.astype(np.float32))
+    assert np.abs(T.cpu().numpy() - ov.T).max() <= 2e-6
+
+
+# ----------------------------------------------------------------------------- scoring
+def _poses_around(orc, R, t, n, rot, trans, seed):
+    rng = np.random.default_rng(seed)
+    out = [(R, t)]
+    for _ in range(n - 1):
+        out.append(orc.compose(rng.uniform(-rot, rot, 3), rng.uniform(-trans, trans, 3), R, t))
+    return out
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("K", [1, 5, 64, 65, 257])
+def test_score_parity_cfg1(pf, orc, dev, cfg1, cfg1_vol, K, layout):
+    say(f"[score] cfg1 K={K} layout={layout}")
+    v, v32, T32 = cfg1_vol
+    xyz, _ = orc.backproject(cfg1["depth2"], cfg1["intr"], 2)
+    x32 = xyz.astype(np.float32)
+    R, t = cfg1["init2"]
+    poses = _poses_around(orc, R, t, K, math.radians(5), 0.03, K)
+    P32 = pf.poses_to_f32(poses)
+    poses64 = [(P32[k].reshape(3, 4)[:, :3].astype(np.float64), P32[k].reshape(3, 4)[:, 3].astype(np.float64))
+               for k in range(K)]
+    lo, hi, na = v32.fitness_interval_many(x32.astype(np.float64), poses64, eps=1e-3)
+    gv = upload(pf, cfg1["vol"], T32, v.W, dev, layout=layout)
+    xt = torch.as_tensor(x32).to(dev)
+    E, nv = pf.particles_score(gv, xt[:, 0].contiguous(), xt[:, 1].contiguous(), xt[:, 2].contiguous(),
+                               torch.as_tensor(P32).to(dev))
+    check_fitness(E.cpu().numpy(), nv.cpu().numpy(), lo, hi)
+    assert np.all(nv.cpu().numpy() > 0)
+    # bitwise reproducible
+    E2, nv2 = pf.particles_score(gv, xt[:, 0].contiguous(), xt[:, 1].contiguous(), xt[:, 2].contiguous(),
+                                 torch.as_tensor(P32).to(dev))
+    assert torch.equal(E, E2) and torch.equal(nv, nv2)
+
+
+@pytest.mark.parametrize("n_pts", [1, 3, 1000])
+def test_score_edge_cases(pf, orc, dev, cfg1, cfg1_vol, n_pts):
+    say(f"[score] edge n_pts={n_pts}")
+    v, v32, T32 = cfg1_vol
+    xyz, _ = orc.backproject(cfg1["depth1"], cfg1["intr"], 1)
+    x32 = xyz[:n_pts].astype(np.float32)
+    far = np.array([[50.0, 0.0, 1.0]], np.float32)     # outside the grid for every pose
+    pts = np.concatenate([x32, far]) if n_pts > 1 else x32
+    poses = [(np.eye(3), np.zeros(3)), (np.eye(3), np.array([100.0, 0.0, 0.0]))]
+    P32 = pf.poses_to_f32(poses)
+    lo, hi, _ = v32.fitness_interval_many(pts.astype(np.float64), poses, eps=1e-3)
+    gv = upload(pf, cfg1["vol"], T32, v.W, dev)
+    pt = torch.as_tensor(np.ascontiguousarray(pts)).to(dev)
+    E, nv = pf.particles_score(gv, pt[:, 0].contiguous(), pt[:, 1].contiguous(), pt[:, 2].contiguous(),
+                               torch.as_tensor(P32).to(dev))
+    check_fitness(E.cpu().numpy(), nv.cpu().numpy(), lo, hi)
+    assert E[1].item() == 1.0 and nv[1].item() == 0          # every sample outside: E = 1
+
+
+def test_score_affine_field_is_zero(pf, orc, dev):
+    say("[score] plane field")
+    spec = synth.VolumeSpec.centred(96, 0.02, 0.08, (0.0, 0.0, 1.2))
+    n = np.array([0.1, -0.2, -1.0])
+    n /= np.linalg.norm(n)
+    c = np.array([0.0, 0.0, 1.2])
+    T = synth.fill_plane_volume(spec, n, float(n @ c)).astype(np.float32)
+    u = np.cross(n, [1.0, 0, 0])
+    u /= np.linalg.norm(u)
+    w = np.cross(n, u)
+    ab = np.random.default_rng(0).uniform(-0.4, 0.4, (5000, 2))
+    P = (c + ab[:, :1] * u + ab[:, 1:] * w).astype(np.float32)
+    gv = upload(pf, spec, T, np.ones(T.shape), dev)
+    pt = torch.as_tensor(P).to(dev)
+    E, nv = pf.particles_score(gv, pt[:, 0].contiguous(), pt[:, 1].contiguous(), pt[:, 2].contiguous(),
+                               torch.as_tensor(pf.poses_to_f32([(np.eye(3), np.zeros(3))])).to(dev))
+    assert nv.item() == 5000 and E.item() <= 2e-6
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+def test_cells_replica_tracks_fusion(pf, orc, dev, cfg1, fmt):
+    """After GPU fusion of two frames, scoring through the cell replica is bitwise identical to
+    scoring through the x-fastest storage (the replica holds exactly the stored values)."""
+    say(f"[score] cell replica vs linear after fusion, format {fmt}")
+    spec, intr = cfg1["vol"], cfg1["intr"]
+    gv = pf.Tsdf(spec, fmt=fmt, device=dev, layout=pf.LAYOUT_CELLS)
+    for depth, (R, t) in [(cfg1["depth1"], cfg1["gt1"]), (cfg1["depth2"], cfg1["gt2"])]:
+        gv.integrate(torch.as_tensor(depth).to(dev), intr, R, t)
+    lin = pf.Tsdf(spec, fmt=fmt, device=dev, layout=pf.LAYOUT_LINEAR, init=False)
+    n = spec.nx * spec.ny * spec.nz
+    lin.T[:n].copy_(gv.T[:n])
+    lin.W.copy_(gv.W)
+    xyz, _ = orc.backproject(cfg1["depth2"], intr, 1)
+    xt = torch.as_tensor(xyz.astype(np.float32)).to(dev)
+    poses = _poses_around(orc, *cfg1["init2"], 300, math.radians(5), 0.03, 1)
+    P = torch.as_tensor(pf.poses_to_f32(poses)).to(dev)
+    a = pf.particles_score(gv, xt[:, 0].contiguous(), xt[:, 1].contiguous(), xt[:, 2].contiguous(), P)
+    b = pf.particles_score(lin, xt[:, 0].contiguous(), xt[:, 1].contiguous(), xt[:, 2].contiguous(), P)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert int((a[1] > 0).sum()) > 250
+
+
+# ----------------------------------------------------------------------------- update
+def test_update_parity(pf, orc, dev, cfg1, cfg1_vol):
+    say("[update] state init, draw, advantage set on identical fitness")
+    v, v32, T32 = cfg1_vol
+    K = 1000
+    prm = pf.TrackParams(seed=12345, frame_index=7, n_iters=3, K=K, rates=(1,), s1_deg=10.0, s1_m=0.1)
+    R0, t0 = cfg1["init2"]
+    state = torch.zeros(pf.state_bytes(K), dtype=torch.uint8, device=dev)
+    poses = torch.zeros((K + 1, 12), dtype=torch.float32, device=dev)
+    pf.particles_state_init(state, R0, t0, prm, poses)
+    D = pf.read_deltas(state, K)
+    s_rad = math.radians(10.0)
+    for k in range(1, K + 1):
+        r, tau = orc.draw_delta(12345, 7, 1, k, s_rad, 0.1)
+        assert np.array_equal(D[k, :3], r) and np.array_equal(D[k, 3:], tau), k
+    Pg = poses.cpu().numpy()
+    for k in (0, 1, 500, K):
+        Ro, to = orc.compose(D[k, :3], D[k, 3:], R0, t0) if k else (R0, t0)
+        ref = pf.poses_to_f32([(Ro, to)])[0]
+        assert np.abs(Pg[k] - ref).max() <= 2 * np.abs(ref).max() * 2 ** -24
+    # identical fitness input on both sides, with exact ties to E_0 that must be excluded
+    rng = np.random.default_rng(5)
+    fit = rng.uniform(0.1, 0.5, K + 1).astype(np.float32)
+    fit[0] = 0.3
+    fit[rng.choice(np.arange(1, K + 1), 20, replace=False)] = 0.3
+    xyz, _ = orc.backproject(cfg1["depth2"], cfg1["intr"], 2)
+    x32 = xyz.astype(np.float32)
+    gv = upload(pf, cfg1["vol"], T32, v.W, dev)
+    xt = torch.as_tensor(x32).to(dev)
+    nvz = torch.zeros(K + 1, dtype=torch.int32, device=dev)
+    pf.particles_update(gv, xt[:, 0].contiguous(), xt[:, 1].contiguous(), xt[:, 2].contiguous(),
+                        torch.as_tensor(fit).to(dev), nvz, state, K, poses)
+    st = pf.read_state(state)
+    na, Ro, to, mean = orc.advantage_update(fit.astype(np.float64), D, R0, t0)
+    assert st.n_adv == na == int((fit[1:] < fit[0]).sum())
+    assert np.abs(np.array(st.mean[:]) - mean).max() <= 1e-15 * max(1.0, np.abs(mean).max()) * 50
+    Rg, tg = np.array(st.R[:]).reshape(3, 3), np.array(st.t[:])
+    assert np.abs(Rg - Ro).max() <= 1e-13 and np.abs(tg - to).max() <= 1e-13
+    # E* of the new pose on the same points, and the search-size update
+    P32 = pf.poses_to_f32([(Rg, tg)])[0].reshape(3, 4).astype(np.float64)
+    lo, hi, _ = v32.fitness_interval_many(x32.astype(np.float64), [(P32[:, :3], P32[:, 3])], eps=1e-3)
+    check_fitness([st.Estar], None, lo, hi)
+    f_lo, f_hi = 0.1 + 0.9 * lo[0], 0.1 + 0.9 * hi[0]
+    assert s_rad * f_lo * (1 - 1e-4) <= st.s_rad <= s_rad * f_hi * (1 + 1e-4)
+    assert st.iter == 2 and st.E0 == np.float32(0.3)
+
+
+# ----------------------------------------------------------------------------- whole frame
+@pytest.mark.parametrize("mode", [0, 1])
+def test_track_frame_parity_cfg1(pf, orc, dev, cfg1, cfg1_vol, mode):
+    say(f"[track] cfg1 compose mode {mode}")
+    v, v32, T32 = cfg1_vol
+    gv = upload(pf, cfg1["vol"], T32, v.W, dev)
+    R0, t0 = cfg1["init2"]
+    prm = pf.TrackParams(seed=3, frame_index=1, n_iters=10, K=256, rates=(1,), pixel_stride=2, s1_deg=5.0, s1_m=0.03,
+                         compose_mode=mode)
+    trk = pf.Tracker(cfg1["intr"], prm, device=dev)
+    depth = torch.as_tensor(cfg1["depth2"]).to(dev)
+    R, t, st = trk.track(gv, depth, R0, t0)
+    oprm = orc.make_params(seed=3, frame_index=1, n_iters=10, K=256, rates=(1,), pixel_stride=2, s1_deg=5.0,
+                           s1_m=0.03, compose_mode=mode)
+    Ro, to, recs = v32.track_frame(cfg1["depth2"], cfg1["intr"], R0, t0, oprm)
+    dr, dt = math.degrees(orc.rot_err(R, Ro)), float(np.linalg.norm(t - to))
+    say(f"    pose vs oracle: {dr:.3e} deg, {dt * 1e3:.3e} mm; |A| gpu {list(st.n_adv[:10])} "
+        f"oracle {[r.n_adv for r in recs]}")
+    assert dr <= 0.05 and dt <= 1e-3
+    assert st.n_points == 4800 - int((cfg1["depth2"][::2, ::2] <= 0).sum())
+    for i in range(10):
+        assert abs(st.E0[i] - recs[i].E0) <= 1e-3 and abs(st.Estar[i] - recs[i].Estar) <= 1e-3
+    # determinism
+    R2, t2, st2 = trk.track(gv, depth, R0, t0)
+    assert np.array_equal(R, R2) and np.array_equal(t, t2)
+    assert list(st.n_adv[:10]) == list(st2.n_adv[:10])
+
+
+def test_track_frame_rates_and_stats(pf, orc, dev, cfg1, cfg1_vol):
+    say("[track] cfg1 rate cycle 1,2,3")
+    v, v32, T32 = cfg1_vol
+    gv = upload(pf, cfg1["vol"], T32, v.W, dev)
+    R0, t0 = cfg1["init2"]
+    prm = pf.TrackParams(seed=9, frame_index=2, n_iters=6, K=300, rates=(1, 2, 3), pixel_stride=1, s1_deg=5.0,
+                         s1_m=0.03)
+    trk = pf.Tracker(cfg1["intr"], prm, device=dev)
+    R, t, st = trk.track(gv, torch.as_tensor(cfg1["depth2"]).to(dev), R0, t0)
+    oprm = orc.make_params(seed=9, frame_index=2, n_iters=6, K=300, rates=(1, 2, 3), pixel_stride=1, s1_deg=5.0,
+                           s1_m=0.03)
+    Ro, to, recs = v32.track_frame(cfg1["depth2"], cfg1["intr"], R0, t0, oprm)
+    n = st.n_points
+    assert [st.n_sub[i] for i in range(6)] == [r.n_pts for r in recs] == [n, (n + 1) // 2, (n + 2) // 3] * 2
+    assert math.degrees(orc.rot_err(R, Ro)) <= 0.05 and np.linalg.norm(t - to) <= 1e-3

@@ -136,6 +136,7 @@ typedef struct pf_track_state {
     double s_rad_done, s_m_done; /* s^(i) of that iteration */
     double E0, Estar;      /* E(P^(i-1)) and E(P^(i)) on S_i */
     double mean[6];        /* averaged delta (r, tau) */
+    double R_prev[9], t_prev[3]; /* P^(i-1) of the last completed iteration */
     double beta;
     uint64_t seed;
     int32_t frame_index;
@@ -217,6 +218,23 @@ int32_t particles_score(const pf_tsdf* v, const float* px, const float* py, cons
                         int32_t n_pts, const float* poses, int32_t K, float* fitness,
                         int32_t* n_valid, void* stream);
 
+/* Adjoint of the fitness (not in the paper, which uses no gradients; it differentiates the
+ * fitness equation of Sec. III-B): for each of B poses P_b = compose(xi_b, base_b) it returns
+ * E_b and dE_b/dxi_b, xi = (rho, phi) = (translation, rotation vector) applied by the delta
+ * composition (PF_COMPOSE_*). The valid set, stencil cells and signs are frozen at P_b:
+ *   dE/d(delta_tau) = (1/|X|) sum_j s_j grad T(y_j),
+ *   dE/d(delta_r)   = (1/|X|) sum_j (y_j - c) x s_j grad T(y_j),
+ * s_j = sign(T(y_j)), grad T the analytic trilinear gradient, c = the camera centre (DECOUPLED) or
+ * the origin (LITERAL); the chain through compose uses the SO(3) left Jacobian J(phi):
+ * dE/dphi = J^T dE/d(delta_r) (DECOUPLED) or J^T (dE/d(delta_r) - rho x dE/d(delta_tau)) (LITERAL).
+ * E and the gradient come from one gather pass; sums are FP32 in a fixed order.
+ * base: device FP64 [B][12] row-major [R | t]; xi: device FP64 [B][6] or NULL (xi = 0);
+ * fitness: device float [B]; grad: device float [B][6] (rho, phi); n_valid: device int32 [B] or NULL. */
+int32_t particles_score_grad(const pf_tsdf* v, const float* px, const float* py, const float* pz,
+                             int32_t n_pts, const double* base, const double* xi, int32_t B,
+                             int32_t compose_mode, float* fitness, float* grad, int32_t* n_valid,
+                             void* stream);
+
 /* Bytes of the device state buffer for K particles (pf_track_state + (K+1)*6 doubles). */
 size_t particles_state_bytes(int32_t K);
 
@@ -249,7 +267,11 @@ size_t track_workspace_bytes(const pf_intrinsics* K, const pf_track_params* p);
 /* Randomized optimization of one frame (Sec. III-B, schedule of Sec. IV-A): back-projects
  * the depth at the pixel stride, builds the sub-sampled views S_r[j] = M[j r], runs n_iters
  * iterations of particles_score + particles_update on the device, optionally polishes the best
- * candidate (polish_steps > 0, see particles_score_grad), then synchronises the stream and
+ * candidate (polish_steps > 0: the lowest fitness among P^(I) and the particles of iteration I,
+ * ties to P^(I) then the lowest index, refined by polish_steps gradient steps xi = -alpha grad E on
+ * the densest view; the first alpha of a step moves no point more than half a voxel, Armijo
+ * acceptance E_new <= E - 1e-4 alpha |grad|^2 with up to 5 halvings, stop when none is accepted),
+ * then synchronises the stream and
  * writes the final pose to *out (host) and the per-iteration record to *stats (host,
  * nullable). It does not fuse the frame: call tsdf_integrate with *out afterwards.
  * depth: device float32 [height][width]; init: host; workspace: device, >= ws_bytes. */

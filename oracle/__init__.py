@@ -115,6 +115,11 @@ def lib():
         L.orc_advantage_update.argtypes = [dp, dp, C.c_int32, C.c_int32, P(Pose), P(Pose), dp]
         L.orc_fitness_grad.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, dp, dp, i64p]
         L.orc_fitness_grad_many.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, C.c_int32, dp, dp, i64p]
+        L.orc_fitness_grad_interval_many.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, C.c_int32,
+                                                     C.c_double, dp, dp]
+        L.orc_fitness_frozen_at.restype = C.c_double
+        L.orc_fitness_frozen_at.argtypes = [P(Vol), dp, C.c_int64, P(Pose), P(Pose)]
+        L.orc_grad_xi_fd.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, dp, C.c_double, dp]
         L.orc_fitness_frozen.restype = C.c_double
         L.orc_fitness_frozen.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, dp]
         L.orc_polish.restype = C.c_int32
@@ -292,11 +297,29 @@ class Volume:
                                     nv.ctypes.data_as(C.POINTER(C.c_int64)))
         return E, g, nv
 
+    def fitness_grad_interval_many(self, xyz, poses, mode=COMPOSE_DECOUPLED, eps=1e-3):
+        """Per pose, [lo, hi] of (E, grad6) over every cell choice of samples within eps of a face."""
+        x = _f64(xyz)
+        B = len(poses)
+        arr = (Pose * B)(*[Pose.of(R, t) for R, t in poses])
+        lo, hi = np.zeros((B, 7)), np.zeros((B, 7))
+        lib().orc_fitness_grad_interval_many(C.byref(self.c()), _dp(x), x.shape[0], arr, B, mode, eps, _dp(lo),
+                                             _dp(hi))
+        return lo, hi
+
     def fitness_frozen(self, xyz, R, t, xi, mode=COMPOSE_DECOUPLED):
         x = _f64(xyz)
         xi = _f64(xi).reshape(6)
         return float(lib().orc_fitness_frozen(C.byref(self.c()), _dp(x), x.shape[0], C.byref(Pose.of(R, t)), mode,
                                               _dp(xi)))
+
+    def grad_xi_fd(self, xyz, R, t, xi0, mode=COMPOSE_DECOUPLED, h=1e-6):
+        """d/dxi of E(compose(xi, (R, t))) at xi0 (frozen at xi0), by central differences."""
+        x = _f64(xyz)
+        xi0 = _f64(xi0).reshape(6)
+        g = np.zeros(6)
+        lib().orc_grad_xi_fd(C.byref(self.c()), _dp(x), x.shape[0], C.byref(Pose.of(R, t)), mode, _dp(xi0), h, _dp(g))
+        return g
 
     def polish(self, xyz, R, t, steps=5, mode=COMPOSE_DECOUPLED):
         x = _f64(xyz)

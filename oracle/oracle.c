@@ -569,33 +569,111 @@ void orc_fitness_grad(const orc_vol* V, const double* xyz, int64_t n, const orc_
     if (nvalid) *nvalid = cnt;
 }
 
+/* Interval form of E and of the frozen-set gradient for comparison with a float32 evaluation:
+ * samples whose grid coordinate lies within `eps` voxels of a cell face are evaluated with every
+ * admissible cell choice. With S_a the component sum and C the valid count, each bound is taken
+ * over the box [S_lo, S_hi] x [C_lo, C_hi] (S/C is monotone in each for C > 0), so the intervals
+ * contain every outcome of such choices. lo/hi: E then the 6 gradient components. */
+void orc_fitness_grad_interval(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t mode,
+                               double eps, double lo[7], double hi[7]) {
+    double Slo[7] = {0}, Shi[7] = {0};
+    int64_t Clo = 0, Chi = 0;
+    double cc[3] = {0, 0, 0};
+    if (mode == 0)
+        for (int a = 0; a < 3; ++a) cc[a] = P->t[a];
+    for (int64_t j = 0; j < n; ++j) {
+        double y[3], g[3];
+        transform(P, xyz + 3 * j, y);
+        grid_coord(V, y, g);
+        int64_t opts[3][2];
+        int nopt[3];
+        for (int a = 0; a < 3; ++a) {
+            double fl = floor(g[a]);
+            opts[a][0] = (int64_t)fl;
+            nopt[a] = 1;
+            double fr = g[a] - fl;
+            if (fr < eps) { opts[a][1] = (int64_t)fl - 1; nopt[a] = 2; }
+            else if (fr > 1.0 - eps) { opts[a][1] = (int64_t)fl + 1; nopt[a] = 2; }
+        }
+        double u[3] = {y[0] - cc[0], y[1] - cc[1], y[2] - cc[2]};
+        double mn[7], mx[7];
+        int cmin = 1, cmax = 0;
+        for (int e = 0; e < 7; ++e) { mn[e] = INFINITY; mx[e] = -INFINITY; }
+        for (int ox = 0; ox < nopt[0]; ++ox)
+            for (int oy = 0; oy < nopt[1]; ++oy)
+                for (int oz = 0; oz < nopt[2]; ++oz) {
+                    int64_t c[3] = {opts[0][ox], opts[1][oy], opts[2][oz]};
+                    double v = 0.0, term[7] = {0, 0, 0, 0, 0, 0, 0};
+                    int ok = sample_cell(V, g, c, &v);
+                    if (ok) {
+                        double f[3] = {g[0] - c[0], g[1] - c[1], g[2] - c[2]};
+                        double gT[3];
+                        trilinear_grad(V, c, f, gT);
+                        double sg = v > 0 ? 1.0 : (v < 0 ? -1.0 : 0.0);
+                        term[0] = fabs(v);
+                        for (int a = 0; a < 3; ++a) term[1 + a] = sg * gT[a];
+                        term[4] = sg * (u[1] * gT[2] - u[2] * gT[1]);
+                        term[5] = sg * (u[2] * gT[0] - u[0] * gT[2]);
+                        term[6] = sg * (u[0] * gT[1] - u[1] * gT[0]);
+                    }
+                    for (int e = 0; e < 7; ++e) {
+                        if (term[e] < mn[e]) mn[e] = term[e];
+                        if (term[e] > mx[e]) mx[e] = term[e];
+                    }
+                    if (ok < cmin) cmin = ok;
+                    if (ok > cmax) cmax = ok;
+                }
+        for (int e = 0; e < 7; ++e) {
+            Slo[e] += mn[e];
+            Shi[e] += mx[e];
+        }
+        Clo += cmin;
+        Chi += cmax;
+    }
+    for (int e = 0; e < 7; ++e) {
+        if (Chi == 0) { lo[e] = hi[e] = (e == 0 ? 1.0 : 0.0); continue; }
+        double cl = Clo > 0 ? (double)Clo : 1.0, ch = (double)Chi;
+        double a1 = Slo[e] / cl, a2 = Slo[e] / ch, b1 = Shi[e] / cl, b2 = Shi[e] / ch;
+        lo[e] = a1 < a2 ? a1 : a2;
+        hi[e] = b1 > b2 ? b1 : b2;
+        if (Clo == 0) {               /* every sample may drop out: E may be 1, gradient 0 */
+            if (e == 0) hi[e] = hi[e] > 1.0 ? hi[e] : 1.0;
+            else { lo[e] = lo[e] < 0.0 ? lo[e] : 0.0; hi[e] = hi[e] > 0.0 ? hi[e] : 0.0; }
+        }
+    }
+}
+
+void orc_fitness_grad_interval_many(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t B,
+                                    int32_t mode, double eps, double* lo, double* hi) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t b = 0; b < B; ++b) orc_fitness_grad_interval(V, xyz, n, P + b, mode, eps, lo + 7 * b, hi + 7 * b);
+}
+
 void orc_fitness_grad_many(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t B,
                            int32_t mode, double* E, double* grad, int64_t* nvalid) {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t b = 0; b < B; ++b) orc_fitness_grad(V, xyz, n, P + b, mode, E + b, grad + 6 * b, nvalid ? nvalid + b : NULL);
 }
 
-/* Frozen objective E_f(xi) = (1/|X0|) sum_{j in X0} s_j T_cell_j(y_j(xi)): the valid set X0, the
- * cells and the signs are those of xi = 0, and T_cell_j is the trilinear polynomial of the
- * cell (extended beyond it if y moves out). Its derivative at 0 is orc_fitness_grad; it is a
- * polynomial in y, so central differences converge at O(h^2). */
-double orc_fitness_frozen(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t mode,
-                          const double xi[6]) {
-    orc_pose Px;
-    orc_compose(mode, xi + 3, xi, P, &Px);
+/* Frozen objective: the valid set X0, the stencil cells and the signs are those of the pose
+ * P_freeze; E_f = (1/|X0|) sum_{j in X0} s_j T_cell_j(y_j), with y_j = P_eval x_j and T_cell_j the
+ * trilinear polynomial of the frozen cell (extended beyond the cell if y_j leaves it). It equals
+ * E(P_freeze) at P_eval = P_freeze and is a polynomial in y, so central differences of it converge
+ * at O(h^2) to the analytic gradient. */
+double orc_fitness_frozen_at(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P_freeze,
+                             const orc_pose* P_eval) {
     double s = 0.0;
     int64_t cnt = 0;
     for (int64_t j = 0; j < n; ++j) {
         double y0[3], g0[3], v0;
-        transform(P, xyz + 3 * j, y0);
+        transform(P_freeze, xyz + 3 * j, y0);
         grid_coord(V, y0, g0);
         int64_t c[3] = {(int64_t)floor(g0[0]), (int64_t)floor(g0[1]), (int64_t)floor(g0[2])};
         if (!sample_cell(V, g0, c, &v0)) continue;
         double sg = v0 > 0 ? 1.0 : (v0 < 0 ? -1.0 : 0.0);
-        double y[3], g[3], v;
-        transform(&Px, xyz + 3 * j, y);
+        double y[3], g[3];
+        transform(P_eval, xyz + 3 * j, y);
         grid_coord(V, y, g);
-        /* evaluate the frozen cell's polynomial at the moved point (stencil values already checked) */
         double f[3] = {g[0] - c[0], g[1] - c[1], g[2] - c[2]};
         double t[2][2][2];
         for (int dz = 0; dz < 2; ++dz)
@@ -608,11 +686,39 @@ double orc_fitness_frozen(const orc_vol* V, const double* xyz, int64_t n, const 
         double a11 = t[1][1][0] + f[0] * (t[1][1][1] - t[1][1][0]);
         double b0 = a00 + f[1] * (a10 - a00);
         double b1 = a01 + f[1] * (a11 - a01);
-        v = b0 + f[2] * (b1 - b0);
-        s += sg * v;
+        s += sg * (b0 + f[2] * (b1 - b0));
         cnt += 1;
     }
     return cnt > 0 ? s / (double)cnt : 1.0;
+}
+
+/* The frozen objective at P with a twist xi = (rho, phi) applied by the delta composition
+ * (rotation vector phi, translation rho), frozen at xi = 0: its derivative at 0 is
+ * orc_fitness_grad. */
+double orc_fitness_frozen(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t mode,
+                          const double xi[6]) {
+    orc_pose Px;
+    orc_compose(mode, xi + 3, xi, P, &Px);
+    return orc_fitness_frozen_at(V, xyz, n, P, &Px);
+}
+
+/* Gradient with respect to the twist parameters xi0 + dxi of compose(xi, base), frozen at
+ * compose(xi0, base), by central differences of the frozen objective with step h (the reference
+ * for the adjoint at xi0 != 0, where the chain through the SO(3) exponential matters). */
+void orc_grad_xi_fd(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* base, int32_t mode,
+                    const double xi0[6], double h, double grad6[6]) {
+    orc_pose P0;
+    orc_compose(mode, xi0 + 3, xi0, base, &P0);
+    for (int a = 0; a < 6; ++a) {
+        double xp[6], xm[6];
+        for (int b = 0; b < 6; ++b) xp[b] = xm[b] = xi0[b];
+        xp[a] += h;
+        xm[a] -= h;
+        orc_pose Pp, Pm;
+        orc_compose(mode, xp + 3, xp, base, &Pp);
+        orc_compose(mode, xm + 3, xm, base, &Pm);
+        grad6[a] = (orc_fitness_frozen_at(V, xyz, n, &P0, &Pp) - orc_fitness_frozen_at(V, xyz, n, &P0, &Pm)) / (2.0 * h);
+    }
 }
 
 /* ----------------------------------------------------------------------------------------

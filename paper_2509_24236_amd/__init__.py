@@ -68,14 +68,14 @@ class pf_track_state(C.Structure):
     _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3), ("s_rad", C.c_double), ("s_m", C.c_double),
                 ("R_new", C.c_double * 9), ("t_new", C.c_double * 3), ("s_rad_done", C.c_double),
                 ("s_m_done", C.c_double), ("E0", C.c_double), ("Estar", C.c_double), ("mean", C.c_double * 6),
-                ("beta", C.c_double), ("seed", C.c_uint64), ("frame_index", C.c_int32), ("iter", C.c_int32),
+                ("R_prev", C.c_double * 9), ("t_prev", C.c_double * 3), ("beta", C.c_double), ("seed", C.c_uint64), ("frame_index", C.c_int32), ("iter", C.c_int32),
                 ("iter_done", C.c_int32), ("K", C.c_int32), ("compose_mode", C.c_int32), ("n_adv", C.c_int32),
                 ("n_sub", C.c_int32), ("n_valid_star", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32)]
 
 
 # every symbol include/profusion.h declares
 EXPORTS = ("pf_last_error", "tsdf_bytes", "tsdf_cells_offset", "tsdf_init", "tsdf_integrate", "tsdf_export_linear", "tsdf_import_linear",
-           "backproject", "particles_score", "particles_state_bytes", "particles_state_init", "particles_update",
+           "backproject", "particles_score", "particles_score_grad", "particles_state_bytes", "particles_state_init", "particles_update",
            "track_workspace_bytes", "track_frame", "pf_timing_enable", "pf_timing_read")
 
 _lib = None
@@ -103,6 +103,7 @@ def lib() -> C.CDLL:
     L.tsdf_import_linear.argtypes = [P(pf_tsdf), vp, vp, vp]
     L.backproject.argtypes = [vp, P(pf_intrinsics), i32, vp, vp, vp, vp, vp]
     L.particles_score.argtypes = [P(pf_tsdf), vp, vp, vp, i32, vp, i32, vp, vp, vp]
+    L.particles_score_grad.argtypes = [P(pf_tsdf), vp, vp, vp, i32, vp, vp, i32, i32, vp, vp, vp, vp]
     L.particles_state_bytes.restype = C.c_size_t
     L.particles_state_bytes.argtypes = [i32]
     L.particles_state_init.argtypes = [vp, P(pf_pose), P(pf_track_params), vp, vp]
@@ -279,6 +280,56 @@ def particles_score(vol: Tsdf, px, py, pz, poses, fitness=None, n_valid=None, n_
     _check(lib().particles_score(C.byref(vol.desc), _ptr(px), _ptr(py), _ptr(pz), n, _ptr(poses), K, _ptr(fitness),
                                  _ptr(n_valid), _stream(stream)))
     return fitness, n_valid
+
+
+def particles_score_grad(vol: Tsdf, px, py, pz, base, xi=None, mode=COMPOSE_DECOUPLED, n_pts=None, stream=None):
+    """E and dE/dxi for poses compose(xi_b, base_b) (base: [B][12] float64 [R | t]; xi: [B][6] float64
+    (rho, phi) or None): returns (fitness [B], grad [B][6], n_valid [B])."""
+    torch = _torch()
+    B = base.shape[0]
+    n = int(px.numel() if n_pts is None else n_pts)
+    if base.dtype != torch.float64 or (xi is not None and xi.dtype != torch.float64):
+        raise ValueError("base and xi must be float64")
+    E = torch.empty(B, dtype=torch.float32, device=base.device)
+    g = torch.empty((B, 6), dtype=torch.float32, device=base.device)
+    nv = torch.empty(B, dtype=torch.int32, device=base.device)
+    _check(lib().particles_score_grad(C.byref(vol.desc), _ptr(px), _ptr(py), _ptr(pz), n, _ptr(base), _ptr(xi), B,
+                                      mode, _ptr(E), _ptr(g), _ptr(nv), _stream(stream)))
+    return E, g, nv
+
+
+def _fitness_fn():
+    torch = _torch()
+
+    class FitnessFn(torch.autograd.Function):
+        """E(compose(xi, base)) with the hand-written adjoint as its backward.
+
+        forward(xi [B][6] float64, base [B][12] float64, vol, px, py, pz, mode) -> E [B] float64.
+        The backward multiplies the upstream gradient into the adjoint's dE/dxi (frozen valid set)."""
+
+        @staticmethod
+        def forward(ctx, xi, base, vol, px, py, pz, mode=COMPOSE_DECOUPLED):
+            E, g, _ = particles_score_grad(vol, px, py, pz, base.contiguous(), xi.detach().contiguous(), mode)
+            ctx.save_for_backward(g)
+            return E.to(xi.dtype)
+
+        @staticmethod
+        def backward(ctx, gE):
+            (g,) = ctx.saved_tensors
+            return gE[:, None] * g.to(gE.dtype), None, None, None, None, None, None
+
+    return FitnessFn
+
+
+_FitnessFn = None
+
+
+def fitness(xi, base, vol, px, py, pz, mode=COMPOSE_DECOUPLED):
+    """Differentiable fitness (torch.autograd.Function backed by particles_score_grad)."""
+    global _FitnessFn
+    if _FitnessFn is None:
+        _FitnessFn = _fitness_fn()
+    return _FitnessFn.apply(xi, base, vol, px, py, pz, mode)
 
 
 def state_bytes(K: int) -> int:

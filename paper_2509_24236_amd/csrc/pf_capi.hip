@@ -221,6 +221,22 @@ int32_t particles_score(const pf_tsdf* v, const float* px, const float* py, cons
     return launch_score(make_view(v), p, poses, K, fitness, n_valid, (hipStream_t)stream);
 }
 
+int32_t particles_score_grad(const pf_tsdf* v, const float* px, const float* py, const float* pz, int32_t n_pts,
+                             const double* base, const double* xi, int32_t B, int32_t compose_mode, float* fitness,
+                             float* grad, int32_t* n_valid, void* stream) {
+    int32_t rc = check_tsdf(v, "particles_score_grad", false);
+    if (rc) return rc;
+    if (!px || !py || !pz || !base || !fitness || !grad)
+        return set_error(PF_EINVAL, "particles_score_grad: null pointer");
+    if (n_pts < 1) return set_error(PF_EINVAL, "particles_score_grad: n_pts %d must be >= 1", n_pts);
+    if (B < 1 || B > 65535) return set_error(PF_EINVAL, "particles_score_grad: B %d not in 1..65535", B);
+    if (compose_mode != PF_COMPOSE_DECOUPLED && compose_mode != PF_COMPOSE_LITERAL)
+        return set_error(PF_EINVAL, "particles_score_grad: unknown compose_mode %d", compose_mode);
+    Points p{px, py, pz, n_pts, nullptr};
+    return launch_grad(make_view(v), p, base, xi, B, 1, compose_mode, fitness, grad, n_valid, nullptr,
+                       (hipStream_t)stream);
+}
+
 size_t particles_state_bytes(int32_t K) {
     if (K < 1 || K > PF_MAX_K) return 0;
     return state_bytes(K);

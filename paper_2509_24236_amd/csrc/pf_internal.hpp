@@ -121,6 +121,17 @@ int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int
 // Largest number of per-workgroup partial sums the single-pose passes use.
 constexpr int kMaxPartials = 256;
 
+// Adjoint and polish (pf_grad.hip).
+struct GradPartial;
+int32_t launch_grad(const VolView& vv, const Points& p, const double* base, const double* xi, int B, int S, int mode,
+                    float* E, float* g, int* nv, GradPartial* partials, hipStream_t s);
+size_t polish_scratch_bytes(int S);
+int polish_accepted_offset();
+int32_t launch_polish(const VolView& vv, const Points& p, int S, pf_track_state* st, int K, const float* fit,
+                      int mode, double vs, int steps, void* scratch, hipStream_t s);
+int32_t launch_state_fitness(const VolView& vv, const Points& p, int S, const pf_track_state* st, void* scratch,
+                             float* E_out, int* n_out, hipStream_t s);
+
 int32_t launch_backproject(const float* depth, const pf_intrinsics* K, int stride, float* px, float* py, float* pz,
                            int* n_out, int* block_counts, hipStream_t s);
 size_t backproject_scratch_ints(const pf_intrinsics* K);

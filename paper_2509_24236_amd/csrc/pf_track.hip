@@ -197,8 +197,9 @@ __global__ void k_state_set(pf_track_state* st, pf_track_state init) { *st = ini
 constexpr int kAdvThreads = 256;
 
 // Field ownership keeps every kernel free of read-after-write hazards across its workgroups:
-// k_adv reads (R, t, s, iter, deltas, fitness) and workgroup 0 writes (R_new, t_new, s_*_done,
-// iter_done, E0, mean, n_adv, n_sub); k_next reads the latter and writes the former.
+// k_adv reads (R, t, s, iter, deltas, fitness) and workgroup 0 writes (R_prev, t_prev, R_new,
+// t_new, s_*_done, iter_done, E0, mean, n_adv, n_sub); k_next reads the latter and writes the
+// former.
 //
 // k_adv, ADV = true: after the pending particles of iteration i were scored on S_i, every
 // workgroup forms the advantage set A = {k >= 1 : E_k < E_0} and the mean delta over A in the
@@ -262,6 +263,8 @@ __global__ __launch_bounds__(kAdvThreads) void k_adv(VolView vv, const float* __
             }
             store_pose12(pose_sh, R, t);
             if (blockIdx.x == 0) {
+                for (int q = 0; q < 9; ++q) st->R_prev[q] = st->R[q];
+                for (int q = 0; q < 3; ++q) st->t_prev[q] = st->t[q];
                 for (int q = 0; q < 9; ++q) st->R_new[q] = R[q];
                 for (int q = 0; q < 3; ++q) st->t_new[q] = t[q];
                 for (int d = 0; d < 6; ++d) st->mean[d] = mean[d];
@@ -439,30 +442,6 @@ int32_t launch_next(int format, bool first, pf_track_state* st, int K, int G, bo
     return check_launch("particle draw");
 }
 
-// Final fitness of the pending pose: reduces the partials into (E, count).
-template <int FMT>
-__global__ void k_final(pf_track_state* st, int K, int n_partials, float* E_out, int* n_out) {
-    const Partial* pt = state_partials(st, K);
-    float sum = 0.0f;
-    int cnt = 0;
-    for (int b = 0; b < n_partials; ++b) {
-        sum += pt[b].sum;
-        cnt += pt[b].cnt;
-    }
-    *E_out = cnt > 0 ? (sum * Fmt<FMT>::scale) / (float)cnt : 1.0f;
-    *n_out = cnt;
-}
-
-int32_t launch_final(int format, pf_track_state* st, int K, int G, float* E_out, int* n_out, hipStream_t s) {
-    switch (format) {
-        case PF_F32_W_F32: hipLaunchKernelGGL(k_final<PF_F32_W_F32>, dim3(1), dim3(1), 0, s, st, K, G, E_out, n_out); break;
-        case PF_F16_W_U8: hipLaunchKernelGGL(k_final<PF_F16_W_U8>, dim3(1), dim3(1), 0, s, st, K, G, E_out, n_out); break;
-        case PF_I16_W_U8: hipLaunchKernelGGL(k_final<PF_I16_W_U8>, dim3(1), dim3(1), 0, s, st, K, G, E_out, n_out); break;
-        default: return set_error(PF_EUNSUPPORTED, "unsupported format %d", format);
-    }
-    return check_launch("final fitness");
-}
-
 pf_track_state make_state(const pf_pose* init, const pf_track_params* p) {
     pf_track_state h;
     memset(&h, 0, sizeof h);
@@ -483,7 +462,7 @@ pf_track_state make_state(const pf_pose* init, const pf_track_params* p) {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t pts, counts, views[3], vcount, poses, fit, nv, state, recs, total;
+    size_t pts, counts, views[3], vcount, poses, fit, nv, state, recs, polish, fin, total;
 };
 
 WsLayout ws_layout(const pf_intrinsics* K, const pf_track_params* p) {
@@ -513,6 +492,10 @@ WsLayout ws_layout(const pf_intrinsics* K, const pf_track_params* p) {
     off += align_up(partials_offset(p->K) + kMaxPartials * sizeof(Partial));
     L.recs = off;
     off += align_up(PF_MAX_ITERS * sizeof(IterRec) + 2 * sizeof(int));
+    L.polish = off;
+    off += align_up(polish_scratch_bytes(kMaxPartials));
+    L.fin = off;
+    off += align_up(256 + kMaxPartials * 8);
     L.total = off;
     return L;
 }
@@ -619,24 +602,30 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
         // the last iteration only completes (E*, s); its particles stay in `poses` / `fit`
         if ((rc = launch_next(vv.format, false, st, p->K, Gv[r], i < p->n_iters, poses, recs, s))) return rc;
     }
-    // fitness of the returned pose P^(I) on the densest view
+    // optional gradient polish of the best candidate, on the densest view
     int densest = 0;
     for (int r = 1; r < p->n_rates; ++r)
         if (p->rates[r] < p->rates[densest]) densest = r;
+    if (p->polish_steps > 0 &&
+        (rc = launch_polish(vv, views[densest], Gv[densest], st, p->K, fit, p->compose_mode, v->voxel_size,
+                            p->polish_steps, ws + L.polish, s)))
+        return rc;
+    // fitness of the returned pose on the densest view
     float* ef_dev = reinterpret_cast<float*>(recs + PF_MAX_ITERS);
     int* nvf_dev = reinterpret_cast<int*>(ef_dev + 1);
-    if ((rc = launch_adv(false, vv, views[densest], Gv[densest], fit, st, p->K, s))) return rc;
-    if ((rc = launch_final(vv.format, st, p->K, Gv[densest], ef_dev, nvf_dev, s))) return rc;
+    if ((rc = launch_state_fitness(vv, views[densest], Gv[densest], st, ws + L.fin, ef_dev, nvf_dev, s))) return rc;
 
     pf_track_state hs;
     IterRec hr[PF_MAX_ITERS];
     float ef;
-    int nvf, nall;
+    int nvf, nall, accepted = 0;
     if (hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(hr, recs, sizeof(IterRec) * p->n_iters, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(&ef, ef_dev, sizeof ef, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(&nvf, nvf_dev, sizeof nvf, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(&nall, vcount, sizeof nall, hipMemcpyDeviceToHost, s) != hipSuccess)
+        hipMemcpyAsync(&nall, vcount, sizeof nall, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        (p->polish_steps > 0 && hipMemcpyAsync(&accepted, ws + L.polish + polish_accepted_offset(), sizeof accepted,
+                                               hipMemcpyDeviceToHost, s) != hipSuccess))
         return set_error(PF_EHIP, "track_frame: read-back failed: %s", hipGetErrorString(hipGetLastError()));
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return set_error(PF_EHIP, "track_frame: %s", hipGetErrorString(e));
@@ -665,6 +654,7 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
             stats->s_m[i] = hr[i].s_m;
         }
         stats->E_final = ef;
+        stats->polish_accepted = accepted;
         stats->n_valid_final = nvf;
         stats->lost = nvf < p->min_valid ? 1 : 0;
     }

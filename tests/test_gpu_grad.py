@@ -1,0 +1,152 @@
+"""Form (3): the hand-written adjoint (particles_score_grad), its torch.autograd wrapper and the
+gradient polish inside track_frame, against the FP64 oracle on the differentiation workload
+(the tiny room, 1000 seeded poses in the +-5 deg / +-3 cm box around the true pose, seed 30)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pf():
+    import paper_2509_24236_amd as pf
+    pf.lib()
+    return pf
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def setup(orc, pf, dev):
+    d = synth.cfg1_inputs()
+    v = orc.Volume(d["vol"])
+    v.integrate(d["depth1"], d["intr"], np.eye(3), np.zeros(3))
+    T32 = v.T.astype(np.float32)
+    v32 = orc.Volume(d["vol"], T=T32.astype(np.float64), W=v.W)
+    gv = pf.Tsdf(d["vol"], device=dev, init=False)
+    gv.import_linear(T32, v.W.astype(np.float32))
+    X, _ = orc.backproject(d["depth2"], d["intr"], 2)
+    X32 = X.astype(np.float32)
+    xt = torch.as_tensor(X32).to(dev)
+    pts = (xt[:, 0].contiguous(), xt[:, 1].contiguous(), xt[:, 2].contiguous())
+    return d, v32, gv, X32, pts
+
+
+def cfg3_poses(orc, d, n, seed=30):
+    rng = np.random.default_rng(seed)
+    R, t = d["gt2"]
+    return [orc.compose(rng.uniform(-1, 1, 3) * math.radians(5), rng.uniform(-1, 1, 3) * 0.03, R, t) for _ in range(n)]
+
+
+def rows(poses):
+    return np.stack([np.concatenate([R, t.reshape(3, 1)], 1).reshape(12) for R, t in poses])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_adjoint_parity_1000_poses(pf, orc, dev, setup, mode):
+    say(f"[grad] 1000 poses, mode {mode}")
+    d, v32, gv, X32, pts = setup
+    poses = cfg3_poses(orc, d, 1000)
+    base = torch.as_tensor(rows(poses)).to(dev)
+    E, g, nv = pf.particles_score_grad(gv, *pts, base, None, mode)
+    # the GPU rounds each pose to FP32 before sampling; give the oracle the same pose
+    P32 = pf.poses_to_f32(poses).astype(np.float64).reshape(-1, 3, 4)
+    lo, hi = v32.fitness_grad_interval_many(X32.astype(np.float64), [(P[:, :3], P[:, 3]) for P in P32], mode,
+                                            eps=1e-3)
+    got = np.concatenate([E.cpu().numpy()[:, None], g.cpu().numpy()], 1).astype(np.float64)
+    scale = np.maximum(np.abs(lo), np.abs(hi))
+    tol = np.concatenate([1e-4 * scale[:, :1], 2e-4 * scale[:, 1:].max(1, keepdims=True).repeat(6, 1)], 1) + 1e-6
+    bad = (got < lo - tol) | (got > hi + tol)
+    assert not bad.any(), f"{bad.any(1).sum()} poses outside the oracle interval; first {np.flatnonzero(bad.any(1))[:5]}"
+    assert (nv.cpu().numpy() > 100).all()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_adjoint_chain_vs_central_differences(pf, orc, dev, setup, mode):
+    """dE/dxi at xi != 0 vs central differences (h = 1e-4) of the oracle's frozen objective."""
+    say(f"[grad] chain rule vs central differences, mode {mode}")
+    d, v32, gv, X32, pts = setup
+    rng = np.random.default_rng(31)
+    poses = cfg3_poses(orc, d, 16, seed=32)
+    xi = np.concatenate([rng.uniform(-0.02, 0.02, (16, 3)), rng.uniform(-0.06, 0.06, (16, 3))], 1)
+    base = torch.as_tensor(rows(poses)).to(dev)
+    E, g, nv = pf.particles_score_grad(gv, *pts, base, torch.as_tensor(xi).to(dev), mode)
+    g = g.cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for b, (R, t) in enumerate(poses):
+        ref = v32.grad_xi_fd(X32.astype(np.float64), R, t, xi[b], mode, h=1e-4)
+        err = np.abs(g[b] - ref).max() / np.abs(ref).max()
+        worst = max(worst, err)
+    say(f"    worst relative deviation {worst:.2e}")
+    assert worst <= 5e-3
+
+
+def test_autograd_function(pf, orc, dev, setup):
+    say("[grad] autograd.Function")
+    d, v32, gv, X32, pts = setup
+    poses = cfg3_poses(orc, d, 8, seed=33)
+    base = torch.as_tensor(rows(poses)).to(dev)
+    xi = torch.zeros((8, 6), dtype=torch.float64, device=dev, requires_grad=True)
+    E = pf.fitness(xi, base, gv, *pts)
+    w = torch.linspace(0.5, 2.0, 8, dtype=torch.float64, device=dev)
+    (E * w).sum().backward()
+    E2, g2, _ = pf.particles_score_grad(gv, *pts, base, None, 0)
+    assert torch.equal(E, E2.double())
+    assert torch.allclose(xi.grad, w[:, None] * g2.double(), rtol=0, atol=0)
+
+
+def test_unfrozen_finite_difference_agreement(pf, orc, dev, setup):
+    """Report only: central differences (h = 1e-4) of the FP32, unfrozen fitness jump where samples
+    enter or leave the valid set, so agreement with the adjoint is a fraction, not a bound."""
+    d, v32, gv, X32, pts = setup
+    poses = cfg3_poses(orc, d, 64, seed=34)
+    base = torch.as_tensor(rows(poses)).to(dev)
+    E, g, _ = pf.particles_score_grad(gv, *pts, base, None, 0)
+    h = 1e-4
+    fd = np.zeros((64, 6))
+    for a in range(6):
+        e = torch.zeros((64, 6), dtype=torch.float64, device=dev)
+        e[:, a] = h
+        Ep, _, _ = pf.particles_score_grad(gv, *pts, base, e, 0)
+        Em, _, _ = pf.particles_score_grad(gv, *pts, base, -e, 0)
+        fd[:, a] = (Ep.double() - Em.double()).cpu().numpy() / (2 * h)
+    g = g.cpu().numpy()
+    rel = np.abs(fd - g) / (np.abs(g).max(1, keepdims=True) + 1e-12)
+    frac = float((rel < 0.1).mean())
+    say(f"    unfrozen FD within 10% of the adjoint for {100 * frac:.1f}% of components")
+    assert frac > 0.3
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_polish_parity(pf, orc, dev, setup, mode):
+    say(f"[polish] track_frame with 5 polish steps, mode {mode}")
+    d, v32, gv, X32, pts = setup
+    R0, t0 = d["init2"]
+    prm = pf.TrackParams(seed=3, frame_index=1, n_iters=10, K=256, rates=(1,), pixel_stride=2, s1_deg=5.0,
+                         s1_m=0.03, compose_mode=mode, polish_steps=5)
+    trk = pf.Tracker(d["intr"], prm, device=dev)
+    R, t, st = trk.track(gv, torch.as_tensor(d["depth2"]).to(dev), R0, t0)
+    oprm = orc.make_params(seed=3, frame_index=1, n_iters=10, K=256, rates=(1,), pixel_stride=2, s1_deg=5.0,
+                           s1_m=0.03, compose_mode=mode, polish_steps=5)
+    Ro, to, recs = v32.track_frame(d["depth2"], d["intr"], R0, t0, oprm)
+    dr, dt = math.degrees(orc.rot_err(R, Ro)), float(np.linalg.norm(t - to))
+    say(f"    pose vs oracle {dr:.2e} deg {dt * 1e3:.3e} mm; accepted {st.polish_accepted}; E_final {st.E_final:.5f}")
+    assert dr <= 0.05 and dt <= 1e-3
+    # the polish lowered the fitness on the densest view relative to the unpolished pose
+    prm0 = pf.TrackParams(seed=3, frame_index=1, n_iters=10, K=256, rates=(1,), pixel_stride=2, s1_deg=5.0,
+                          s1_m=0.03, compose_mode=mode, polish_steps=0)
+    _, _, st0 = pf.Tracker(d["intr"], prm0, device=dev).track(gv, torch.as_tensor(d["depth2"]).to(dev), R0, t0)
+    assert st.E_final <= st0.E_final

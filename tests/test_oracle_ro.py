@@ -210,3 +210,52 @@ def test_polish_decreases_fitness(orc):
     assert acc >= 1 and E1 < E0
     E1b, _ = vol.fitness(X, R1, t1)
     assert abs(E1b - E1) <= 1e-15
+
+
+def _left_jacobian(phi):
+    """Left Jacobian of SO(3) (textbook closed form): exp(phi + d) = exp(J_l(phi) d) exp(phi) + O(d^2)."""
+    th = np.linalg.norm(phi)
+    K = np.array([[0, -phi[2], phi[1]], [phi[2], 0, -phi[0]], [-phi[1], phi[0], 0]])
+    return np.eye(3) + (1 - np.cos(th)) / th ** 2 * K + (th - np.sin(th)) / th ** 3 * K @ K
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_grad_xi_fd_chain_rule(orc, mode):
+    """The oracle's xi-space finite differences agree with the closed-form chain rule through the
+    SO(3) left Jacobian applied to the analytic gradient at the composed pose."""
+    d = synth.cfg1_inputs()
+    vol = orc.Volume(d["vol"])
+    vol.integrate(d["depth1"], d["intr"], np.eye(3), np.zeros(3))
+    X, _ = orc.backproject(d["depth2"], d["intr"], 2)
+    R, t = d["init2"]
+    xi0 = np.array([0.004, -0.003, 0.002, 0.03, -0.02, 0.015])       # (rho, phi)
+    g_fd = vol.grad_xi_fd(X, R, t, xi0, mode)
+    R0, t0 = orc.compose(xi0[3:], xi0[:3], R, t, mode)
+    _, g, nv = vol.fitness_grad(X, R0, t0, mode)
+    g_rho, g_phi = g[:3], g[3:]
+    J = _left_jacobian(xi0[3:])
+    if mode == 0:
+        ref = np.concatenate([g_rho, J.T @ g_phi])
+    else:
+        ref = np.concatenate([g_rho, J.T @ (g_phi - np.cross(xi0[:3], g_rho))])
+    assert np.abs(g_fd - ref).max() <= 1e-6 * np.abs(ref).max()
+    # at xi0 = 0 the xi-space derivative is the analytic gradient itself
+    assert np.abs(vol.grad_xi_fd(X, R, t, np.zeros(6), mode) - vol.fitness_grad(X, R, t, mode)[1]).max() \
+        <= 1e-6 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_grad_interval_contains_exact(orc, mode):
+    d = synth.cfg1_inputs()
+    vol = orc.Volume(d["vol"])
+    vol.integrate(d["depth1"], d["intr"], np.eye(3), np.zeros(3))
+    X, _ = orc.backproject(d["depth2"], d["intr"], 2)
+    rng = np.random.default_rng(8)
+    R0, t0 = d["init2"]
+    poses = [orc.compose(rng.uniform(-0.05, 0.05, 3), rng.uniform(-0.02, 0.02, 3), R0, t0) for _ in range(12)]
+    E, g, nv = vol.fitness_grad_many(X, poses, mode)
+    lo, hi = vol.fitness_grad_interval_many(X, poses, mode, eps=1e-3)
+    exact = np.concatenate([E[:, None], g], 1)
+    assert np.all(lo <= exact + 1e-15) and np.all(exact <= hi + 1e-15)
+    lo0, hi0 = vol.fitness_grad_interval_many(X, poses, mode, eps=0.0)
+    assert np.abs(lo0 - exact).max() <= 1e-15 * np.abs(exact).max() * 10 and np.abs(hi0 - exact).max() <= 1e-13

@@ -279,6 +279,52 @@ int32_t track_frame(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
                     const pf_pose* init, const pf_track_params* p, pf_pose* out,
                     pf_track_stats* stats, void* workspace, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------------ batches */
+
+/* Many independent tracking problems run together: every step of the frame optimization is one
+ * launch over all problems (the scoring launch is persistent: a fixed grid walks the list of
+ * (problem, pose group) items), so the whole batch is a short fixed sequence of kernels that a
+ * HIP graph can capture once and replay. Each problem computes bit for bit what track_frame
+ * computes for it alone (the per-pose reduction order does not depend on the batching); this
+ * needs K >= 64 (track_frame scores up to 64 poses with wider workgroups), which is enforced. */
+typedef struct pf_batch_problem {
+    pf_tsdf vol;             /* the problem's volume (all problems share format and layout) */
+    const float* depth;      /* device, float32 [height][width] */
+    pf_intrinsics K;
+    pf_pose init;            /* P^(0) */
+    pf_track_params params;  /* n_iters, n_rates equal across the batch; polish_steps must be 0 */
+} pf_batch_problem;
+
+/* Launch plan of a batch (the project autotuner chooses it per shape class). */
+typedef struct pf_batch_plan {
+    int32_t score_tk;        /* poses per scoring workgroup: 1, 2, 4 or 8 */
+    int32_t score_grid;      /* workgroups of the persistent scoring launch, >= 1 */
+    int32_t order;           /* 0: items in problem order; 1: problems with most points first */
+    int32_t reserved;        /* must be 0 */
+} pf_batch_plan;
+
+typedef struct pf_batch pf_batch; /* opaque host-side record of a prepared batch */
+
+/* Workspace bytes for a batch of n problems (host array). */
+size_t track_batch_workspace_bytes(const pf_batch_problem* problems, int32_t n);
+
+/* Validates the problems (host array), lays them out in `workspace` (device) and uploads the
+ * problem table and item lists; synchronises `stream`. Returns NULL on error (pf_last_error).
+ * The returned record is host memory owned by the caller via track_batch_destroy. */
+pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const pf_batch_plan* plan,
+                             void* workspace, size_t ws_bytes, void* stream);
+
+/* Enqueues the whole batch (back-projection, views, every iteration, final fitness) on
+ * `stream`. Kernel launches only: no host synchronisation, copy or allocation, so it can be
+ * captured into a HIP graph and replayed; the depth and volume contents are read at run time. */
+int32_t track_batch_run(pf_batch* b, void* stream);
+
+/* Synchronises `stream` and copies each problem's pose (out[n], host) and record (stats[n], host,
+ * nullable) back. */
+int32_t track_batch_results(pf_batch* b, pf_pose* out, pf_track_stats* stats, void* stream);
+
+void track_batch_destroy(pf_batch* b);
+
 /* ------------------------------------------------------------------------------ timing */
 
 /* Kernel timing of the particle-scoring launches made by track_frame: when enabled, each such

@@ -73,10 +73,20 @@ class pf_track_state(C.Structure):
                 ("n_sub", C.c_int32), ("n_valid_star", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32)]
 
 
+class pf_batch_problem(C.Structure):
+    _fields_ = [("vol", pf_tsdf), ("depth", C.c_void_p), ("K", pf_intrinsics), ("init", pf_pose),
+                ("params", pf_track_params)]
+
+
+class pf_batch_plan(C.Structure):
+    _fields_ = [("score_tk", C.c_int32), ("score_grid", C.c_int32), ("order", C.c_int32), ("reserved", C.c_int32)]
+
+
 # every symbol include/profusion.h declares
 EXPORTS = ("pf_last_error", "tsdf_bytes", "tsdf_cells_offset", "tsdf_init", "tsdf_integrate", "tsdf_export_linear", "tsdf_import_linear",
            "backproject", "particles_score", "particles_score_grad", "particles_state_bytes", "particles_state_init", "particles_update",
-           "track_workspace_bytes", "track_frame", "pf_timing_enable", "pf_timing_read")
+           "track_workspace_bytes", "track_frame", "track_batch_workspace_bytes", "track_batch_create",
+           "track_batch_run", "track_batch_results", "track_batch_destroy", "pf_timing_enable", "pf_timing_read")
 
 _lib = None
 
@@ -112,10 +122,18 @@ def lib() -> C.CDLL:
     L.track_workspace_bytes.argtypes = [P(pf_intrinsics), P(pf_track_params)]
     L.track_frame.argtypes = [P(pf_tsdf), vp, P(pf_intrinsics), P(pf_pose), P(pf_track_params), P(pf_pose),
                               P(pf_track_stats), vp, C.c_size_t, vp]
+    L.track_batch_workspace_bytes.restype = C.c_size_t
+    L.track_batch_workspace_bytes.argtypes = [P(pf_batch_problem), i32]
+    L.track_batch_create.restype = vp
+    L.track_batch_create.argtypes = [P(pf_batch_problem), i32, P(pf_batch_plan), vp, C.c_size_t, vp]
+    L.track_batch_run.argtypes = [vp, vp]
+    L.track_batch_results.argtypes = [vp, P(pf_pose), P(pf_track_stats), vp]
+    L.track_batch_destroy.restype = None
+    L.track_batch_destroy.argtypes = [vp]
     L.pf_timing_enable.argtypes = [i32]
     L.pf_timing_read.argtypes = [P(C.c_double), P(C.c_int64), P(C.c_int64), i32]
     for name in EXPORTS:
-        if name != "pf_last_error" and getattr(L, name).restype is None:
+        if name not in ("pf_last_error", "track_batch_destroy") and getattr(L, name).restype is None:
             getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -410,3 +428,65 @@ def timing_read(reset: bool = False):
     ms, nl, ne = C.c_double(), C.c_int64(), C.c_int64()
     _check(lib().pf_timing_read(C.byref(ms), C.byref(nl), C.byref(ne), 1 if reset else 0))
     return ms.value, nl.value, ne.value
+
+
+# ----------------------------------------------------------------------------- batches
+@dataclasses.dataclass
+class BatchPlan:
+    score_tk: int = 4
+    score_grid: int = 1024
+    order: int = 1
+
+    def c(self) -> pf_batch_plan:
+        return pf_batch_plan(self.score_tk, self.score_grid, self.order, 0)
+
+
+class Batch:
+    """Many tracking problems run as one fixed kernel sequence (track_batch_*).
+
+    problems: list of (Tsdf, depth tensor, intrinsics, R0, t0, TrackParams)."""
+
+    def __init__(self, problems, plan: Optional[BatchPlan] = None, device="cuda", stream=None):
+        torch = _torch()
+        self.plan = plan or BatchPlan()
+        n = len(problems)
+        arr = (pf_batch_problem * n)()
+        self._keep = []
+        for i, (vol, depth, intr, R0, t0, prm) in enumerate(problems):
+            arr[i].vol = vol.desc
+            arr[i].depth = _ptr(depth).value
+            arr[i].K = make_intrinsics(intr)
+            arr[i].init = make_pose(R0, t0)
+            arr[i].params = prm.c()
+            self._keep.append((vol, depth))
+        self._arr, self.n = arr, n
+        self.ws_bytes = int(lib().track_batch_workspace_bytes(arr, n))
+        if self.ws_bytes == 0:
+            raise PFError(PF_EINVAL, last_error())
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        h = lib().track_batch_create(arr, n, C.byref(self.plan.c()), _ptr(self.ws), C.c_size_t(self.ws_bytes),
+                                     _stream(stream))
+        if not h:
+            raise PFError(PF_EINVAL, last_error())
+        self._h = C.c_void_p(h)
+
+    def run(self, stream=None):
+        """Enqueues the whole batch (kernels only; capturable into a HIP graph)."""
+        _check(lib().track_batch_run(self._h, _stream(stream)))
+
+    def results(self, stream=None):
+        out = (pf_pose * self.n)()
+        st = (pf_track_stats * self.n)()
+        _check(lib().track_batch_results(self._h, out, st, _stream(stream)))
+        return [(*pose_rt(out[i]), st[i]) for i in range(self.n)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().track_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

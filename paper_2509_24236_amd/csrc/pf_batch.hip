@@ -1,0 +1,461 @@
+// Batched tracking of many independent problems (frames or sequences with their own volumes,
+// resolutions and particle counts). Every step of the frame optimization is one launch over all
+// problems; the scoring launch is persistent (a fixed grid strides over the list of (problem,
+// pose group) items, longest problems first). The step bodies are the same device functions the
+// single-problem kernels run, so each problem reproduces track_frame bit for bit. The host
+// record holds the grid sizes, which makes track_batch_run a fixed kernel sequence: no host
+// synchronisation, copy or allocation, and therefore capturable into a HIP graph.
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "pf_steps.hpp"
+
+namespace pf {
+
+size_t state_bytes(int K);
+pf_track_state initial_state(const pf_pose* init, const pf_track_params* p);
+int32_t check_problem(const pf_batch_problem& q, int idx);
+
+struct BatchProb {
+    VolView vv;
+    BpArgs bp;
+    int bp_blocks;
+    int K;
+    float* px;
+    float* py;
+    float* pz;
+    int* counts;
+    int* ncount;            // [0] = |M|, [1 + r] = |S_r|
+    float* vx[3];
+    float* vy[3];
+    float* vz[3];
+    int caps[3];
+    int rates[3];
+    int G[3];               // E* partial workgroups per rate
+    int densest;
+    float* poses;
+    float* fit;
+    int* nv;
+    pf_track_state* st;
+    IterRec* recs;
+    float* efin;
+    int* nfin;
+};
+
+namespace {
+
+__device__ inline void view_of(const BatchProb& P, int r, const float*& x, const float*& y, const float*& z,
+                               const int*& nd) {
+    if (P.rates[r] == 1) {
+        x = P.px;
+        y = P.py;
+        z = P.pz;
+        nd = P.ncount;
+    } else {
+        x = P.vx[r];
+        y = P.vy[r];
+        z = P.vz[r];
+        nd = P.ncount + 1 + r;
+    }
+}
+
+__global__ __launch_bounds__(kBpThreads) void kb_bp_count(const BatchProb* tab, const int4* items) {
+    const int4 w = items[blockIdx.x];
+    bp_count_step(tab[w.x].bp, tab[w.x].counts, w.y);
+}
+
+__global__ __launch_bounds__(kBpThreads) void kb_bp_scatter(const BatchProb* tab, const int4* items) {
+    const int4 w = items[blockIdx.x];
+    const BatchProb& P = tab[w.x];
+    bp_scatter_step(P.bp, P.counts, P.bp_blocks, P.px, P.py, P.pz, P.ncount, w.y);
+}
+
+__global__ __launch_bounds__(256) void kb_view(const BatchProb* tab, const int4* items) {
+    const int4 w = items[blockIdx.x];
+    const BatchProb& P = tab[w.x];
+    const int r = w.y;
+    view_step(P.px, P.py, P.pz, P.ncount, P.rates[r], P.caps[r], P.vx[r], P.vy[r], P.vz[r], P.ncount + 1 + r, w.z);
+}
+
+__global__ void kb_state_set(const BatchProb* tab, const pf_track_state* init, int n) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) *tab[p].st = init[p];
+}
+
+template <int FMT, bool FIRST>
+__global__ __launch_bounds__(256) void kb_next(const BatchProb* tab, const int4* items, int phase, int draw) {
+    const int4 w = items[blockIdx.x];
+    const BatchProb& P = tab[w.x];
+    next_step<FMT, FIRST>(P.st, P.K, P.G[phase], draw, P.poses, P.recs, w.y);
+}
+
+template <int FMT, int LAYOUT, int TK>
+__global__ __launch_bounds__(256) void kb_score(const BatchProb* tab, const int4* items, int n_items, int phase) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 w = items[it];
+        const BatchProb& P = tab[w.x];
+        const float *x, *y, *z;
+        const int* nd;
+        view_of(P, phase, x, y, z, nd);
+        score_step<FMT, LAYOUT, TK, 256>(P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv);
+    }
+}
+
+template <int FMT, int LAYOUT, bool ADV>
+__global__ __launch_bounds__(256) void kb_adv(const BatchProb* tab, const int4* items, int phase) {
+    const int4 w = items[blockIdx.x];
+    const BatchProb& P = tab[w.x];
+    const float *x, *y, *z;
+    const int* nd;
+    view_of(P, ADV ? phase : P.densest, x, y, z, nd);
+    adv_step<FMT, LAYOUT, ADV>(P.vv, x, y, z, 0, nd, P.fit, P.st, P.K, w.y, w.z);
+}
+
+template <int FMT>
+__global__ void kb_final(const BatchProb* tab, int n) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const BatchProb& P = tab[p];
+    const Partial* pt = state_partials(P.st, P.K);
+    float sum = 0.0f;
+    int cnt = 0;
+    for (int b = 0; b < P.G[P.densest]; ++b) {
+        sum += pt[b].sum;
+        cnt += pt[b].cnt;
+    }
+    *P.efin = cnt > 0 ? (sum * Fmt<FMT>::scale) / (float)cnt : 1.0f;
+    *P.nfin = cnt;
+}
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct ProbLayout {
+    size_t pts, counts, ncount, views[3], poses, fit, nv, state, recs, fin, end;
+};
+
+ProbLayout prob_layout(const pf_batch_problem& q, size_t off) {
+    ProbLayout L;
+    const size_t npix = (size_t)q.K.width * q.K.height;
+    const pf_track_params& p = q.params;
+    L.pts = off;
+    off += al(3 * npix * sizeof(float));
+    L.counts = off;
+    off += al(((npix + kBpChunk - 1) / kBpChunk + 1) * sizeof(int));
+    L.ncount = off;
+    off += al(8 * sizeof(int));
+    for (int r = 0; r < 3; ++r) {
+        L.views[r] = off;
+        if (r < p.n_rates && p.rates[r] > 1) off += al(3 * ((npix + p.rates[r] - 1) / p.rates[r]) * sizeof(float));
+    }
+    L.poses = off;
+    off += al((size_t)(p.K + 1) * 12 * sizeof(float));
+    L.fit = off;
+    off += al((size_t)(p.K + 1) * sizeof(float));
+    L.nv = off;
+    off += al((size_t)(p.K + 1) * sizeof(int));
+    L.state = off;
+    off += al(state_bytes(p.K));
+    L.recs = off;
+    off += al(PF_MAX_ITERS * sizeof(IterRec));
+    L.fin = off;
+    off += al(2 * sizeof(int));
+    L.end = off;
+    return L;
+}
+
+}  // namespace
+}  // namespace pf
+
+using namespace pf;
+
+struct pf_batch {
+    int n = 0, n_iters = 0, n_rates = 0, format = 0, layout = 0;
+    pf_batch_plan plan{};
+    char* ws = nullptr;
+    BatchProb* tab = nullptr;
+    pf_track_state* init = nullptr;
+    int4* items = nullptr;                  // all lists, back to back
+    size_t off_bp = 0, off_view = 0, off_next = 0, off_score = 0, off_fin = 0, off_adv[3] = {0, 0, 0};
+    int n_bp = 0, n_view = 0, n_next = 0, n_score = 0, n_fin = 0, n_adv[3] = {0, 0, 0};
+    std::vector<BatchProb> host;
+    std::vector<int> min_valid;
+};
+
+namespace {
+
+size_t table_bytes(int n) { return al(sizeof(BatchProb) * n) + al(sizeof(pf_track_state) * n); }
+
+template <int FMT, int LAYOUT, int TK>
+void launch_score_batch(pf_batch* b, int phase, hipStream_t s) {
+    const int grid = std::min(b->plan.score_grid, b->n_score);
+    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, TK>), dim3(grid), dim3(256), 0, s, b->tab, b->items + b->off_score,
+                       b->n_score, phase);
+}
+
+template <int FMT, int LAYOUT>
+int32_t run_t(pf_batch* b, hipStream_t s) {
+    hipLaunchKernelGGL(kb_bp_count, dim3(b->n_bp), dim3(kBpThreads), 0, s, b->tab, b->items + b->off_bp);
+    hipLaunchKernelGGL(kb_bp_scatter, dim3(b->n_bp), dim3(kBpThreads), 0, s, b->tab, b->items + b->off_bp);
+    if (b->n_view) hipLaunchKernelGGL(kb_view, dim3(b->n_view), dim3(256), 0, s, b->tab, b->items + b->off_view);
+    hipLaunchKernelGGL(kb_state_set, dim3((b->n + 63) / 64), dim3(64), 0, s, b->tab, b->init, b->n);
+    hipLaunchKernelGGL((kb_next<FMT, true>), dim3(b->n_next), dim3(256), 0, s, b->tab, b->items + b->off_next, 0, 1);
+    for (int i = 1; i <= b->n_iters; ++i) {
+        const int ph = (i - 1) % b->n_rates;
+        switch (b->plan.score_tk) {
+            case 1: launch_score_batch<FMT, LAYOUT, 1>(b, ph, s); break;
+            case 2: launch_score_batch<FMT, LAYOUT, 2>(b, ph, s); break;
+            case 8: launch_score_batch<FMT, LAYOUT, 8>(b, ph, s); break;
+            default: launch_score_batch<FMT, LAYOUT, 4>(b, ph, s); break;
+        }
+        hipLaunchKernelGGL((kb_adv<FMT, LAYOUT, true>), dim3(b->n_adv[ph]), dim3(256), 0, s, b->tab,
+                           b->items + b->off_adv[ph], ph);
+        hipLaunchKernelGGL((kb_next<FMT, false>), dim3(b->n_next), dim3(256), 0, s, b->tab, b->items + b->off_next,
+                           ph, i < b->n_iters ? 1 : 0);
+    }
+    hipLaunchKernelGGL((kb_adv<FMT, LAYOUT, false>), dim3(b->n_fin), dim3(256), 0, s, b->tab, b->items + b->off_fin,
+                       0);
+    hipLaunchKernelGGL(kb_final<FMT>, dim3((b->n + 63) / 64), dim3(64), 0, s, b->tab, b->n);
+    return check_launch("track_batch_run");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t track_batch_workspace_bytes(const pf_batch_problem* problems, int32_t n) {
+    if (!problems || n < 1) return 0;
+    size_t off = table_bytes(n);
+    for (int p = 0; p < n; ++p) {
+        if (check_problem(problems[p], p)) return 0;
+        off = prob_layout(problems[p], off).end;
+    }
+    size_t items = 0;
+    for (int p = 0; p < n; ++p) {
+        const pf_batch_problem& q = problems[p];
+        const size_t npix = (size_t)q.K.width * q.K.height;
+        items += 2 * ((npix + kBpChunk - 1) / kBpChunk);
+        for (int r = 0; r < q.params.n_rates; ++r)
+            items += (npix / q.params.rates[r] + 256) / 256 + (size_t)kMaxPartials;
+        items += 2 * ((size_t)q.params.K + 256) / 256 + (size_t)q.params.K + 1 + kMaxPartials;
+    }
+    return off + al(items * sizeof(int4));
+}
+
+pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const pf_batch_plan* plan, void* workspace,
+                             size_t ws_bytes, void* stream) {
+    if (!problems || n < 1 || !plan || !workspace) {
+        set_error(PF_EINVAL, "track_batch_create: null argument or n < 1");
+        return nullptr;
+    }
+    if (plan->score_tk != 1 && plan->score_tk != 2 && plan->score_tk != 4 && plan->score_tk != 8) {
+        set_error(PF_EINVAL, "track_batch_create: score_tk %d not in {1, 2, 4, 8}", plan->score_tk);
+        return nullptr;
+    }
+    if (plan->score_grid < 1 || plan->reserved != 0 || (plan->order != 0 && plan->order != 1)) {
+        set_error(PF_EINVAL, "track_batch_create: bad plan (grid %d, order %d)", plan->score_grid, plan->order);
+        return nullptr;
+    }
+    for (int p = 0; p < n; ++p)
+        if (check_problem(problems[p], p)) return nullptr;
+    const pf_batch_problem& q0 = problems[0];
+    for (int p = 1; p < n; ++p) {
+        const pf_batch_problem& q = problems[p];
+        if (q.params.n_iters != q0.params.n_iters || q.params.n_rates != q0.params.n_rates ||
+            q.vol.format != q0.vol.format || q.vol.layout != q0.vol.layout) {
+            set_error(PF_EINVAL, "track_batch_create: problem %d differs from problem 0 in n_iters, n_rates, format "
+                                 "or layout", p);
+            return nullptr;
+        }
+    }
+    const size_t need = track_batch_workspace_bytes(problems, n);
+    if (ws_bytes < need) {
+        set_error(PF_ENOMEM, "track_batch_create: workspace of %zu bytes, %zu needed", ws_bytes, need);
+        return nullptr;
+    }
+    pf_batch* b = new (std::nothrow) pf_batch();
+    if (!b) {
+        set_error(PF_ENOMEM, "track_batch_create: host allocation failed");
+        return nullptr;
+    }
+    b->n = n;
+    b->n_iters = q0.params.n_iters;
+    b->n_rates = q0.params.n_rates;
+    b->format = q0.vol.format;
+    b->layout = q0.vol.layout;
+    b->plan = *plan;
+    b->ws = static_cast<char*>(workspace);
+    b->tab = reinterpret_cast<BatchProb*>(b->ws);
+    b->init = reinterpret_cast<pf_track_state*>(b->ws + al(sizeof(BatchProb) * n));
+    std::vector<pf_track_state> init(n);
+    size_t off = table_bytes(n);
+    b->host.resize(n);
+    for (int p = 0; p < n; ++p) {
+        const pf_batch_problem& q = problems[p];
+        const ProbLayout L = prob_layout(q, off);
+        off = L.end;
+        BatchProb& P = b->host[p];
+        memset(&P, 0, sizeof P);
+        P.vv = make_view(&q.vol);
+        const size_t npix = (size_t)q.K.width * q.K.height;
+        P.bp.depth = q.depth;
+        P.bp.width = q.K.width;
+        P.bp.height = q.K.height;
+        P.bp.stride = q.params.pixel_stride;
+        P.bp.fx = (float)q.K.fx;
+        P.bp.fy = (float)q.K.fy;
+        P.bp.cx = (float)q.K.cx;
+        P.bp.cy = (float)q.K.cy;
+        P.bp_blocks = (int)((npix + kBpChunk - 1) / kBpChunk);
+        P.K = q.params.K;
+        P.px = reinterpret_cast<float*>(b->ws + L.pts);
+        P.py = P.px + npix;
+        P.pz = P.py + npix;
+        P.counts = reinterpret_cast<int*>(b->ws + L.counts);
+        P.ncount = reinterpret_cast<int*>(b->ws + L.ncount);
+        P.densest = 0;
+        for (int r = 0; r < 3; ++r) {
+            const int rate = r < q.params.n_rates ? q.params.rates[r] : 1;
+            P.rates[r] = rate;
+            P.caps[r] = (int)((npix + rate - 1) / rate);
+            P.G[r] = n_partials_for(P.caps[r]);
+            P.vx[r] = reinterpret_cast<float*>(b->ws + L.views[r]);
+            P.vy[r] = P.vx[r] + P.caps[r];
+            P.vz[r] = P.vy[r] + P.caps[r];
+            if (r < q.params.n_rates && rate < P.rates[P.densest]) P.densest = r;
+        }
+        P.poses = reinterpret_cast<float*>(b->ws + L.poses);
+        P.fit = reinterpret_cast<float*>(b->ws + L.fit);
+        P.nv = reinterpret_cast<int*>(b->ws + L.nv);
+        P.st = reinterpret_cast<pf_track_state*>(b->ws + L.state);
+        P.recs = reinterpret_cast<IterRec*>(b->ws + L.recs);
+        P.efin = reinterpret_cast<float*>(b->ws + L.fin);
+        P.nfin = reinterpret_cast<int*>(b->ws + L.fin + sizeof(float));
+        init[p] = initial_state(&q.init, &q.params);
+        b->min_valid.push_back(q.params.min_valid);
+    }
+    // item lists
+    std::vector<int> order(n);
+    for (int p = 0; p < n; ++p) order[p] = p;
+    if (plan->order == 1)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+            const size_t na = (size_t)problems[a].K.width * problems[a].K.height * (problems[a].params.K + 1);
+            const size_t nc = (size_t)problems[c].K.width * problems[c].K.height * (problems[c].params.K + 1);
+            return na > nc;
+        });
+    std::vector<int4> items;
+    auto mark = [&](size_t& o) { o = items.size(); };
+    mark(b->off_bp);
+    for (int p = 0; p < n; ++p)
+        for (int k = 0; k < b->host[p].bp_blocks; ++k) items.push_back(make_int4(p, k, 0, 0));
+    b->n_bp = (int)(items.size() - b->off_bp);
+    mark(b->off_view);
+    for (int p = 0; p < n; ++p)
+        for (int r = 0; r < b->n_rates; ++r)
+            if (b->host[p].rates[r] > 1)
+                for (int k = 0; k < (b->host[p].caps[r] + 255) / 256; ++k) items.push_back(make_int4(p, r, k, 0));
+    b->n_view = (int)(items.size() - b->off_view);
+    mark(b->off_next);
+    for (int p = 0; p < n; ++p)
+        for (int k = 0; k < (b->host[p].K + 1 + 255) / 256; ++k) items.push_back(make_int4(p, k, 0, 0));
+    b->n_next = (int)(items.size() - b->off_next);
+    mark(b->off_score);
+    const int tk = plan->score_tk;
+    for (int p : order)
+        for (int g = 0; g < (b->host[p].K + 1 + tk - 1) / tk; ++g) items.push_back(make_int4(p, g, 0, 0));
+    b->n_score = (int)(items.size() - b->off_score);
+    for (int ph = 0; ph < b->n_rates; ++ph) {
+        mark(b->off_adv[ph]);
+        for (int p = 0; p < n; ++p)
+            for (int k = 0; k < b->host[p].G[ph]; ++k) items.push_back(make_int4(p, k, b->host[p].G[ph], 0));
+        b->n_adv[ph] = (int)(items.size() - b->off_adv[ph]);
+    }
+    mark(b->off_fin);
+    for (int p = 0; p < n; ++p) {
+        const int G = b->host[p].G[b->host[p].densest];
+        for (int k = 0; k < G; ++k) items.push_back(make_int4(p, k, G, 0));
+    }
+    b->n_fin = (int)(items.size() - b->off_fin);
+    b->items = reinterpret_cast<int4*>(b->ws + off);
+    if (off + items.size() * sizeof(int4) > ws_bytes) {
+        delete b;
+        set_error(PF_ENOMEM, "track_batch_create: item lists exceed the workspace");
+        return nullptr;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(b->tab, b->host.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b->init, init.data(), sizeof(pf_track_state) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b->items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        delete b;
+        set_error(PF_EHIP, "track_batch_create: upload failed: %s", hipGetErrorString(hipGetLastError()));
+        return nullptr;
+    }
+    return b;
+}
+
+int32_t track_batch_run(pf_batch* b, void* stream) {
+    if (!b) return set_error(PF_EINVAL, "track_batch_run: null batch");
+    hipStream_t s = (hipStream_t)stream;
+    const bool cells = b->layout == PF_LAYOUT_CELLS;
+    switch (b->format) {
+        case PF_F32_W_F32: return cells ? run_t<PF_F32_W_F32, PF_LAYOUT_CELLS>(b, s) : run_t<PF_F32_W_F32, PF_LAYOUT_LINEAR>(b, s);
+        case PF_F16_W_U8: return cells ? run_t<PF_F16_W_U8, PF_LAYOUT_CELLS>(b, s) : run_t<PF_F16_W_U8, PF_LAYOUT_LINEAR>(b, s);
+        case PF_I16_W_U8: return cells ? run_t<PF_I16_W_U8, PF_LAYOUT_CELLS>(b, s) : run_t<PF_I16_W_U8, PF_LAYOUT_LINEAR>(b, s);
+        default: return set_error(PF_EUNSUPPORTED, "track_batch_run: unsupported format %d", b->format);
+    }
+}
+
+int32_t track_batch_results(pf_batch* b, pf_pose* out, pf_track_stats* stats, void* stream) {
+    if (!b || !out) return set_error(PF_EINVAL, "track_batch_results: null argument");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = b->n;
+    std::vector<pf_track_state> st(n);
+    std::vector<IterRec> recs((size_t)n * PF_MAX_ITERS);
+    std::vector<float> ef(n);
+    std::vector<int> nf(n), na(n);
+    for (int p = 0; p < n; ++p) {
+        const BatchProb& P = b->host[p];
+        if (hipMemcpyAsync(&st[p], P.st, sizeof(pf_track_state), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&recs[(size_t)p * PF_MAX_ITERS], P.recs, sizeof(IterRec) * b->n_iters, hipMemcpyDeviceToHost,
+                           s) != hipSuccess ||
+            hipMemcpyAsync(&ef[p], P.efin, sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&nf[p], P.nfin, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&na[p], P.ncount, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return set_error(PF_EHIP, "track_batch_results: read-back failed");
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_error(PF_EHIP, "track_batch_results: %s", hipGetErrorString(e));
+    for (int p = 0; p < n; ++p) {
+        if (st[p].flags) return set_error(PF_EINVAL, "track_batch_results: problem %d state flags %d", p, st[p].flags);
+        for (int q = 0; q < 9; ++q) out[p].R[q] = st[p].R[q];
+        for (int q = 0; q < 3; ++q) out[p].t[q] = st[p].t[q];
+        if (stats) {
+            pf_track_stats& S = stats[p];
+            memset(&S, 0, sizeof S);
+            S.n_points = na[p];
+            S.n_iters = b->n_iters;
+            for (int i = 0; i < b->n_iters; ++i) {
+                const IterRec& r = recs[(size_t)p * PF_MAX_ITERS + i];
+                S.E0[i] = r.E0;
+                S.Estar[i] = r.Estar;
+                S.n_adv[i] = r.n_adv;
+                S.n_sub[i] = r.n_sub;
+                S.n_valid[i] = r.n_valid;
+                S.s_rad[i] = r.s_rad;
+                S.s_m[i] = r.s_m;
+            }
+            S.E_final = ef[p];
+            S.n_valid_final = nf[p];
+            S.lost = nf[p] < b->min_valid[p] ? 1 : 0;
+        }
+    }
+    return PF_OK;
+}
+
+void track_batch_destroy(pf_batch* b) { delete b; }
+
+}  // extern "C"

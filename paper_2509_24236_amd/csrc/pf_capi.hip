@@ -140,6 +140,21 @@ int32_t check_params(const pf_track_params* p, const char* fn) {
 }
 
 }  // namespace
+
+int32_t check_problem(const pf_batch_problem& q, int idx) {
+    char fn[64];
+    snprintf(fn, sizeof fn, "track_batch problem %d", idx);
+    int32_t rc;
+    if ((rc = check_tsdf(&q.vol, fn, false))) return rc;
+    if ((rc = check_intr(&q.K, fn))) return rc;
+    if ((rc = check_pose(&q.init, fn))) return rc;
+    if ((rc = check_params(&q.params, fn))) return rc;
+    if (!q.depth) return set_error(PF_EINVAL, "%s: null depth", fn);
+    if (q.params.polish_steps != 0) return set_error(PF_EUNSUPPORTED, "%s: polish is not batched", fn);
+    if (q.params.K < 64) return set_error(PF_EINVAL, "%s: K %d < 64", fn, q.params.K);
+    return PF_OK;
+}
+
 }  // namespace pf
 
 using namespace pf;

@@ -16,7 +16,7 @@
 // contraction, so it runs on the vector ALUs, not on the matrix cores.
 #include <math.h>
 
-#include "pf_sample.hpp"
+#include "pf_steps.hpp"
 
 namespace pf {
 namespace {
@@ -26,33 +26,8 @@ __global__ __launch_bounds__(BLOCK) void k_score(VolView vv, const float* __rest
                                                  const float* __restrict__ pz, int n_host, const int* __restrict__ n_dev,
                                                  const float* __restrict__ poses, int K, float* __restrict__ fitness,
                                                  int* __restrict__ n_valid) {
-    const Gather<FMT, LAYOUT> G = make_gather<FMT, LAYOUT>(vv);
-    const int k0 = blockIdx.x * TK;
-    // poses in grid units, uniform across the workgroup (scalar registers)
-    GridPose g[TK];
-#pragma unroll
-    for (int j = 0; j < TK; ++j)
-        g[j] = fold_pose(poses + (size_t)min(k0 + j, K - 1) * 12, vv.inv_vs, vv.gx0, vv.gy0, vv.gz0);
-    const int n = n_dev ? *n_dev : n_host;
-    const unsigned lx = (unsigned)(vv.nx - 1), ly = (unsigned)(vv.ny - 1), lz = (unsigned)(vv.nz - 1);
-    float sum[TK];
-    int cnt[TK];
-#pragma unroll
-    for (int j = 0; j < TK; ++j) {
-        sum[j] = 0.0f;
-        cnt[j] = 0;
-    }
-    const float s = vv.inv_vs;
-    for (int q = threadIdx.x; q < n; q += BLOCK)
-        eval_poses<FMT, LAYOUT, TK>(G, lx, ly, lz, g, px[q] * s, py[q] * s, pz[q] * s, sum, cnt);
-    block_reduce<TK, BLOCK>(sum, cnt);
-    if (threadIdx.x < TK) {
-        const int k = k0 + threadIdx.x;
-        if (k < K) {
-            fitness[k] = cnt[0] > 0 ? (sum[0] * Fmt<FMT>::scale) / (float)cnt[0] : 1.0f;
-            n_valid[k] = cnt[0];
-        }
-    }
+    score_step<FMT, LAYOUT, TK, BLOCK>(vv, px, py, pz, n_dev ? *n_dev : n_host, poses, K, blockIdx.x * TK, fitness,
+                                       n_valid);
 }
 
 template <int FMT, int LAYOUT, int TK, int BLOCK>

@@ -1,0 +1,399 @@
+// Step bodies of the per-frame optimization as device functions taking an explicit workgroup
+// index: the single-problem kernels and the batched persistent kernels call the same code, so a
+// batched problem computes bit for bit what the plain path computes.
+#pragma once
+
+#include <math.h>
+
+#include "pf_sample.hpp"
+
+namespace pf {
+
+constexpr int kBpThreads = 256;
+constexpr int kBpPerThread = 4;
+constexpr int kBpChunk = kBpThreads * kBpPerThread;  // pixels per workgroup, in raster order
+
+struct BpArgs {
+    const float* depth;
+    int width, height, stride;
+    float fx, fy, cx, cy;
+};
+
+__device__ inline bool bp_valid(const BpArgs& a, int pix, float& z) {
+    const int n = a.width * a.height;
+    if (pix >= n) return false;
+    const int v = pix / a.width, u = pix - v * a.width;
+    if ((u % a.stride) != 0 || (v % a.stride) != 0) return false;
+    z = a.depth[pix];
+    return isfinite(z) && z > 0.0f;
+}
+
+__device__ inline void bp_count_step(const BpArgs& a, int* counts, int blk) {
+    const int base = blk * kBpChunk + threadIdx.x * kBpPerThread;
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < kBpPerThread; ++q) {
+        float z;
+        c += bp_valid(a, base + q, z) ? 1 : 0;
+    }
+    __shared__ int red[kBpThreads / kWave];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < kBpThreads / kWave; ++w) s += red[w];
+        counts[blk] = s;
+    }
+    __syncthreads();
+}
+
+// Each workgroup sums the counts of the workgroups before it (a few hundred integers), scans
+// its own pixels and writes them in raster order; workgroup 0 also writes the total.
+__device__ inline void bp_scatter_step(const BpArgs& a, const int* counts, int nblocks, float* px, float* py,
+                                       float* pz, int* n_out, int blk) {
+    __shared__ int red[kBpThreads / kWave];
+    __shared__ int wsum[kBpThreads / kWave];
+    __shared__ int base_sh, total_sh;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    int before = 0, all = 0;
+    for (int b = threadIdx.x; b < nblocks; b += kBpThreads) {
+        const int c = counts[b];
+        all += c;
+        if (b < blk) before += c;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        before += __shfl_xor(before, off);
+        all += __shfl_xor(all, off);
+    }
+    if (lane == 0) {
+        red[wid] = before;
+        wsum[wid] = all;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0, t = 0;
+        for (int w = 0; w < kBpThreads / kWave; ++w) {
+            s += red[w];
+            t += wsum[w];
+        }
+        base_sh = s;
+        total_sh = t;
+        if (blk == 0) *n_out = t;
+    }
+    __syncthreads();
+    // in-workgroup exclusive scan of the per-thread counts (thread order = raster order)
+    const int pbase = blk * kBpChunk + threadIdx.x * kBpPerThread;
+    float zs[kBpPerThread];
+    bool ok[kBpPerThread];
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < kBpPerThread; ++q) {
+        ok[q] = bp_valid(a, pbase + q, zs[q]);
+        c += ok[q] ? 1 : 0;
+    }
+    int incl = c;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    __shared__ int wtot[kBpThreads / kWave];
+    if (lane == kWave - 1) wtot[wid] = incl;
+    __syncthreads();
+    int woff = 0;
+    for (int w = 0; w < wid; ++w) woff += wtot[w];
+    int pos = base_sh + woff + incl - c;
+#pragma unroll
+    for (int q = 0; q < kBpPerThread; ++q) {
+        if (ok[q]) {
+            const int pix = pbase + q;
+            const int v = pix / a.width, u = pix - v * a.width;
+            const float z = zs[q];
+            px[pos] = ((float)u - a.cx) * z / a.fx;
+            py[pos] = ((float)v - a.cy) * z / a.fy;
+            pz[pos] = z;
+            ++pos;
+        }
+    }
+    __syncthreads();
+}
+
+// S_r[j] = M[j r] for j < ceil(n / r), copied contiguously; the count goes to *n_view.
+__device__ inline void view_step(const float* px, const float* py, const float* pz, const int* n_all, int r, int cap,
+                                 float* vx, float* vy, float* vz, int* n_view, int blk) {
+    const int n = *n_all;
+    const int m = (n + r - 1) / r;
+    const int j = blk * 256 + threadIdx.x;
+    if (j == 0) *n_view = m;
+    if (j < m && j < cap) {
+        vx[j] = px[j * r];
+        vy[j] = py[j * r];
+        vz[j] = pz[j * r];
+    }
+}
+
+// ------------------------------------------------------------------ optimizer state
+struct IterRec {
+    float E0, Estar;
+    int n_adv, n_sub, n_valid, pad;
+    double s_rad, s_m;
+};
+
+struct Partial {
+    float sum;
+    int cnt;
+};
+
+__host__ __device__ inline size_t partials_offset(int K) {
+    return PF_STATE_DELTAS_OFFSET + (((size_t)(K + 1) * 6 * sizeof(double) + 255) & ~(size_t)255);
+}
+
+__device__ inline double* state_deltas(pf_track_state* st) {
+    return reinterpret_cast<double*>(reinterpret_cast<char*>(st) + PF_STATE_DELTAS_OFFSET);
+}
+
+__device__ inline Partial* state_partials(pf_track_state* st, int K) {
+    return reinterpret_cast<Partial*>(reinterpret_cast<char*>(st) + partials_offset(K));
+}
+
+
+constexpr int kAdvThreads = 256;
+
+// Field ownership keeps every kernel free of read-after-write hazards across its workgroups:
+// k_adv reads (R, t, s, iter, deltas, fitness) and workgroup 0 writes (R_prev, t_prev, R_new,
+// t_new, s_*_done, iter_done, E0, mean, n_adv, n_sub); k_next reads the latter and writes the
+// former.
+//
+// k_adv, ADV = true: after the pending particles of iteration i were scored on S_i, every
+// workgroup forms the advantage set A = {k >= 1 : E_k < E_0} and the mean delta over A in the
+// same fixed order (so all compute the same P^(i) in FP64), then scores P^(i) on its chunk of
+// S_i; the chunk's (sum, count) goes to the partials. ADV = false scores the pending pose P
+// (used for the returned pose's final fitness).
+template <int FMT, int LAYOUT, bool ADV>
+__device__ inline void adv_step(const VolView& vv, const float* __restrict__ px, const float* __restrict__ py,
+                                const float* __restrict__ pz, int n_host, const int* __restrict__ n_dev,
+                                const float* __restrict__ fitness, pf_track_state* st, int K, int blk, int nblk) {
+    if (st->K != K) {
+        if (blk == 0 && threadIdx.x == 0) st->flags |= 1;
+        return;
+    }
+    __shared__ float pose_sh[12];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int n = n_dev ? *n_dev : n_host;
+    if constexpr (ADV) {
+        const double* dl = state_deltas(st);
+        const float E0 = fitness[0];
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        int na = 0;
+        for (int k = 1 + threadIdx.x; k <= K; k += kAdvThreads) {
+            if (fitness[k] < E0) {
+#pragma unroll
+                for (int d = 0; d < 6; ++d) acc[d] += dl[6 * k + d];
+                na += 1;
+            }
+        }
+        __shared__ double dred[6][kAdvThreads / kWave];
+        __shared__ int cred[kAdvThreads / kWave];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) acc[d] += __shfl_xor(acc[d], off);
+            na += __shfl_xor(na, off);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) dred[d][wid] = acc[d];
+            cred[wid] = na;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sm[6] = {0, 0, 0, 0, 0, 0};
+            int c = 0;
+            for (int w = 0; w < kAdvThreads / kWave; ++w) {
+                for (int d = 0; d < 6; ++d) sm[d] += dred[d][w];
+                c += cred[w];
+            }
+            double R[9], t[3], mean[6] = {0, 0, 0, 0, 0, 0};
+            for (int q = 0; q < 9; ++q) R[q] = st->R[q];
+            for (int q = 0; q < 3; ++q) t[q] = st->t[q];
+            if (c > 0) {
+                for (int d = 0; d < 6; ++d) mean[d] = sm[d] / (double)c;
+                double Ro[9], to[3];
+                apply_delta(st->compose_mode, mean, mean + 3, R, t, Ro, to);
+                for (int q = 0; q < 9; ++q) R[q] = Ro[q];
+                for (int q = 0; q < 3; ++q) t[q] = to[q];
+            }
+            store_pose12(pose_sh, R, t);
+            if (blk == 0) {
+                for (int q = 0; q < 9; ++q) st->R_prev[q] = st->R[q];
+                for (int q = 0; q < 3; ++q) st->t_prev[q] = st->t[q];
+                for (int q = 0; q < 9; ++q) st->R_new[q] = R[q];
+                for (int q = 0; q < 3; ++q) st->t_new[q] = t[q];
+                for (int d = 0; d < 6; ++d) st->mean[d] = mean[d];
+                st->n_adv = c;
+                st->E0 = (double)E0;
+                st->s_rad_done = st->s_rad;
+                st->s_m_done = st->s_m;
+                st->iter_done = st->iter;
+                st->n_sub = n;
+            }
+        }
+    } else {
+        if (threadIdx.x == 0) {
+            double R[9], t[3];
+            for (int q = 0; q < 9; ++q) R[q] = st->R[q];
+            for (int q = 0; q < 3; ++q) t[q] = st->t[q];
+            store_pose12(pose_sh, R, t);
+        }
+    }
+    __syncthreads();
+    // this workgroup's chunk of the view, scored with the scoring kernel's arithmetic
+    const Gather<FMT, LAYOUT> G = make_gather<FMT, LAYOUT>(vv);
+    GridPose g[1] = {fold_pose(pose_sh, vv.inv_vs, vv.gx0, vv.gy0, vv.gz0)};
+    const unsigned lx = (unsigned)(vv.nx - 1), ly = (unsigned)(vv.ny - 1), lz = (unsigned)(vv.nz - 1);
+    const int chunk = (n + nblk - 1) / nblk;
+    const int q0 = blk * chunk, q1 = min(n, q0 + chunk);
+    float sum[1] = {0.0f};
+    int cnt[1] = {0};
+    const float sc = vv.inv_vs;
+    for (int q = q0 + (int)threadIdx.x; q < q1; q += kAdvThreads)
+        eval_poses<FMT, LAYOUT, 1>(G, lx, ly, lz, g, px[q] * sc, py[q] * sc, pz[q] * sc, sum, cnt);
+    block_reduce<1, kAdvThreads>(sum, cnt);
+    if (threadIdx.x == 0) {
+        Partial* pt = state_partials(st, K);
+        pt[blk].sum = sum[0];
+        pt[blk].cnt = cnt[0];
+    }
+    __syncthreads();
+}
+
+// Completes iteration i (unless FIRST) and draws the K particles of the next one:
+// E* from the partials in order, s^(i+1) = s^(i) (beta + (1 - beta) E*), then particle k is the
+// delta (omega a[0:3], v a[3:6]) with a from the counter stream, composed with P^(i) in FP64 and
+// rounded to FP32; slot 0 is P^(i). FIRST draws iteration 1 around the initial state.
+template <int FMT, bool FIRST>
+__device__ inline void next_step(pf_track_state* st, int K, int n_partials, int draw, float* next_poses, IterRec* recs,
+                                 int blk) {
+    if (st->K != K) return;
+    __shared__ double sh_s[2];
+    __shared__ int sh_cnt;
+    __shared__ float sh_E;
+    if (!FIRST && threadIdx.x == 0) {
+        const Partial* pt = state_partials(st, K);
+        float sum = 0.0f;
+        int cnt = 0;
+        for (int b = 0; b < n_partials; ++b) {
+            sum += pt[b].sum;
+            cnt += pt[b].cnt;
+        }
+        const float Es = cnt > 0 ? (sum * Fmt<FMT>::scale) / (float)cnt : 1.0f;
+        const double f = st->beta + (1.0 - st->beta) * (double)Es;
+        sh_s[0] = st->s_rad_done * f;
+        sh_s[1] = st->s_m_done * f;
+        sh_cnt = cnt;
+        sh_E = Es;
+    }
+    __syncthreads();
+    const int k = blk * 256 + threadIdx.x;
+    double R[9], t[3], s_rad, s_m;
+    uint32_t it;
+    if (FIRST) {
+        for (int q = 0; q < 9; ++q) R[q] = st->R[q];
+        for (int q = 0; q < 3; ++q) t[q] = st->t[q];
+        s_rad = st->s_rad;
+        s_m = st->s_m;
+        it = (uint32_t)st->iter;
+    } else {
+        for (int q = 0; q < 9; ++q) R[q] = st->R_new[q];
+        for (int q = 0; q < 3; ++q) t[q] = st->t_new[q];
+        s_rad = sh_s[0];
+        s_m = sh_s[1];
+        it = (uint32_t)st->iter_done + 1u;
+    }
+    __syncthreads();   // every thread has read the state before it is rewritten below
+    if (!FIRST && k == 0) {
+        const int i = st->iter_done;
+        if (recs && i >= 1 && i <= PF_MAX_ITERS) {
+            IterRec& r = recs[i - 1];
+            r.E0 = (float)st->E0;
+            r.Estar = sh_E;
+            r.n_adv = st->n_adv;
+            r.n_sub = st->n_sub;
+            r.n_valid = sh_cnt;
+            r.s_rad = st->s_rad_done;
+            r.s_m = st->s_m_done;
+        }
+        st->Estar = (double)sh_E;
+        st->n_valid_star = sh_cnt;
+        for (int q = 0; q < 9; ++q) st->R[q] = R[q];
+        for (int q = 0; q < 3; ++q) st->t[q] = t[q];
+        st->s_rad = s_rad;
+        st->s_m = s_m;
+        st->iter = (int)it;
+    }
+    if (draw && k <= K) {
+        double* dl = state_deltas(st);
+        if (k == 0) {
+            store_pose12(next_poses, R, t);
+            for (int d = 0; d < 6; ++d) dl[d] = 0.0;
+        } else {
+            const uint64_t seed = st->seed;
+            const uint32_t fr = (uint32_t)st->frame_index;
+            double r[3], tau[3];
+            for (int d = 0; d < 3; ++d) r[d] = s_rad * draw_pm1(seed, fr, it, (uint32_t)k, (uint32_t)d);
+            for (int d = 0; d < 3; ++d) tau[d] = s_m * draw_pm1(seed, fr, it, (uint32_t)k, (uint32_t)(3 + d));
+            double Ro[9], to[3];
+            apply_delta(st->compose_mode, r, tau, R, t, Ro, to);
+            store_pose12(next_poses + (size_t)k * 12, Ro, to);
+            for (int d = 0; d < 3; ++d) {
+                dl[6 * k + d] = r[d];
+                dl[6 * k + 3 + d] = tau[d];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+
+int n_partials_for(int cap);
+
+// ------------------------------------------------------------------ particle scoring
+// Workgroup of BLOCK threads scoring poses k0 .. k0+TK-1 over all n points: every lane keeps a
+// point in registers and evaluates it against the TK poses (uniform, in scalar registers); each
+// pose's (sum, count) is reduced once, in a fixed order that depends on BLOCK only, so the
+// result of a pose does not depend on TK or on which workgroup scores it.
+template <int FMT, int LAYOUT, int TK, int BLOCK>
+__device__ inline void score_step(const VolView& vv, const float* __restrict__ px, const float* __restrict__ py,
+                                  const float* __restrict__ pz, int n, const float* __restrict__ poses, int K, int k0,
+                                  float* __restrict__ fitness, int* __restrict__ n_valid) {
+    const Gather<FMT, LAYOUT> G = make_gather<FMT, LAYOUT>(vv);
+    GridPose g[TK];
+#pragma unroll
+    for (int j = 0; j < TK; ++j)
+        g[j] = fold_pose(poses + (size_t)min(k0 + j, K - 1) * 12, vv.inv_vs, vv.gx0, vv.gy0, vv.gz0);
+    const unsigned lx = (unsigned)(vv.nx - 1), ly = (unsigned)(vv.ny - 1), lz = (unsigned)(vv.nz - 1);
+    float sum[TK];
+    int cnt[TK];
+#pragma unroll
+    for (int j = 0; j < TK; ++j) {
+        sum[j] = 0.0f;
+        cnt[j] = 0;
+    }
+    const float s = vv.inv_vs;
+    for (int q = threadIdx.x; q < n; q += BLOCK)
+        eval_poses<FMT, LAYOUT, TK>(G, lx, ly, lz, g, px[q] * s, py[q] * s, pz[q] * s, sum, cnt);
+    block_reduce<TK, BLOCK>(sum, cnt);
+    if (threadIdx.x < TK) {
+        const int k = k0 + threadIdx.x;
+        if (k < K) {
+            fitness[k] = cnt[0] > 0 ? (sum[0] * Fmt<FMT>::scale) / (float)cnt[0] : 1.0f;
+            n_valid[k] = cnt[0];
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace pf

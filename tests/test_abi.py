@@ -44,7 +44,8 @@ def test_struct_layouts_match_header(pf):
     structs = {
         "pf_pose": pf.pf_pose, "pf_intrinsics": pf.pf_intrinsics, "pf_tsdf": pf.pf_tsdf,
         "pf_track_params": pf.pf_track_params, "pf_track_stats": pf.pf_track_stats,
-        "pf_track_state": pf.pf_track_state,
+        "pf_track_state": pf.pf_track_state, "pf_batch_problem": pf.pf_batch_problem,
+        "pf_batch_plan": pf.pf_batch_plan,
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for name, cls in structs.items():
@@ -166,3 +167,30 @@ def test_params_validation(pf):
     assert L.particles_state_bytes(0) == 0
     # header, then the FP64 deltas at 512, then 256-byte aligned per-workgroup partials
     assert L.particles_state_bytes(10) == 512 + 768 + 256 * 8
+
+
+def test_batch_validation(pf):
+    L = pf.lib()
+    q = (pf.pf_batch_problem * 2)()
+    for i in range(2):
+        q[i].vol = _desc(pf, 16, 16, 16, 0, 1)
+        q[i].depth = 0x5000
+        q[i].K = pf.pf_intrinsics(100.0, 100.0, 40.0, 30.0, 80, 60)
+        q[i].init = pf.make_pose(np.eye(3), np.zeros(3))
+        q[i].params = pf.TrackParams(K=256, n_iters=4, rates=(1,), pixel_stride=2).c()
+    assert L.track_batch_workspace_bytes(q, 2) > 0
+    q[1].params.K = 32                         # batching needs K >= 64
+    assert L.track_batch_workspace_bytes(q, 2) == 0
+    assert "K 32 < 64" in pf.last_error()
+    q[1].params.K = 256
+    q[1].params.polish_steps = 2
+    assert L.track_batch_workspace_bytes(q, 2) == 0
+    q[1].params.polish_steps = 0
+    bad = pf.pf_batch_plan(3, 1024, 0, 0)
+    h = L.track_batch_create(q, 2, C.byref(bad), C.c_void_p(0x6000), C.c_size_t(1 << 30), None)
+    assert not h and "score_tk" in pf.last_error()
+    q[1].params.n_iters = 5                    # all problems must share n_iters
+    ok = pf.pf_batch_plan(4, 1024, 1, 0)
+    h = L.track_batch_create(q, 2, C.byref(ok), C.c_void_p(0x6000), C.c_size_t(1 << 30), None)
+    assert not h and "differs" in pf.last_error()
+    assert L.track_batch_run(None, None) == pf.PF_EINVAL

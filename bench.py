@@ -82,6 +82,85 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}))
 
 
+def bench_batch(args):
+    """Batching workload: 64 independent problems (own rooms, resolutions 160x120 .. 640x480,
+    K in [256, 4096], own 256^3 FP32 volumes at 1 cm, 10 iterations, every 2nd pixel), each with
+    frame 1 fused; frame 2 tracked as (a) 64 sequential track_frame calls, (b) one batch, (c) one
+    replay of the batch captured in a HIP graph. Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2509_24236_amd as pf
+    import synth
+    from paper_2509_24236_amd import autotune
+    dev = torch.device("cuda:0")
+    n = args.problems
+    log(f"[bench] building {n} batching problems")
+    probs, evals = [], 0
+    for p in range(n):
+        d = synth.random_depth_for_batch(p)
+        vol = pf.Tsdf(d["vol"], device=dev)
+        vol.integrate(torch.as_tensor(d["depth1"]).to(dev), d["intr"], np.eye(3), np.zeros(3))
+        prm = pf.TrackParams(seed=40 + p, frame_index=1, n_iters=10, K=d["K"], rates=(1,), pixel_stride=2,
+                             s1_deg=10.0, s1_m=0.10)
+        probs.append((vol, torch.as_tensor(d["depth2"]).to(dev), d["intr"], *d["init2"], prm))
+    torch.cuda.synchronize()
+    plan = autotune.plan_for(probs) if not args.tune else autotune.tune(probs, log=log)
+    trackers = [pf.Tracker(p[2], p[5], device=dev) for p in probs]
+
+    def sequential():
+        out = []
+        for trk, (vol, depth, intr, R0, t0, prm) in zip(trackers, probs):
+            out.append(trk.track(vol, depth, R0, t0))
+        return out
+
+    seq = sequential()           # warm-up, and the per-problem reference
+    evals = sum((p[5].K + 1) * st.n_sub[i] for p, (_, _, st) in zip(probs, seq) for i in range(st.n_iters))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sequential()
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / args.steps
+    b = pf.Batch(probs, plan, device=dev)
+    b.run()
+    res = b.results()
+    same = all(np.array_equal(r[0], q[0]) and np.array_equal(r[1], q[1]) for r, q in zip(res, seq))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.run(stream=s)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / args.steps
+    res_g = b.results()
+    same_g = all(np.array_equal(r[0], q[0]) and np.array_equal(r[1], q[1]) for r, q in zip(res_g, seq))
+    b.close()
+    out = {"metric": "batched particle-point fitness evals/s (64 heterogeneous problems, one frame each)",
+           "value": evals / t_graph, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+           "ms_per_step": 1e3 * t_graph, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{n} problems: 160x120..640x480, K 256..4096, 256^3 f32 at 1 cm, 10 iterations, "
+                                  "every 2nd pixel", "plan": dataclasses_asdict(plan)},
+           "sequential_ms": 1e3 * t_seq, "batch_eager_ms": 1e3 * t_batch, "batch_graph_ms": 1e3 * t_graph,
+           "speedup_vs_sequential": t_seq / t_graph, "bitwise_equal_to_plain": bool(same and same_g),
+           "evals_per_batch": evals}
+    print(json.dumps(out), flush=True)
+
+
+def dataclasses_asdict(x):
+    import dataclasses
+    return dataclasses.asdict(x)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,9 +169,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true", help="run only a plain 1 GiB device copy")
+    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch"],
+                    help="sequence: the paper-scale sequence (the headline); batch: 64 heterogeneous problems")
+    ap.add_argument("--problems", type=int, default=64)
+    ap.add_argument("--tune", action="store_true", help="batch: run the autotuner first and record the plan")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "batch":
+        bench_batch(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures the single-GPU path only (--gpus {args.gpus} requested); the multi-GPU "

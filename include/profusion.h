@@ -235,6 +235,12 @@ int32_t particles_score_grad(const pf_tsdf* v, const float* px, const float* py,
                              int32_t compose_mode, float* fitness, float* grad, int32_t* n_valid,
                              void* stream);
 
+/* Launch shape of the scoring launches with more than 64 poses (particles_score and
+ * track_frame): poses per workgroup (1, 2, 4, 8) and workgroup size (128, 256, 512; 1 pose needs
+ * >= 256). Process-wide; default 4 and 256. Results are bitwise reproducible for a given workgroup
+ * size, which sets the summation order (the batched path always uses 256). */
+int32_t pf_score_config(int32_t poses_per_group, int32_t group_size);
+
 /* Bytes of the device state buffer for K particles (pf_track_state + (K+1)*6 doubles). */
 size_t particles_state_bytes(int32_t K);
 

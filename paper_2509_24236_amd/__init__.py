@@ -84,7 +84,7 @@ class pf_batch_plan(C.Structure):
 
 # every symbol include/profusion.h declares
 EXPORTS = ("pf_last_error", "tsdf_bytes", "tsdf_cells_offset", "tsdf_init", "tsdf_integrate", "tsdf_export_linear", "tsdf_import_linear",
-           "backproject", "particles_score", "particles_score_grad", "particles_state_bytes", "particles_state_init", "particles_update",
+           "backproject", "particles_score", "particles_score_grad", "pf_score_config", "particles_state_bytes", "particles_state_init", "particles_update",
            "track_workspace_bytes", "track_frame", "track_batch_workspace_bytes", "track_batch_create",
            "track_batch_run", "track_batch_results", "track_batch_destroy", "pf_timing_enable", "pf_timing_read")
 
@@ -114,6 +114,7 @@ def lib() -> C.CDLL:
     L.backproject.argtypes = [vp, P(pf_intrinsics), i32, vp, vp, vp, vp, vp]
     L.particles_score.argtypes = [P(pf_tsdf), vp, vp, vp, i32, vp, i32, vp, vp, vp]
     L.particles_score_grad.argtypes = [P(pf_tsdf), vp, vp, vp, i32, vp, vp, i32, i32, vp, vp, vp, vp]
+    L.pf_score_config.argtypes = [i32, i32]
     L.particles_state_bytes.restype = C.c_size_t
     L.particles_state_bytes.argtypes = [i32]
     L.particles_state_init.argtypes = [vp, P(pf_pose), P(pf_track_params), vp, vp]
@@ -348,6 +349,11 @@ def fitness(xi, base, vol, px, py, pz, mode=COMPOSE_DECOUPLED):
     if _FitnessFn is None:
         _FitnessFn = _fitness_fn()
     return _FitnessFn.apply(xi, base, vol, px, py, pz, mode)
+
+
+def score_config(poses_per_group: int = 4, group_size: int = 256):
+    """Launch shape of the many-pose scoring launches (process-wide)."""
+    _check(lib().pf_score_config(poses_per_group, group_size))
 
 
 def state_bytes(K: int) -> int:

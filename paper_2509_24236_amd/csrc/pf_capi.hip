@@ -20,6 +20,7 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
               const pf_track_params* p, pf_pose* out, pf_track_stats* stats, void* workspace, size_t ws_bytes,
               hipStream_t s);
 int32_t timing_enable(int on);
+int32_t score_config(int tk, int block);
 int32_t timing_read(double* ms, int64_t* launches, int64_t* evals, int reset);
 
 namespace {
@@ -70,6 +71,8 @@ int32_t check_tsdf(const pf_tsdf* v, const char* fn, bool need_weight = true) {
     if (!v) return set_error(PF_EINVAL, "%s: null volume", fn);
     if (v->nx < 2 || v->ny < 2 || v->nz < 2)
         return set_error(PF_EINVAL, "%s: volume dims %d x %d x %d (each must be >= 2)", fn, v->nx, v->ny, v->nz);
+    if (v->ny > 65535 || v->nz > 65535)
+        return set_error(PF_EINVAL, "%s: ny and nz must be <= 65535", fn);
     if ((int64_t)v->nx * v->ny * v->nz >= ((int64_t)1 << 31))
         return set_error(PF_EINVAL, "%s: volume of %lld voxels exceeds 2^31 - 1", fn,
                          (long long)v->nx * v->ny * v->nz);
@@ -250,6 +253,10 @@ int32_t particles_score_grad(const pf_tsdf* v, const float* px, const float* py,
     Points p{px, py, pz, n_pts, nullptr};
     return launch_grad(make_view(v), p, base, xi, B, 1, compose_mode, fitness, grad, n_valid, nullptr,
                        (hipStream_t)stream);
+}
+
+int32_t pf_score_config(int32_t poses_per_group, int32_t group_size) {
+    return score_config(poses_per_group, group_size);
 }
 
 size_t particles_state_bytes(int32_t K) {

@@ -39,11 +39,21 @@ int32_t launch_t(const VolView& vv, const Points& p, const float* poses, int K, 
     return check_launch("particles_score");
 }
 
+// Launch shape of the many-pose scoring launches (pf_score_config): poses per workgroup and
+// workgroup size. The per-pose reduction order depends on the workgroup size only.
+int g_tk = 4, g_block = 256;
+
 template <int FMT, int LAYOUT>
 int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
                   hipStream_t s) {
-    // few poses: spread the points over a wide workgroup; many poses: 4 poses per workgroup
+    // few poses: spread the points over a wide workgroup
     if (K <= 64) return launch_t<FMT, LAYOUT, 1, 1024>(vv, p, poses, K, fitness, n_valid, s);
+#define PF_SHAPE(TK, B) \
+    if (g_tk == TK && g_block == B) return launch_t<FMT, LAYOUT, TK, B>(vv, p, poses, K, fitness, n_valid, s);
+    PF_SHAPE(1, 256) PF_SHAPE(2, 256) PF_SHAPE(8, 256)
+    PF_SHAPE(1, 512) PF_SHAPE(2, 512) PF_SHAPE(4, 512) PF_SHAPE(8, 512)
+    PF_SHAPE(2, 128) PF_SHAPE(4, 128) PF_SHAPE(8, 128)
+#undef PF_SHAPE
     return launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, s);
 }
 
@@ -55,6 +65,16 @@ int32_t launch_fmt(const VolView& vv, const Points& p, const float* poses, int K
 }
 
 }  // namespace
+
+int32_t score_config(int tk, int block) {
+    const bool ok_tk = tk == 1 || tk == 2 || tk == 4 || tk == 8;
+    const bool ok_b = block == 128 || block == 256 || block == 512;
+    if (!ok_tk || !ok_b || (tk == 1 && block == 128))
+        return set_error(PF_EINVAL, "pf_score_config: unsupported shape (%d poses, %d threads)", tk, block);
+    g_tk = tk;
+    g_block = block;
+    return PF_OK;
+}
 
 int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
                      hipStream_t s) {

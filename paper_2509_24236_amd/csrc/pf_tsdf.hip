@@ -120,17 +120,17 @@ struct FuseArgs {
 // The projection is evaluated in FP64 with the same operation order as the plain definition
 // and with contraction disabled, so the per-voxel decisions (updated or not, which pixel)
 // are those of an FP64 evaluation of the formula as written; the running average is FP32.
+// Grid: x in workgroups of kBlock voxels, y and z one row per workgroup, so no index division.
+// A conservative FP32 pre-test drops voxels that lie outside the image by more than two pixels
+// (FP32 error here is far below a pixel), which the FP64 test would drop too.
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
 #pragma clang fp contract(off)
     using S = Store<FMT>;
-    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t nxy = (int64_t)a.d.nx * a.d.ny;
-    if (idx >= a.d.n) return;
-    const int k = (int)(idx / nxy);
-    const int64_t rem = idx - (int64_t)k * nxy;
-    const int j = (int)(rem / a.d.nx);
-    const int i = (int)(rem - (int64_t)j * a.d.nx);
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int j = blockIdx.y, k = blockIdx.z;
+    if (i >= a.d.nx) return;
+    const int64_t idx = ((int64_t)k * a.d.ny + j) * a.d.nx + i;
     const double px = a.ox + a.vs * (double)i;
     const double py = a.oy + a.vs * (double)j;
     const double pz = a.oz + a.vs * (double)k;
@@ -139,6 +139,12 @@ __global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
     if (!(qz > 0.0)) return;
     const double qx = a.R[0] * dx + a.R[3] * dy + a.R[6] * dz;
     const double qy = a.R[1] * dx + a.R[4] * dy + a.R[7] * dz;
+    if (qz > 1e-6) {   // (below, FP32 could overflow; the FP64 test decides alone)
+        const float iz = 1.0f / (float)qz;
+        const float uf32 = (float)a.fx * (float)qx * iz + (float)a.cx;
+        const float vf32 = (float)a.fy * (float)qy * iz + (float)a.cy;
+        if (!(uf32 > -2.5f && uf32 < (float)a.width + 1.5f && vf32 > -2.5f && vf32 < (float)a.height + 1.5f)) return;
+    }
     const double u = a.fx * qx / qz + a.cx;
     const double v = a.fy * qy / qz + a.cy;
     const double uf = floor(u + 0.5), vf = floor(v + 0.5);
@@ -156,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
     const float w = S::decw(W[idx]);
     const float tn = (S::dec(told) * w + (float)phi) / (w + 1.0f);
     const typename S::T tnew = S::enc(tn);
-    T[idx] = tnew;
+    if (!S::same(told, tnew)) T[idx] = tnew;
     W[idx] = S::encw(fminf(w + 1.0f, a.w_max));
     if (a.C && !S::same(told, tnew)) write_corners(static_cast<typename S::T*>(a.C), a.d, i, j, k, tnew);
 }
@@ -249,8 +255,8 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
     a.height = K->height;
     a.w_max = (float)v->w_max;
     a.depth = depth;
-    const int64_t blocks = (a.d.n + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_integrate<FMT>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    const dim3 grid((unsigned)((a.d.nx + kBlock - 1) / kBlock), (unsigned)a.d.ny, (unsigned)a.d.nz);
+    hipLaunchKernelGGL(k_integrate<FMT>, grid, dim3(kBlock), 0, s, a);
     return check_launch("tsdf_integrate");
 }
 

@@ -324,13 +324,19 @@ def pr_standin(gt_prev, gt_cur, rng, sigma_rot_deg=3.0, sigma_t=0.03):
     return pose_mul(Rrel, trel, rot(dr), dt)
 
 
-def cfg2_frames(n_frames=200, traj_seed=11, scene_seed=10, noise_seed=12, pr_seed=13):
+CFG2_LENGTH = 200
+
+
+def cfg2_frames(n_frames=CFG2_LENGTH, traj_seed=11, scene_seed=10, noise_seed=12, pr_seed=13):
     """The paper-scale sequence: scene, world GT poses, noisy depth maps (lazy) and PR stand-ins.
 
-    Depth maps are rendered on demand by `depth(t)` so callers can bound host memory.
+    The scene is always placed against the full 200-frame trajectory, so the first n_frames of
+    any call are the same frames. Depth maps are rendered on demand by `depth(t)` so callers can
+    bound host memory.
     """
-    traj_room = cfg2_trajectory(n_frames, traj_seed)
-    scene = cfg2_scene(traj_room, scene_seed)
+    traj_full = cfg2_trajectory(max(n_frames, CFG2_LENGTH), traj_seed)
+    scene = cfg2_scene(traj_full, scene_seed)
+    traj_room = traj_full[:n_frames]
     gt = world_trajectory(scene, traj_room)
     vol = VolumeSpec.centred(512, 0.01, 0.04, room_centre_world(scene))
     rng = np.random.default_rng(pr_seed)

@@ -321,3 +321,70 @@ def test_track_frame_rates_and_stats(pf, orc, dev, cfg1, cfg1_vol):
     n = st.n_points
     assert [st.n_sub[i] for i in range(6)] == [r.n_pts for r in recs] == [n, (n + 1) // 2, (n + 2) // 3] * 2
     assert math.degrees(orc.rot_err(R, Ro)) <= 0.05 and np.linalg.norm(t - to) <= 1e-3
+
+
+# ----------------------------------------------------------------------------- full size
+@pytest.fixture(scope="module")
+def cfg2_full(orc):
+    f = synth.cfg2_frames(2)
+    ov = orc.Volume(f["vol"])
+    ov.integrate(f["depth"](0), f["intr"], np.eye(3), np.zeros(3))
+    return f, ov
+
+
+def test_fullsize_fusion_weights_exact(pf, dev, cfg2_full):
+    say("[fullsize] 512^3 fusion of frame 0: weights exact, values within FP32 rounding")
+    f, ov = cfg2_full
+    gv = pf.Tsdf(f["vol"], device=dev)
+    gv.integrate(torch.as_tensor(f["depth"](0)).to(dev), f["intr"], np.eye(3), np.zeros(3))
+    T, W = gv.export_linear()
+    W = W.cpu().numpy()
+    assert np.array_equal(W, ov.W.astype(np.float32))
+    T = T.cpu().numpy()
+    upd = ov.W > 0
+    assert np.abs(T[upd].astype(np.float64) - ov.T[upd]).max() <= 1e-6
+    assert upd.sum() > 10_000_000
+
+
+def test_fullsize_scoring_sampled(pf, orc, dev, cfg2_full):
+    """The bench launch configuration (3073 poses, rate-1/8 view, cell replica, 4 poses per
+    workgroup): 48 sampled poses against the oracle's intervals."""
+    say("[fullsize] 3073 poses on the rate-1/8 view, 48 sampled against the oracle")
+    f, ov = cfg2_full
+    T32 = ov.T.astype(np.float32)
+    gv = upload(pf, f["vol"], T32, ov.W, dev)
+    X, _ = orc.backproject(f["depth"](1), f["intr"], 1)
+    S = orc.subsample(X, 8).astype(np.float32)
+    R0, t0 = f["gt"][1]
+    poses = _poses_around(orc, R0, t0, 3073, math.radians(10), 0.10, 5)
+    P32 = pf.poses_to_f32(poses)
+    st = torch.as_tensor(S).to(dev)
+    E, nv = pf.particles_score(gv, st[:, 0].contiguous(), st[:, 1].contiguous(), st[:, 2].contiguous(),
+                               torch.as_tensor(P32).to(dev))
+    E = E.cpu().numpy()
+    idx = np.unique(np.concatenate([[0, 1, 2, 3072], np.random.default_rng(6).choice(3073, 44, replace=False)]))
+    v32 = orc.Volume(f["vol"], T=T32.astype(np.float64), W=ov.W)
+    p64 = [(P32[k].reshape(3, 4)[:, :3].astype(np.float64), P32[k].reshape(3, 4)[:, 3].astype(np.float64)) for k in idx]
+    lo, hi, _ = v32.fitness_interval_many(S.astype(np.float64), p64, eps=1e-3)
+    check_fitness(E[idx], None, lo, hi)
+    del v32
+
+
+def test_fullsize_track_frame(pf, orc, dev, cfg2_full):
+    say("[fullsize] track frame 1: 3072 particles x 20 iterations, rates 8/16/32")
+    f, ov = cfg2_full
+    T32 = ov.T.astype(np.float32)
+    gv = upload(pf, f["vol"], T32, ov.W, dev)
+    v32 = orc.Volume(f["vol"], T=T32.astype(np.float64), W=ov.W)
+    R0, t0 = f["rel"][1]                    # P_1^(0) = I * P_(1,0)
+    prm = pf.TrackParams(seed=14, frame_index=1, n_iters=20, K=3072, rates=(8, 16, 32), pixel_stride=1)
+    R, t, st = pf.Tracker(f["intr"], prm, device=dev).track(gv, torch.as_tensor(f["depth"](1)).to(dev), R0, t0)
+    oprm = orc.make_params(seed=14, frame_index=1, n_iters=20, K=3072, rates=(8, 16, 32), pixel_stride=1,
+                           s1_deg=10.0, s1_m=0.10)
+    Ro, to, recs = v32.track_frame(f["depth"](1), f["intr"], R0, t0, oprm)
+    dr, dt = math.degrees(orc.rot_err(R, Ro)), float(np.linalg.norm(t - to))
+    say(f"    pose vs oracle {dr:.2e} deg {dt * 1e3:.3e} mm; |A| gpu {list(st.n_adv[:6])} oracle "
+        f"{[r.n_adv for r in recs[:6]]}")
+    assert dr <= 0.05 and dt <= 1e-3
+    assert [st.n_sub[i] for i in range(20)] == [r.n_pts for r in recs]
+    del v32

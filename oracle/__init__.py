@@ -116,7 +116,7 @@ def lib():
         L.orc_fitness_grad.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, dp, dp, i64p]
         L.orc_fitness_grad_many.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, C.c_int32, dp, dp, i64p]
         L.orc_fitness_grad_interval_many.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, C.c_int32,
-                                                     C.c_double, dp, dp]
+                                                     C.c_double, C.c_double, dp, dp]
         L.orc_fitness_frozen_at.restype = C.c_double
         L.orc_fitness_frozen_at.argtypes = [P(Vol), dp, C.c_int64, P(Pose), P(Pose)]
         L.orc_grad_xi_fd.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, dp, C.c_double, dp]
@@ -297,14 +297,15 @@ class Volume:
                                     nv.ctypes.data_as(C.POINTER(C.c_int64)))
         return E, g, nv
 
-    def fitness_grad_interval_many(self, xyz, poses, mode=COMPOSE_DECOUPLED, eps=1e-3):
-        """Per pose, [lo, hi] of (E, grad6) over every cell choice of samples within eps of a face."""
+    def fitness_grad_interval_many(self, xyz, poses, mode=COMPOSE_DECOUPLED, eps=1e-3, sign_eps=0.0):
+        """Per pose, [lo, hi] of (E, grad6) over every cell choice of samples within eps of a face
+        and both signs of samples whose value is within sign_eps of 0."""
         x = _f64(xyz)
         B = len(poses)
         arr = (Pose * B)(*[Pose.of(R, t) for R, t in poses])
         lo, hi = np.zeros((B, 7)), np.zeros((B, 7))
-        lib().orc_fitness_grad_interval_many(C.byref(self.c()), _dp(x), x.shape[0], arr, B, mode, eps, _dp(lo),
-                                             _dp(hi))
+        lib().orc_fitness_grad_interval_many(C.byref(self.c()), _dp(x), x.shape[0], arr, B, mode, eps, sign_eps,
+                                             _dp(lo), _dp(hi))
         return lo, hi
 
     def fitness_frozen(self, xyz, R, t, xi, mode=COMPOSE_DECOUPLED):

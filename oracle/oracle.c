@@ -571,11 +571,11 @@ void orc_fitness_grad(const orc_vol* V, const double* xyz, int64_t n, const orc_
 
 /* Interval form of E and of the frozen-set gradient for comparison with a float32 evaluation:
  * samples whose grid coordinate lies within `eps` voxels of a cell face are evaluated with every
- * admissible cell choice. With S_a the component sum and C the valid count, each bound is taken
+ * admissible cell choice, and samples whose value lies within `sign_eps` of 0 with both signs. With S_a the component sum and C the valid count, each bound is taken
  * over the box [S_lo, S_hi] x [C_lo, C_hi] (S/C is monotone in each for C > 0), so the intervals
  * contain every outcome of such choices. lo/hi: E then the 6 gradient components. */
 void orc_fitness_grad_interval(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t mode,
-                               double eps, double lo[7], double hi[7]) {
+                               double eps, double sign_eps, double lo[7], double hi[7]) {
     double Slo[7] = {0}, Shi[7] = {0};
     int64_t Clo = 0, Chi = 0;
     double cc[3] = {0, 0, 0};
@@ -605,20 +605,27 @@ void orc_fitness_grad_interval(const orc_vol* V, const double* xyz, int64_t n, c
                     int64_t c[3] = {opts[0][ox], opts[1][oy], opts[2][oz]};
                     double v = 0.0, term[7] = {0, 0, 0, 0, 0, 0, 0};
                     int ok = sample_cell(V, g, c, &v);
-                    if (ok) {
-                        double f[3] = {g[0] - c[0], g[1] - c[1], g[2] - c[2]};
-                        double gT[3];
-                        trilinear_grad(V, c, f, gT);
-                        double sg = v > 0 ? 1.0 : (v < 0 ? -1.0 : 0.0);
-                        term[0] = fabs(v);
-                        for (int a = 0; a < 3; ++a) term[1 + a] = sg * gT[a];
-                        term[4] = sg * (u[1] * gT[2] - u[2] * gT[1]);
-                        term[5] = sg * (u[2] * gT[0] - u[0] * gT[2]);
-                        term[6] = sg * (u[0] * gT[1] - u[1] * gT[0]);
-                    }
-                    for (int e = 0; e < 7; ++e) {
-                        if (term[e] < mn[e]) mn[e] = term[e];
-                        if (term[e] > mx[e]) mx[e] = term[e];
+                    /* the sign of a value within sign_eps of 0 is ambiguous at lower precision:
+                     * both signs are admissible there */
+                    int ns = 1;
+                    double signs[2] = {v > 0 ? 1.0 : (v < 0 ? -1.0 : 0.0), 0.0};
+                    if (ok && fabs(v) < sign_eps) { signs[0] = 1.0; signs[1] = -1.0; ns = 2; }
+                    for (int si = 0; si < ns; ++si) {
+                        if (ok) {
+                            double f[3] = {g[0] - c[0], g[1] - c[1], g[2] - c[2]};
+                            double gT[3];
+                            trilinear_grad(V, c, f, gT);
+                            double sg = signs[si];
+                            term[0] = fabs(v);
+                            for (int a = 0; a < 3; ++a) term[1 + a] = sg * gT[a];
+                            term[4] = sg * (u[1] * gT[2] - u[2] * gT[1]);
+                            term[5] = sg * (u[2] * gT[0] - u[0] * gT[2]);
+                            term[6] = sg * (u[0] * gT[1] - u[1] * gT[0]);
+                        }
+                        for (int e = 0; e < 7; ++e) {
+                            if (term[e] < mn[e]) mn[e] = term[e];
+                            if (term[e] > mx[e]) mx[e] = term[e];
+                        }
                     }
                     if (ok < cmin) cmin = ok;
                     if (ok > cmax) cmax = ok;
@@ -644,9 +651,10 @@ void orc_fitness_grad_interval(const orc_vol* V, const double* xyz, int64_t n, c
 }
 
 void orc_fitness_grad_interval_many(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t B,
-                                    int32_t mode, double eps, double* lo, double* hi) {
+                                    int32_t mode, double eps, double sign_eps, double* lo, double* hi) {
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int32_t b = 0; b < B; ++b) orc_fitness_grad_interval(V, xyz, n, P + b, mode, eps, lo + 7 * b, hi + 7 * b);
+    for (int32_t b = 0; b < B; ++b)
+        orc_fitness_grad_interval(V, xyz, n, P + b, mode, eps, sign_eps, lo + 7 * b, hi + 7 * b);
 }
 
 void orc_fitness_grad_many(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, int32_t B,

@@ -228,7 +228,8 @@ __device__ inline void setup_pose(const double* base12, const double* xi6, int m
 template <int FMT, int LAYOUT>
 __global__ __launch_bounds__(kGradThreads) void k_grad(VolView vv, const float* __restrict__ px,
                                                        const float* __restrict__ py, const float* __restrict__ pz,
-                                                       int n, const double* __restrict__ base,
+                                                       int n_host, const int* __restrict__ n_dev,
+                                                       const double* __restrict__ base,
                                                        const double* __restrict__ xi, int mode, float* E_out,
                                                        float* grad_out, int* nv_out, GradPartial* partials) {
     __shared__ float pose_sh[12];
@@ -237,6 +238,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(VolView vv, const float* 
     if (threadIdx.x == 0) setup_pose(base + (size_t)b * 12, xi ? xi + (size_t)b * 6 : nullptr, mode, pose_sh, c_sh);
     __syncthreads();
     const float c[3] = {c_sh[0], c_sh[1], c_sh[2]};
+    const int n = n_dev ? *n_dev : n_host;
     const int chunk = (n + S - 1) / S;
     const int q0 = s * chunk, q1 = min(n, q0 + chunk);
     GradPartial acc = {};
@@ -255,7 +257,8 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(VolView vv, const float* 
 template <int FMT, int LAYOUT>
 __global__ __launch_bounds__(kGradThreads) void k_pose_partials(VolView vv, const float* __restrict__ px,
                                                                 const float* __restrict__ py,
-                                                                const float* __restrict__ pz, int n,
+                                                                const float* __restrict__ pz, int n_host,
+                                                                const int* __restrict__ n_dev,
                                                                 const double* __restrict__ poses, const int* stop,
                                                                 Partial2* partials) {
     if (stop && *stop) return;
@@ -270,6 +273,7 @@ __global__ __launch_bounds__(kGradThreads) void k_pose_partials(VolView vv, cons
     const Gather<FMT, LAYOUT> G = make_gather<FMT, LAYOUT>(vv);
     GridPose g[1] = {fold_pose(pose_sh, vv.inv_vs, vv.gx0, vv.gy0, vv.gz0)};
     const unsigned lx = (unsigned)(vv.nx - 1), ly = (unsigned)(vv.ny - 1), lz = (unsigned)(vv.nz - 1);
+    const int n = n_dev ? *n_dev : n_host;
     const int chunk = (n + S - 1) / S;
     const int q0 = s * chunk, q1 = min(n, q0 + chunk);
     float sum[1] = {0.0f};
@@ -421,8 +425,8 @@ __global__ void k_state_pose_rows(const pf_track_state* st, double* P12) {
 template <int FMT, int LAYOUT>
 int32_t grad_t(const VolView& vv, const Points& p, const double* base, const double* xi, int B, int S, int mode,
                float* E, float* g, int* nv, GradPartial* partials, hipStream_t s) {
-    hipLaunchKernelGGL((k_grad<FMT, LAYOUT>), dim3(B, S), dim3(kGradThreads), 0, s, vv, p.x, p.y, p.z, p.n, base, xi,
-                       mode, E, g, nv, partials);
+    hipLaunchKernelGGL((k_grad<FMT, LAYOUT>), dim3(B, S), dim3(kGradThreads), 0, s, vv, p.x, p.y, p.z, p.n, p.n_dev,
+                       base, xi, mode, E, g, nv, partials);
     return check_launch("particles_score_grad");
 }
 
@@ -430,7 +434,7 @@ template <int FMT, int LAYOUT>
 int32_t pose_partials_t(const VolView& vv, const Points& p, const double* poses, int P, int S, const int* stop,
                         Partial2* out, hipStream_t s) {
     hipLaunchKernelGGL((k_pose_partials<FMT, LAYOUT>), dim3(P, S), dim3(kGradThreads), 0, s, vv, p.x, p.y, p.z, p.n,
-                       poses, stop, out);
+                       p.n_dev, poses, stop, out);
     return check_launch("pose fitness");
 }
 

@@ -117,15 +117,15 @@ struct FuseArgs {
     const float* depth;
 };
 
-// The projection is evaluated in FP64 with the same operation order as the plain definition
-// and with contraction disabled, so the per-voxel decisions (updated or not, which pixel)
-// are those of an FP64 evaluation of the formula as written; the running average is FP32.
+// The projection is evaluated in FP64 with the same operation order as the plain definition,
+// and this file is compiled without multiply-add contraction, so the per-voxel decisions
+// (updated or not, which pixel) are those of an FP64 evaluation of the formula as written; the
+// running average is FP32.
 // Grid: x in workgroups of kBlock voxels, y and z one row per workgroup, so no index division.
 // A conservative FP32 pre-test drops voxels that lie outside the image by more than two pixels
 // (FP32 error here is far below a pixel), which the FP64 test would drop too.
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
-#pragma clang fp contract(off)
     using S = Store<FMT>;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     const int j = blockIdx.y, k = blockIdx.z;

@@ -259,3 +259,7 @@ def test_grad_interval_contains_exact(orc, mode):
     assert np.all(lo <= exact + 1e-15) and np.all(exact <= hi + 1e-15)
     lo0, hi0 = vol.fitness_grad_interval_many(X, poses, mode, eps=0.0)
     assert np.abs(lo0 - exact).max() <= 1e-15 * np.abs(exact).max() * 10 and np.abs(hi0 - exact).max() <= 1e-13
+    # the sign band only widens the interval
+    lo1, hi1 = vol.fitness_grad_interval_many(X, poses, mode, eps=1e-3, sign_eps=1e-3)
+    assert np.all(lo1 <= lo + 1e-15) and np.all(hi1 >= hi - 1e-15)
+    assert np.any(lo1 < lo) or np.any(hi1 > hi)

@@ -64,9 +64,11 @@ def test_adjoint_parity_1000_poses(pf, orc, dev, setup, mode):
     E, g, nv = pf.particles_score_grad(gv, *pts, base, None, mode)
     # the GPU rounds each pose to FP32 before sampling; give the oracle the same pose
     P32 = pf.poses_to_f32(poses).astype(np.float64).reshape(-1, 3, 4)
-    # values within 1e-6 of 0 may change sign in FP32 (trilinear rounding is a few 1e-8 here)
+    # a value near 0 may take the other sign in FP32: the sample position carries ~1e-5 voxel of
+    # rounding (grid coordinates up to 128), and the field changes by vs / tau = 0.25 per voxel,
+    # so |T| < 1e-5 is not sign-stable; the band is 1e-4
     lo, hi = v32.fitness_grad_interval_many(X32.astype(np.float64), [(P[:, :3], P[:, 3]) for P in P32], mode,
-                                            eps=1e-3, sign_eps=1e-6)
+                                            eps=1e-3, sign_eps=1e-4)
     got = np.concatenate([E.cpu().numpy()[:, None], g.cpu().numpy()], 1).astype(np.float64)
     scale = np.maximum(np.abs(lo), np.abs(hi))
     tol = np.concatenate([1e-4 * scale[:, :1], 2e-4 * scale[:, 1:].max(1, keepdims=True).repeat(6, 1)], 1) + 1e-6

@@ -70,6 +70,39 @@ def cpu_baseline(frames, vol_spec, intr, n_frames, seconds):
                       f"rates 1/8, 1/16, 1/32) + fuse of frames 1..{done} on a 512^3 volume ({track_s:.1f} s timed)"}
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "k_score_sequence_counters.txt")
+SCORE_SOURCES = ("pf_sample.hpp", "pf_steps.hpp", "pf_score.hip", "pf_internal.hpp")
+
+
+def score_source_hash():
+    """SHA-256 over the sources the scoring kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in SCORE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2509_24236_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(avg_launch_ms):
+    """HBM traffic of one scoring launch from the committed FETCH_SIZE / WRITE_SIZE summary, each
+    scaled by what the counter reads for a plain copy of known size, as GB/s over the measured
+    average launch time. None when there is no summary or the kernel changed since it was taken."""
+    if not os.path.exists(COUNTERS):
+        return None, None
+    vals = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("score_source_sha256") != score_source_hash():
+        return None, None
+    per_launch = (float(vals["fetch_kib_per_dispatch"]) * 1024.0 * float(vals["fetch_scale"]) +
+                  float(vals["write_kib_per_dispatch"]) * 1024.0 * float(vals["write_scale"]))
+    return per_launch / (avg_launch_ms * 1e-3) / 1e9, per_launch
+
+
 def copy_calibration():
     """A plain device copy of known size, to scale the FETCH_SIZE / WRITE_SIZE counters."""
     import torch
@@ -174,16 +207,16 @@ def main():
     ap.add_argument("--problems", type=int, default=64)
     ap.add_argument("--tune", action="store_true", help="batch: run the autotuner first and record the plan")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures the single-GPU path only (--gpus {args.gpus} requested); the multi-GPU "
+              "particle sharding is a design note, not an implemented path", file=sys.stderr)
+        sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
         return
     if args.workload == "batch":
         bench_batch(args)
         return
-    if args.gpus != 1:
-        print(f"bench.py measures the single-GPU path only (--gpus {args.gpus} requested); the multi-GPU "
-              "particle sharding is a design note, not an implemented path", file=sys.stderr)
-        sys.exit(2)
 
     import numpy as np
     import torch
@@ -237,6 +270,7 @@ def main():
     ms_per_frame = 1e3 * elapsed / args.steps
     avg_launch_ms = score_ms / max(1, launches)
     achieved = BYTES_PER_EVAL * (evals / max(1, launches)) / (avg_launch_ms * 1e-3) / 1e9
+    traffic, traffic_bytes = counter_traffic(avg_launch_ms)
     gt_err = [np.linalg.norm(est[t][1] - frames["gt"][t][1]) for t in range(1, len(est))]
     log(f"[bench] {ms_per_frame:.3f} ms/frame, scoring {avg_launch_ms:.4f} ms/launch avg, "
         f"{evals / max(score_ms, 1e-9) * 1e3:.3e} evals/s in-kernel; GT translation error median "
@@ -265,12 +299,14 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "particles_score (k_score<f32, cells, 4 poses, 256 threads>)",
+            "kernel": "particles_score per iteration: k_score_regime<f32, cells> launched as 2x64, 4x128 and "
+                      "4x256 (poses x threads), one of which runs for the spread of the particles",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_bytes_per_launch": traffic_bytes,
             "avg_launch_ms": avg_launch_ms,
             "launches": launches,
             "evals_per_launch": evals / max(1, launches),

@@ -236,9 +236,12 @@ int32_t particles_score_grad(const pf_tsdf* v, const float* px, const float* py,
                              void* stream);
 
 /* Launch shape of the scoring launches with more than 64 poses (particles_score and
- * track_frame): poses per workgroup (1, 2, 4, 8) and workgroup size (128, 256, 512; 1 pose needs
- * >= 256). Process-wide; default 4 and 256. Results are bitwise reproducible for a given workgroup
- * size, which sets the summation order (the batched path always uses 256). */
+ * track_frame): poses per workgroup (1, 2, 4, 8) and workgroup size (64, 128, 256, 512; 1 pose
+ * needs >= 256), or 0 and 0 (the default) for the automatic shape: track_frame then picks the shape
+ * of every iteration on the device from the spread of the search size that drew its particles,
+ * and particles_score uses 4 poses x 256 threads. Process-wide. Fitness sums are exact (64-bit
+ * fixed point), so every shape, and the batched path, gives bitwise identical results; the shape
+ * changes speed only. Returns PF_EINVAL for an unsupported shape. */
 int32_t pf_score_config(int32_t poses_per_group, int32_t group_size);
 
 /* Bytes of the device state buffer for K particles (pf_track_state + (K+1)*6 doubles). */

@@ -351,8 +351,8 @@ def fitness(xi, base, vol, px, py, pz, mode=COMPOSE_DECOUPLED):
     return _FitnessFn.apply(xi, base, vol, px, py, pz, mode)
 
 
-def score_config(poses_per_group: int = 4, group_size: int = 256):
-    """Launch shape of the many-pose scoring launches (process-wide)."""
+def score_config(poses_per_group: int = 0, group_size: int = 0):
+    """Launch shape of the many-pose scoring launches (process-wide); 0, 0 = automatic."""
     _check(lib().pf_score_config(poses_per_group, group_size))
 
 

@@ -121,13 +121,13 @@ __global__ void kb_final(const BatchProb* tab, int n) {
     if (p >= n) return;
     const BatchProb& P = tab[p];
     const Partial* pt = state_partials(P.st, P.K);
-    float sum = 0.0f;
+    FixSum sum = 0;
     int cnt = 0;
     for (int b = 0; b < P.G[P.densest]; ++b) {
         sum += pt[b].sum;
         cnt += pt[b].cnt;
     }
-    *P.efin = cnt > 0 ? (sum * Fmt<FMT>::scale) / (float)cnt : 1.0f;
+    *P.efin = fitness_from<FMT>(sum, cnt);
     *P.nfin = cnt;
 }
 

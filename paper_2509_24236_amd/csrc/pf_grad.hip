@@ -21,8 +21,9 @@ struct GradPartial {
 };
 
 struct Partial2 {
-    float sum;
+    FixSum sum;
     int cnt;
+    int pad;
 };
 
 // State of the on-device polish (lives in track_frame's workspace).
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(VolView vv, const float* 
                     nv_out ? nv_out + b : nullptr);
 }
 
-// grid (P, S): FP32 fitness partials of FP64 poses (row-major [R | t]) on point chunks.
+// grid (P, S): exact fitness partials of FP64 poses (row-major [R | t]) on point chunks.
 template <int FMT, int LAYOUT>
 __global__ __launch_bounds__(kGradThreads) void k_pose_partials(VolView vv, const float* __restrict__ px,
                                                                 const float* __restrict__ py,
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(kGradThreads) void k_pose_partials(VolView vv, cons
     const int n = n_dev ? *n_dev : n_host;
     const int chunk = (n + S - 1) / S;
     const int q0 = s * chunk, q1 = min(n, q0 + chunk);
-    float sum[1] = {0.0f};
+    FixSum sum[1] = {0};
     int cnt[1] = {0};
     const float sc = vv.inv_vs;
     for (int q = q0 + (int)threadIdx.x; q < q1; q += kGradThreads)
@@ -288,15 +289,16 @@ __global__ __launch_bounds__(kGradThreads) void k_pose_partials(VolView vv, cons
     }
 }
 
-__device__ inline float fitness_of(const Partial2* pt, int S, float scale, int* cnt_out) {
-    float sum = 0.0f;
+template <int FMT>
+__device__ inline float fitness_of(const Partial2* pt, int S, int* cnt_out) {
+    FixSum sum = 0;
     int cnt = 0;
     for (int s = 0; s < S; ++s) {
         sum += pt[s].sum;
         cnt += pt[s].cnt;
     }
     if (cnt_out) *cnt_out = cnt;
-    return cnt > 0 ? (sum * scale) / (float)cnt : 1.0f;
+    return fitness_from<FMT>(sum, cnt);
 }
 
 // Best candidate: the lowest fitness among P^(I) (E*) and the particles of iteration I (fit[1..K],
@@ -396,7 +398,7 @@ template <int FMT>
 __global__ void k_polish_pick(PolishState* ps, const Partial2* cp, int S) {
     if (ps->stop) return;
     for (int h = 0; h < 6; ++h) {
-        const float Eh = fitness_of(cp + (size_t)h * S, S, Fmt<FMT>::scale, nullptr);
+        const float Eh = fitness_of<FMT>(cp + (size_t)h * S, S, nullptr);
         if ((double)Eh <= ps->E - 1e-4 * ps->alpha[h] * ps->gg) {
             for (int q = 0; q < 12; ++q) ps->P[q] = ps->cand[h][q];
             ps->accepted += 1;
@@ -511,7 +513,7 @@ int polish_accepted_offset() { return (int)offsetof(PolishState, accepted); }
 template <int FMT>
 __global__ void k_final_pose(const Partial2* pt, int S, float* E_out, int* n_out) {
     int cnt;
-    *E_out = fitness_of(pt, S, Fmt<FMT>::scale, &cnt);
+    *E_out = fitness_of<FMT>(pt, S, &cnt);
     *n_out = cnt;
 }
 

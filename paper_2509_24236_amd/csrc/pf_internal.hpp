@@ -114,9 +114,10 @@ int32_t launch_tsdf_integrate(const pf_tsdf* v, const float* depth, const pf_int
 int32_t launch_tsdf_export(const pf_tsdf* v, float* T, float* W, hipStream_t s);
 int32_t launch_tsdf_import(const pf_tsdf* v, const float* T, const float* W, hipStream_t s);
 
-// Scores poses [K][12] (camera -> world float32) into fitness / n_valid.
+// Scores poses [K][12] (camera -> world float32) into fitness / n_valid. With an optimizer state,
+// the launch shape follows the spread of the search size that drew the poses.
 int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
-                     hipStream_t s);
+                     hipStream_t s, const pf_track_state* st = nullptr);
 
 // Largest number of per-workgroup partial sums the single-pose passes use.
 constexpr int kMaxPartials = 256;

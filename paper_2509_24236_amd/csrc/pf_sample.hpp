@@ -1,6 +1,13 @@
 // Per-sample evaluation of the fitness equation (Sec. III-B) for the three storage formats and
-// the two layouts, and the deterministic workgroup reduction of (sum, count) pairs. Shared by
-// the scoring, update and gradient kernels so every path evaluates a pose identically.
+// the two layouts, and the workgroup reduction of (sum, count) pairs. Shared by the scoring,
+// update and gradient kernels so every path evaluates a pose identically.
+//
+// Sums of |T| are exact: each FP32 sample value is converted to a 32-bit fixed-point integer
+// (2^-32 units of the normalised TSDF; 2^-17 stored units for int16) and added in 64-bit
+// integers. Integer addition is associative, so a pose's fitness does not depend on how the
+// points were split over lanes, waves, workgroups or launches: every launch shape, the batched
+// path and the single-problem path give the same bits. The conversion error is below 2^-32 per
+// sample, far under FP32 accumulation error.
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -15,12 +22,16 @@ namespace pf {
 template <int FMT>
 struct Fmt;
 
+// `fix` maps a valid |value| (in stored units, always below the band limit) into [0, 2^32);
+// `unfix` maps the fixed-point sum back to normalised TSDF units.
 template <>
 struct Fmt<PF_F32_W_F32> {
     using T = float;
     __device__ static inline float val(float a) { return a; }
     __device__ static inline bool in_band(float a) { return fabsf(a) < 1.0f; }
     static constexpr float scale = 1.0f;
+    static constexpr float fix = 4294967296.0f;                  // 2^32
+    static constexpr double unfix = 1.0 / 4294967296.0;
 };
 
 template <>
@@ -29,6 +40,8 @@ struct Fmt<PF_F16_W_U8> {
     __device__ static inline float val(__half a) { return __half2float(a); }
     __device__ static inline bool in_band(float a) { return fabsf(a) < 1.0f; }
     static constexpr float scale = 1.0f;
+    static constexpr float fix = 4294967296.0f;
+    static constexpr double unfix = 1.0 / 4294967296.0;
 };
 
 template <>
@@ -37,7 +50,20 @@ struct Fmt<PF_I16_W_U8> {
     __device__ static inline float val(int16_t a) { return (float)a; }
     __device__ static inline bool in_band(float a) { return fabsf(a) < 32767.0f; }
     static constexpr float scale = 1.0f / 32767.0f;
+    static constexpr float fix = 131072.0f;                      // 2^17: 32767 * 2^17 < 2^32
+    static constexpr double unfix = 1.0 / (131072.0 * 32767.0);
 };
+
+using FixSum = unsigned long long;
+
+// Largest float below 2^32: a clamp that keeps the conversion defined whatever the input.
+constexpr float kFixMax = 4294967040.0f;
+
+// E from an exact (sum, count) pair; E = 1 for an empty valid set.
+template <int FMT>
+__device__ inline float fitness_from(FixSum sum, int cnt) {
+    return cnt > 0 ? (float)((double)sum * Fmt<FMT>::unfix / (double)cnt) : 1.0f;
+}
 
 // Gathers the 8 stencil corners of cell (cx, cy, cz) (already clamped into the grid) in the order
 // (dx, dy, dz) = 000 100 010 110 001 101 011 111.
@@ -112,12 +138,12 @@ __device__ inline GridPose fold_pose(const float* P, float inv_vs, float gx0, fl
 
 // Evaluates one point (already divided by the voxel size) against NP poses in three phases:
 // the cell of every pose, then all gathers, then validity and interpolation, so that the gathers
-// of all poses are in flight together. Branch-free: the cell is clamped into the grid so every
-// gather is in bounds, and an out-of-grid sample is rejected afterwards. Adds |value| (in stored
-// units) and 1 to (sum[j], cnt[j]) for every valid sample.
+// of all poses are in flight together. The cell is clamped into the grid so every gather is in
+// bounds, and an out-of-grid sample is rejected afterwards. Adds |value| (fixed point) and 1 to
+// (sum[j], cnt[j]) for every valid sample.
 template <int FMT, int LAYOUT, int NP>
 __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, unsigned ly, unsigned lz,
-                                  const GridPose (&g)[NP], float x, float y, float z, float (&sum)[NP],
+                                  const GridPose (&g)[NP], float x, float y, float z, FixSum (&sum)[NP],
                                   int (&cnt)[NP]) {
     using ST = typename Fmt<FMT>::T;
     const ST* p[NP];
@@ -142,10 +168,30 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     // keep the phases apart: the scheduler would otherwise interleave them pose by pose and
     // leave only one pose's gathers in flight
     __builtin_amdgcn_sched_barrier(0);
+    // A pose that lands in the same cell as the previous pose reuses its corners instead of
+    // gathering them again. Late in an optimization the search size has contracted so far that
+    // neighbouring particles sample the same cells almost everywhere, and the loads of a whole
+    // wavefront are then skipped; the values are identical either way.
+    // The copy is made after all gathers were issued: the flag that selects it is passed through
+    // an empty asm statement so the compiler cannot fold the copy into the branch, where it would
+    // wait for the previous pose's gather before issuing the next one.
     float c[NP][8];
+    int dup[NP];
+    dup[0] = 0;
+    G.load(p[0], c[0]);
 #pragma unroll
-    for (int j = 0; j < NP; ++j) G.load(p[j], c[j]);
+    for (int j = 1; j < NP; ++j) {
+        dup[j] = p[j] == p[j - 1] ? 1 : 0;
+        if (!dup[j]) G.load(p[j], c[j]);
+    }
     __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 1; j < NP; ++j) {
+        int d = dup[j];
+        asm volatile("" : "+v"(d));
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[j][q] = d ? c[j - 1][q] : c[j][q];
+    }
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         bool ok = inb[j];
@@ -158,16 +204,16 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
         const float b0 = fmaf(f[j][1], a10 - a00, a00);
         const float b1 = fmaf(f[j][1], a11 - a01, a01);
         const float v = fmaf(f[j][2], b1 - b0, b0);
-        sum[j] += ok ? fabsf(v) : 0.0f;
+        const float a = ok ? fminf(fabsf(v) * Fmt<FMT>::fix, kFixMax) : 0.0f;
+        sum[j] += (FixSum)(unsigned)a;
         cnt[j] += ok ? 1 : 0;
     }
 }
 
-// Deterministic workgroup reduction of TK (sum, count) pairs; thread j < TK returns pair j in
-// s[0], c[0]. Order: per-lane sums, a fixed butterfly across the wave, then waves in order.
+// Workgroup reduction of TK exact (sum, count) pairs; thread j < TK returns pair j in s[0], c[0].
 template <int TK, int BLOCK>
-__device__ inline void block_reduce(float (&s)[TK], int (&c)[TK]) {
-    __shared__ float ls[TK][BLOCK / kWave];
+__device__ inline void block_reduce(FixSum (&s)[TK], int (&c)[TK]) {
+    __shared__ FixSum ls[TK][BLOCK / kWave];
     __shared__ int lc[TK][BLOCK / kWave];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
 #pragma unroll
@@ -185,7 +231,7 @@ __device__ inline void block_reduce(float (&s)[TK], int (&c)[TK]) {
     __syncthreads();
     if (threadIdx.x < TK) {
         const int j = threadIdx.x;
-        float a = 0.0f;
+        FixSum a = 0;
         int b = 0;
 #pragma unroll
         for (int w = 0; w < BLOCK / kWave; ++w) {

@@ -30,6 +30,39 @@ __global__ __launch_bounds__(BLOCK) void k_score(VolView vv, const float* __rest
                                        n_valid);
 }
 
+// Spread regime of the particles being scored, from the search size that drew them: the largest
+// displacement of a point 2 m from the rotation centre, in voxels. Wide spreads gather from cells
+// scattered over the band and are bound by L2 misses; tight spreads revisit the same cells and are
+// bound by the vector memory pipeline. Each regime has its own launch shape; the choice changes
+// speed only, since the sums are exact.
+constexpr double kSpreadLever = 2.0;                 // metres
+constexpr double kSpreadWide = 2.0, kSpreadTight = 0.05;   // voxels
+
+__device__ inline int spread_regime(const pf_track_state* st, double inv_vs) {
+    const double d = (st->s_rad * kSpreadLever + st->s_m) * inv_vs;
+    return d > kSpreadWide ? 0 : (d > kSpreadTight ? 1 : 2);
+}
+
+template <int FMT, int LAYOUT, int TK, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_score_regime(VolView vv, const float* __restrict__ px,
+                                                        const float* __restrict__ py, const float* __restrict__ pz,
+                                                        int n_host, const int* __restrict__ n_dev,
+                                                        const float* __restrict__ poses, int K,
+                                                        float* __restrict__ fitness, int* __restrict__ n_valid,
+                                                        const pf_track_state* st, int regime) {
+    if (spread_regime(st, (double)vv.inv_vs) != regime) return;
+    score_step<FMT, LAYOUT, TK, BLOCK>(vv, px, py, pz, n_dev ? *n_dev : n_host, poses, K, blockIdx.x * TK, fitness,
+                                       n_valid);
+}
+
+template <int FMT, int LAYOUT, int TK, int BLOCK>
+void launch_regime(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
+                   const pf_track_state* st, int regime, hipStream_t s) {
+    const int blocks = (K + TK - 1) / TK;
+    hipLaunchKernelGGL((k_score_regime<FMT, LAYOUT, TK, BLOCK>), dim3(blocks), dim3(BLOCK), 0, s, vv, p.x, p.y, p.z,
+                       p.n, p.n_dev, poses, K, fitness, n_valid, st, regime);
+}
+
 template <int FMT, int LAYOUT, int TK, int BLOCK>
 int32_t launch_t(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
                  hipStream_t s) {
@@ -40,8 +73,8 @@ int32_t launch_t(const VolView& vv, const Points& p, const float* poses, int K, 
 }
 
 // Launch shape of the many-pose scoring launches (pf_score_config): poses per workgroup and
-// workgroup size. The per-pose reduction order depends on the workgroup size only.
-int g_tk = 4, g_block = 256;
+// workgroup size, or 0 and 0 for the shape by spread regime (the default).
+int g_tk = 0, g_block = 0;
 
 template <int FMT, int LAYOUT>
 int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
@@ -53,13 +86,30 @@ int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K,
     PF_SHAPE(1, 256) PF_SHAPE(2, 256) PF_SHAPE(8, 256)
     PF_SHAPE(1, 512) PF_SHAPE(2, 512) PF_SHAPE(4, 512) PF_SHAPE(8, 512)
     PF_SHAPE(2, 128) PF_SHAPE(4, 128) PF_SHAPE(8, 128)
+    PF_SHAPE(2, 64) PF_SHAPE(4, 64) PF_SHAPE(8, 64)
 #undef PF_SHAPE
     return launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, s);
 }
 
+// One launch per regime; each reads the search size and all but one return at once.
+template <int FMT, int LAYOUT>
+int32_t launch_fl_state(const VolView& vv, const Points& p, const float* poses, int K, float* fitness,
+                        int* n_valid, const pf_track_state* st, hipStream_t s) {
+    if (K <= 64 || g_tk != 0) return launch_fl<FMT, LAYOUT>(vv, p, poses, K, fitness, n_valid, s);
+    launch_regime<FMT, LAYOUT, 2, 64>(vv, p, poses, K, fitness, n_valid, st, 0, s);
+    launch_regime<FMT, LAYOUT, 4, 128>(vv, p, poses, K, fitness, n_valid, st, 1, s);
+    launch_regime<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, 2, s);
+    return check_launch("particles_score");
+}
+
 template <int FMT>
 int32_t launch_fmt(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
-                   hipStream_t s) {
+                   const pf_track_state* st, hipStream_t s) {
+    if (st) {
+        if (vv.layout == PF_LAYOUT_CELLS)
+            return launch_fl_state<FMT, PF_LAYOUT_CELLS>(vv, p, poses, K, fitness, n_valid, st, s);
+        return launch_fl_state<FMT, PF_LAYOUT_LINEAR>(vv, p, poses, K, fitness, n_valid, st, s);
+    }
     if (vv.layout == PF_LAYOUT_CELLS) return launch_fl<FMT, PF_LAYOUT_CELLS>(vv, p, poses, K, fitness, n_valid, s);
     return launch_fl<FMT, PF_LAYOUT_LINEAR>(vv, p, poses, K, fitness, n_valid, s);
 }
@@ -67,9 +117,13 @@ int32_t launch_fmt(const VolView& vv, const Points& p, const float* poses, int K
 }  // namespace
 
 int32_t score_config(int tk, int block) {
+    if (tk == 0 && block == 0) {
+        g_tk = g_block = 0;
+        return PF_OK;
+    }
     const bool ok_tk = tk == 1 || tk == 2 || tk == 4 || tk == 8;
-    const bool ok_b = block == 128 || block == 256 || block == 512;
-    if (!ok_tk || !ok_b || (tk == 1 && block == 128))
+    const bool ok_b = block == 64 || block == 128 || block == 256 || block == 512;
+    if (!ok_tk || !ok_b || (tk == 1 && block < 256))
         return set_error(PF_EINVAL, "pf_score_config: unsupported shape (%d poses, %d threads)", tk, block);
     g_tk = tk;
     g_block = block;
@@ -77,11 +131,11 @@ int32_t score_config(int tk, int block) {
 }
 
 int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
-                     hipStream_t s) {
+                     hipStream_t s, const pf_track_state* st) {
     switch (vv.format) {
-        case PF_F32_W_F32: return launch_fmt<PF_F32_W_F32>(vv, p, poses, K, fitness, n_valid, s);
-        case PF_F16_W_U8: return launch_fmt<PF_F16_W_U8>(vv, p, poses, K, fitness, n_valid, s);
-        case PF_I16_W_U8: return launch_fmt<PF_I16_W_U8>(vv, p, poses, K, fitness, n_valid, s);
+        case PF_F32_W_F32: return launch_fmt<PF_F32_W_F32>(vv, p, poses, K, fitness, n_valid, st, s);
+        case PF_F16_W_U8: return launch_fmt<PF_F16_W_U8>(vv, p, poses, K, fitness, n_valid, st, s);
+        case PF_I16_W_U8: return launch_fmt<PF_I16_W_U8>(vv, p, poses, K, fitness, n_valid, st, s);
         default: return set_error(PF_EUNSUPPORTED, "particles_score: unsupported format %d", vv.format);
     }
 }

@@ -143,8 +143,9 @@ struct IterRec {
 };
 
 struct Partial {
-    float sum;
+    FixSum sum;
     int cnt;
+    int pad;
 };
 
 __host__ __device__ inline size_t partials_offset(int K) {
@@ -256,7 +257,7 @@ __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px,
     const unsigned lx = (unsigned)(vv.nx - 1), ly = (unsigned)(vv.ny - 1), lz = (unsigned)(vv.nz - 1);
     const int chunk = (n + nblk - 1) / nblk;
     const int q0 = blk * chunk, q1 = min(n, q0 + chunk);
-    float sum[1] = {0.0f};
+    FixSum sum[1] = {0};
     int cnt[1] = {0};
     const float sc = vv.inv_vs;
     for (int q = q0 + (int)threadIdx.x; q < q1; q += kAdvThreads)
@@ -283,13 +284,13 @@ __device__ inline void next_step(pf_track_state* st, int K, int n_partials, int 
     __shared__ float sh_E;
     if (!FIRST && threadIdx.x == 0) {
         const Partial* pt = state_partials(st, K);
-        float sum = 0.0f;
+        FixSum sum = 0;
         int cnt = 0;
         for (int b = 0; b < n_partials; ++b) {
             sum += pt[b].sum;
             cnt += pt[b].cnt;
         }
-        const float Es = cnt > 0 ? (sum * Fmt<FMT>::scale) / (float)cnt : 1.0f;
+        const float Es = fitness_from<FMT>(sum, cnt);
         const double f = st->beta + (1.0 - st->beta) * (double)Es;
         sh_s[0] = st->s_rad_done * f;
         sh_s[1] = st->s_m_done * f;
@@ -375,21 +376,38 @@ __device__ inline void score_step(const VolView& vv, const float* __restrict__ p
     for (int j = 0; j < TK; ++j)
         g[j] = fold_pose(poses + (size_t)min(k0 + j, K - 1) * 12, vv.inv_vs, vv.gx0, vv.gy0, vv.gz0);
     const unsigned lx = (unsigned)(vv.nx - 1), ly = (unsigned)(vv.ny - 1), lz = (unsigned)(vv.nz - 1);
-    float sum[TK];
+    FixSum sum[TK];
     int cnt[TK];
 #pragma unroll
     for (int j = 0; j < TK; ++j) {
-        sum[j] = 0.0f;
+        sum[j] = 0;
         cnt[j] = 0;
     }
     const float s = vv.inv_vs;
-    for (int q = threadIdx.x; q < n; q += BLOCK)
-        eval_poses<FMT, LAYOUT, TK>(G, lx, ly, lz, g, px[q] * s, py[q] * s, pz[q] * s, sum, cnt);
+    // the next point is loaded while the current one's gathers are in flight, so every pass of
+    // the loop waits for one memory round trip instead of two
+    int q = threadIdx.x;
+    float nx = 0.0f, ny = 0.0f, nz = 0.0f;
+    if (q < n) {
+        nx = px[q];
+        ny = py[q];
+        nz = pz[q];
+    }
+    for (; q < n; q += BLOCK) {
+        const float x = nx * s, y = ny * s, z = nz * s;
+        const int qn = q + BLOCK;
+        if (qn < n) {
+            nx = px[qn];
+            ny = py[qn];
+            nz = pz[qn];
+        }
+        eval_poses<FMT, LAYOUT, TK>(G, lx, ly, lz, g, x, y, z, sum, cnt);
+    }
     block_reduce<TK, BLOCK>(sum, cnt);
     if (threadIdx.x < TK) {
         const int k = k0 + threadIdx.x;
         if (k < K) {
-            fitness[k] = cnt[0] > 0 ? (sum[0] * Fmt<FMT>::scale) / (float)cnt[0] : 1.0f;
+            fitness[k] = fitness_from<FMT>(sum[0], cnt[0]);
             n_valid[k] = cnt[0];
         }
     }

@@ -286,7 +286,7 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
         const int r = (i - 1) % p->n_rates;
         const Points& S = views[r];
         if (timed) (void)hipEventRecord(g_timing.ev[2 * (i - 1)], s);
-        if ((rc = launch_score(vv, S, poses, p->K + 1, fit, nv, s))) return rc;
+        if ((rc = launch_score(vv, S, poses, p->K + 1, fit, nv, s, st))) return rc;
         if (timed) (void)hipEventRecord(g_timing.ev[2 * (i - 1) + 1], s);
         if ((rc = launch_adv(true, vv, S, Gv[r], fit, st, p->K, s))) return rc;
         // the last iteration only completes (E*, s); its particles stay in `poses` / `fit`

@@ -166,7 +166,7 @@ def test_params_validation(pf):
     _rc(pf, rc, "K")
     assert L.particles_state_bytes(0) == 0
     # header, then the FP64 deltas at 512, then 256-byte aligned per-workgroup partials
-    assert L.particles_state_bytes(10) == 512 + 768 + 256 * 8
+    assert L.particles_state_bytes(10) == 512 + 768 + 256 * 16
 
 
 def test_batch_validation(pf):
@@ -194,3 +194,17 @@ def test_batch_validation(pf):
     h = L.track_batch_create(q, 2, C.byref(ok), C.c_void_p(0x6000), C.c_size_t(1 << 30), None)
     assert not h and "differs" in pf.last_error()
     assert L.track_batch_run(None, None) == pf.PF_EINVAL
+
+
+def test_score_config_validation(pf):
+    """Launch shapes: 0/0 (automatic) and the listed shapes are accepted; anything else is
+    rejected with PF_EINVAL. The call is host-only."""
+    L = pf.lib()
+    try:
+        for tk, blk in [(0, 0), (1, 256), (1, 512), (2, 64), (4, 128), (8, 512)]:
+            assert L.pf_score_config(tk, blk) == pf.PF_OK, (tk, blk)
+        for tk, blk in [(3, 256), (4, 96), (1, 128), (1, 64), (0, 256), (16, 256), (-1, 256)]:
+            assert L.pf_score_config(tk, blk) == pf.PF_EINVAL, (tk, blk)
+            assert b"pf_score_config" in L.pf_last_error()
+    finally:
+        L.pf_score_config(0, 0)

@@ -323,6 +323,59 @@ def test_track_frame_rates_and_stats(pf, orc, dev, cfg1, cfg1_vol):
     assert math.degrees(orc.rot_err(R, Ro)) <= 0.05 and np.linalg.norm(t - to) <= 1e-3
 
 
+SHAPES = [(1, 256), (2, 256), (4, 256), (8, 256), (1, 512), (2, 512), (4, 512), (8, 512), (2, 128), (4, 128),
+          (8, 128), (2, 64), (4, 64), (8, 64)]
+
+
+@pytest.mark.parametrize("spread_deg", [5.0, 0.01])
+def test_score_shapes_bitwise_identical(pf, orc, dev, cfg1, cfg1_vol, spread_deg):
+    """Fitness sums are exact, so every launch shape (and the few-pose path) gives the same bits."""
+    say(f"[shapes] 257 poses, spread {spread_deg} deg, {len(SHAPES)} launch shapes")
+    v, v32, T32 = cfg1_vol
+    gv = upload(pf, cfg1["vol"], T32, v.W, dev)
+    X, _ = orc.backproject(cfg1["depth2"], cfg1["intr"], 2)
+    xt = torch.as_tensor(X.astype(np.float32)).to(dev)
+    pts = (xt[:, 0].contiguous(), xt[:, 1].contiguous(), xt[:, 2].contiguous())
+    R, t = cfg1["gt2"]
+    poses = _poses_around(orc, R, t, 257, math.radians(spread_deg), spread_deg * 0.006, seed=77)
+    P = torch.as_tensor(pf.poses_to_f32(poses)).to(dev)
+    ref = None
+    try:
+        for tk, blk in SHAPES:
+            pf.score_config(tk, blk)
+            E, nv = pf.particles_score(gv, *pts, P)
+            got = (E.cpu().numpy().view(np.uint32), nv.cpu().numpy())
+            if ref is None:
+                ref = got
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (tk, blk)
+    finally:
+        pf.score_config(0, 0)
+    E64, nv64 = pf.particles_score(gv, *pts, P[:64].contiguous())
+    assert np.array_equal(E64.cpu().numpy().view(np.uint32), ref[0][:64])
+    assert np.array_equal(nv64.cpu().numpy(), ref[1][:64])
+
+
+def test_track_frame_automatic_shape_matches_fixed(pf, orc, dev, cfg1, cfg1_vol):
+    """track_frame picks the scoring shape per iteration from the spread on the device; the
+    result is bitwise that of any fixed shape."""
+    say("[shapes] track_frame automatic vs fixed launch shapes")
+    v, v32, T32 = cfg1_vol
+    gv = upload(pf, cfg1["vol"], T32, v.W, dev)
+    R0, t0 = cfg1["init2"]
+    prm = pf.TrackParams(seed=3, frame_index=1, n_iters=10, K=256, rates=(1,), pixel_stride=2, s1_deg=5.0, s1_m=0.03)
+    depth = torch.as_tensor(cfg1["depth2"]).to(dev)
+    R, t, st = pf.Tracker(cfg1["intr"], prm, device=dev).track(gv, depth, R0, t0)
+    try:
+        for tk, blk in [(4, 256), (2, 64), (8, 512)]:
+            pf.score_config(tk, blk)
+            Rf, tf, stf = pf.Tracker(cfg1["intr"], prm, device=dev).track(gv, depth, R0, t0)
+            assert np.array_equal(R, Rf) and np.array_equal(t, tf), (tk, blk)
+            assert list(st.n_adv[:10]) == list(stf.n_adv[:10])
+            assert list(st.Estar[:10]) == list(stf.Estar[:10])
+    finally:
+        pf.score_config(0, 0)
+
+
 # ----------------------------------------------------------------------------- full size
 @pytest.fixture(scope="module")
 def cfg2_full(orc):

@@ -35,7 +35,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(frames, vol_spec, intr, n_frames, seconds):
+def cpu_baseline(frames, vol_spec, intr, n_frames, seconds, schedule="fixed"):
     """Times the FP64 oracle on a bounded sample of the same workload: it fuses frame 0, then
     tracks (3072 particles x 20 iterations, rates 1/8, 1/16, 1/32) and fuses frames 1, 2, ...
     until `seconds` have elapsed. Throughput counts the same (K+1) x |S_i| samples per iteration
@@ -51,23 +51,27 @@ def cpu_baseline(frames, vol_spec, intr, n_frames, seconds):
     for t in range(1, n_frames):
         Rp, tp = est[-1]
         Rr, tr = frames["rel"][t]
-        prm = oracle.make_params(seed=14, frame_index=t, n_iters=20, K=3072, rates=(8, 16, 32), pixel_stride=1,
-                                 s1_deg=10.0, s1_m=0.10)
+        if schedule == "paper":
+            prm = oracle.make_params(seed=14, frame_index=t, n_iters=20, Ks=(1024, 3072, 10240), rates=(8, 16, 32),
+                                     pixel_stride=1, s1_deg=10.0, s1_m=0.10, stop_deg=0.05, stop_m=0.0005)
+        else:
+            prm = oracle.make_params(seed=14, frame_index=t, n_iters=20, K=3072, rates=(8, 16, 32), pixel_stride=1,
+                                     s1_deg=10.0, s1_m=0.10)
         depth = frames["depth"](t)
         t1 = time.perf_counter()
         R, tt, recs = ov.track_frame(depth, intr, Rp @ Rr, Rp @ tr + tp, prm)
         ov.integrate(depth, intr, R, tt)
         track_s += time.perf_counter() - t1
         est.append((R, tt))
-        evals += sum((prm.K + 1) * r.n_pts for r in recs)
+        evals += sum((r.n_particles + 1) * r.n_pts for r in recs)
         done += 1
         log(f"[bench] oracle frame {t}: {track_s:.1f} s so far")
         if time.perf_counter() - t0 >= seconds:
             break
     return {"value": evals / track_s, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
             "ms_per_frame": 1e3 * track_s / done,
-            "sample": f"FP64 oracle, same sequence: fusion of frame 0, then track (3072 particles x 20 iterations, "
-                      f"rates 1/8, 1/16, 1/32) + fuse of frames 1..{done} on a 512^3 volume ({track_s:.1f} s timed)"}
+            "sample": f"FP64 oracle, same sequence and schedule: fusion of frame 0, then track + fuse of frames "
+                      f"1..{done} on a 512^3 volume ({track_s:.1f} s timed)"}
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_score_sequence_counters.txt")
@@ -189,6 +193,54 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_regimes(args):
+    """Scoring kernel alone across the spread regimes of one frame's optimization: 3073 poses drawn
+    in a box of +-s around the true pose of frame 1 (s = 10, 1, 0.1, 0.001 deg with s/100 m), scored
+    on the rate-1/8 view against the 512^3 FP32 volume holding frame 0, with the launch shape the
+    automatic mode uses for that spread. Prints one JSON line; for counter runs (rocprofv3 --pmc),
+    every regime is launched 1 + args.steps times in order."""
+    import numpy as np
+    import torch
+    import paper_2509_24236_amd as pf
+    import synth
+    dev = torch.device("cuda:0")
+    f = synth.cfg2_frames(2)
+    intr, spec = f["intr"], f["vol"]
+    vol = pf.Tsdf(spec, device=dev)
+    vol.integrate(torch.as_tensor(f["depth"](0)).to(dev), intr, np.eye(3), np.zeros(3))
+    px, py, pz, n = pf.backproject(torch.as_tensor(f["depth"](1)).to(dev), intr, 1)
+    N = int(n[0].item())
+    x, y, z = px[:N:8].contiguous(), py[:N:8].contiguous(), pz[:N:8].contiguous()
+    Rg, tg = f["gt"][1]
+    rng = np.random.default_rng(0)
+    out = {"workload": "particles_score, 3073 poses x rate-1/8 view of frame 1 (%d points), 512^3 f32 cells"
+                       % x.numel(), "regimes": []}
+    for s_deg, shape in [(10.0, (2, 64)), (1.0, (2, 64)), (0.1, (4, 128)), (0.001, (4, 256))]:
+        poses = [(Rg, tg)]
+        for _ in range(3072):
+            r = rng.uniform(-1, 1, 3) * math.radians(s_deg)
+            poses.append((synth.rot(r) @ Rg, tg + rng.uniform(-1, 1, 3) * s_deg / 100.0))
+        P = torch.as_tensor(pf.poses_to_f32(poses)).to(dev)
+        pf.score_config(*shape)
+        E, nv = pf.particles_score(vol, x, y, z, P)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pf.particles_score(vol, x, y, z, P, E, nv)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[len(ts) // 2]
+        ev = 3073 * x.numel()
+        out["regimes"].append({"spread_deg": s_deg, "shape": list(shape), "ms": ms, "evals_per_s": ev / ms * 1e3,
+                               "algorithmic_GBps": BYTES_PER_EVAL * ev / ms / 1e6})
+        log(f"[regimes] spread {s_deg} deg, shape {shape}: {ms:.4f} ms, {ev / ms / 1e6:.1f} Gevals/s")
+    pf.score_config(0, 0)
+    print(json.dumps(out), flush=True)
+
+
 def dataclasses_asdict(x):
     import dataclasses
     return dataclasses.asdict(x)
@@ -202,9 +254,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true", help="run only a plain 1 GiB device copy")
-    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch"],
-                    help="sequence: the paper-scale sequence (the headline); batch: 64 heterogeneous problems")
+    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch", "regimes"],
+                    help="sequence: the paper-scale sequence (the headline); batch: 64 heterogeneous problems; "
+                         "regimes: the scoring kernel alone at four particle spreads (diagnostic)")
     ap.add_argument("--problems", type=int, default=64)
+    ap.add_argument("--schedule", default="fixed", choices=["fixed", "paper"],
+                    help="sequence: fixed = 3072 particles x 20 iterations (the headline configuration); paper = "
+                         "the alternating particle counts and early exit of Sec. IV-A")
     ap.add_argument("--tune", action="store_true", help="batch: run the autotuner first and record the plan")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -216,6 +272,9 @@ def main():
         return
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "regimes":
+        bench_regimes(args)
         return
 
     import numpy as np
@@ -233,14 +292,21 @@ def main():
     depth = [torch.as_tensor(frames["depth"](t)).to(dev) for t in range(n_frames)]
     rel = frames["rel"]
     K, I, rates = 3072, 20, (8, 16, 32)
-    params = pf.TrackParams(seed=14, frame_index=1, n_iters=I, K=K, rates=rates, pixel_stride=1, s1_deg=10.0,
-                            s1_m=0.10)
+    if args.schedule == "paper":
+        # Sec. IV-A's own schedule: K alternates 1024 / 3072 / 10240 with the rates, early exit
+        params = pf.TrackParams(seed=14, frame_index=1, n_iters=I, K=10240, Ks=(1024, 3072, 10240), rates=rates,
+                                pixel_stride=1, s1_deg=10.0, s1_m=0.10, stop_deg=0.05, stop_m=0.0005)
+    else:
+        params = pf.TrackParams(seed=14, frame_index=1, n_iters=I, K=K, rates=rates, pixel_stride=1, s1_deg=10.0,
+                                s1_m=0.10)
     vol = pf.Tsdf(spec, device=dev)
     trk = pf.Tracker(intr, params, device=dev)
     torch.cuda.synchronize()
 
     est = [(np.eye(3), np.zeros(3))]
     vol.integrate(depth[0], intr, *est[0])
+
+    iters_run = []
 
     def step(t):
         Rp, tp = est[t - 1]
@@ -250,6 +316,7 @@ def main():
         R, tt, st = trk.track(vol, depth[t], R0, t0)
         vol.integrate(depth[t], intr, R, tt)
         est.append((R, tt))
+        iters_run.append(st.n_iters)
         return st
 
     log(f"[bench] warmup {args.warmup} frames")
@@ -261,6 +328,7 @@ def main():
     log(f"[bench] timing {args.steps} frames")
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    del iters_run[:]
     for t in range(args.warmup + 1, args.warmup + args.steps + 1):
         step(t)
     torch.cuda.synchronize()
@@ -291,10 +359,15 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "paper-scale sequence: 640x480 depth, 512^3 FP32 TSDF at 1 cm (tau 4 cm), 3072 particles x "
-                        "20 iterations at point rates 1/8, 1/16, 1/32, then fusion; one step = one frame",
+                        "20 iterations at point rates 1/8, 1/16, 1/32, then fusion; one step = one frame"
+                        if args.schedule == "fixed" else
+                        "paper-scale sequence: 640x480 depth, 512^3 FP32 TSDF at 1 cm (tau 4 cm), particles "
+                        "alternating 1024 / 3072 / 10240 with point rates 1/8, 1/16, 1/32, at most 20 iterations, "
+                        "stop once the search size is below (0.05 deg, 0.5 mm), then fusion; one step = one frame",
             "frames_timed": args.steps,
-            "particles": K,
+            "particles": K if args.schedule == "fixed" else [1024, 3072, 10240],
             "iterations": I,
+            "mean_iterations_run": sum(iters_run) / max(1, len(iters_run)),
             "tsdf": "512^3 f32 T + f32 W, cell-major f32 replica for scoring",
         },
         "roofline": {
@@ -314,7 +387,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(frames, spec, intr, n_frames, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(frames, spec, intr, n_frames, args.cpu_seconds, args.schedule)
     print(json.dumps(out), flush=True)
 
 

@@ -103,13 +103,21 @@ typedef struct pf_track_params {
     int32_t compose_mode;   /* PF_COMPOSE_* */
     int32_t polish_steps;   /* gradient polish steps after the last iteration (0 = none) */
     int32_t min_valid;      /* stats.lost is set when the final pose has fewer valid samples */
+    /* The paper's own schedule (Sec. IV-A): the particle count alternates with the sampling rate
+     * (1024, 3072, 10240 there), and the optimization typically stops early. alt_K = 1: iteration
+     * i draws Ks[(i-1) mod n_rates] particles, each in 1 .. K (K is the capacity). stop_deg,
+     * stop_m > 0: the optimization ends after the first iteration whose updated search size
+     * s^(i+1) is below both (the stop rule is a reading; 0 = always run n_iters). */
+    int32_t alt_K;
+    int32_t Ks[3];
     int32_t reserved;       /* must be 0 */
+    double stop_deg, stop_m;
 } pf_track_params;
 
 /* Per-frame record written by track_frame (host). */
 typedef struct pf_track_stats {
     int32_t n_points;               /* valid back-projected points at the pixel stride */
-    int32_t n_iters;
+    int32_t n_iters;                /* iterations that ran */
     int32_t lost;                   /* 1 if the final valid count < min_valid */
     int32_t polish_accepted;        /* accepted polish steps */
     float E0[PF_MAX_ITERS];         /* E(P^(i-1)) on S_i */
@@ -121,6 +129,7 @@ typedef struct pf_track_stats {
     double s_m[PF_MAX_ITERS];       /* s^(i), translation part */
     float E_final;                  /* fitness of the returned pose on the densest view */
     int32_t n_valid_final;
+    int32_t n_particles[PF_MAX_ITERS]; /* K of iteration i */
 } pf_track_stats;
 
 /* Device-resident optimizer state used by particles_update. The layout is public so callers
@@ -148,7 +157,12 @@ typedef struct pf_track_state {
     int32_t n_sub;         /* |S_i| of the last completed iteration */
     int32_t n_valid_star;  /* |X| of P^(i) */
     int32_t flags;         /* bit 0: particles_update called with a K other than the state's */
+    int32_t K_cur;         /* particles drawn for the pending iteration (K unless alt_K) */
+    int32_t done;          /* 1 once the stop rule ended the optimization */
+    int32_t alt_K, n_rates;
+    int32_t Ks[3];
     int32_t reserved;
+    double stop_rad, stop_m;
 } pf_track_state;
 
 #define PF_STATE_DELTAS_OFFSET 512
@@ -248,21 +262,24 @@ int32_t pf_score_config(int32_t poses_per_group, int32_t group_size);
 size_t particles_state_bytes(int32_t K);
 
 /* Initialises the device state for one frame: P^(0) = init (host), s^(1) from p (degrees are
- * converted to radians), iteration 1, and draws the K particles of iteration 1 into
- * next_poses (device, [K+1][12] float32; slot 0 = P^(0)). */
+ * converted to radians), iteration 1, the particle schedule and stop size of p, and draws the
+ * particles of iteration 1 (K, or Ks[0] with alt_K) into next_poses (device, [K+1][12]
+ * float32; slot 0 = P^(0)). */
 int32_t particles_state_init(void* state, const pf_pose* init, const pf_track_params* p,
                              float* next_poses, void* stream);
 
 /* One step of the randomized optimization (Sec. III-B) after the pending particles of
- * iteration i were scored on the point set S_i (px, py, pz, n_pts) into fitness / n_valid
- * ([K+1], slot 0 = the current pose P^(i-1)):
+ * iteration i (state->K_cur of them) were scored on the point set S_i (px, py, pz, n_pts) into
+ * fitness / n_valid ([K_cur+1], slot 0 = the current pose P^(i-1)):
  *   A = {k >= 1 : E_k < E_0} (strict); if A is non-empty, P^(i) = compose(mean over A of the
  *   rotation vectors and of the translations, P^(i-1)), else P^(i) = P^(i-1);
  *   E* = E(P^(i); S_i); s^(i+1) = s^(i) (beta + (1 - beta) E*);
- * then draws the K particles of iteration i+1: a in [-1,1)^6 from SplitMix64 at counter
- * t<<40 | (i+1)<<32 | k<<3 | d, rotation vector omega a[0:3], translation v a[3:6], composed
- * with P^(i) in FP64 and rounded to float32 into next_poses (slot 0 = P^(i)).
- * state: device buffer of particles_state_bytes(K) bytes; K must equal the K the state was
+ * then, unless s^(i+1) is below the stop size (state->done is then set and every later call
+ * returns without work), draws the particles of iteration i+1 (K, or Ks[i mod n_rates] with
+ * alt_K; state->K_cur): a in [-1,1)^6 from SplitMix64 at counter t<<40 | (i+1)<<32 | k<<3 | d,
+ * rotation vector omega a[0:3], translation v a[3:6], composed with P^(i) in FP64 and rounded to
+ * float32 into next_poses (slot 0 = P^(i)).
+ * state: device buffer of particles_state_bytes(K) bytes; K is the capacity the state was
  * initialised with (a mismatch sets bit 0 of state->flags and leaves the state unchanged). */
 int32_t particles_update(const pf_tsdf* v, const float* px, const float* py, const float* pz,
                          int32_t n_pts, const float* fitness, const int32_t* n_valid,
@@ -275,7 +292,9 @@ size_t track_workspace_bytes(const pf_intrinsics* K, const pf_track_params* p);
 
 /* Randomized optimization of one frame (Sec. III-B, schedule of Sec. IV-A): back-projects
  * the depth at the pixel stride, builds the sub-sampled views S_r[j] = M[j r], runs n_iters
- * iterations of particles_score + particles_update on the device, optionally polishes the best
+ * iterations of particles_score + particles_update on the device (fewer when the stop size ends
+ * the optimization; the launches of the remaining iterations return at once, with no host
+ * synchronisation), optionally polishes the best
  * candidate (polish_steps > 0: the lowest fitness among P^(I) and the particles of iteration I,
  * ties to P^(I) then the lowest index, refined by polish_steps gradient steps xi = -alpha grad E on
  * the densest view; the first alpha of a step moves no point more than half a voxel, Armijo

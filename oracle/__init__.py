@@ -70,12 +70,14 @@ class Params(C.Structure):
                 ("K", C.c_int32), ("n_rates", C.c_int32), ("rates", C.c_int32 * 3),
                 ("pixel_stride", C.c_int32), ("s1_deg", C.c_double), ("s1_m", C.c_double),
                 ("beta", C.c_double), ("compose_mode", C.c_int32), ("polish_steps", C.c_int32),
-                ("min_valid", C.c_int32)]
+                ("min_valid", C.c_int32), ("alt_K", C.c_int32), ("Ks", C.c_int32 * 3), ("stop_deg", C.c_double),
+                ("stop_m", C.c_double)]
 
 
 class IterRec(C.Structure):
     _fields_ = [("E0", C.c_double), ("Estar", C.c_double), ("s_rad", C.c_double), ("s_m", C.c_double),
-                ("n_adv", C.c_int64), ("n_pts", C.c_int64), ("nvalid0", C.c_int64), ("pose", Pose)]
+                ("n_adv", C.c_int64), ("n_pts", C.c_int64), ("nvalid0", C.c_int64), ("pose", Pose),
+                ("n_particles", C.c_int64)]
 
 
 _lib = None
@@ -125,7 +127,8 @@ def lib():
         L.orc_polish.restype = C.c_int32
         L.orc_polish.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, C.c_int32, dp]
         L.orc_track_frame.restype = C.c_int64
-        L.orc_track_frame.argtypes = [P(Vol), P(C.c_float), P(Intr), P(Pose), P(Params), P(Pose), P(IterRec)]
+        L.orc_track_frame.argtypes = [P(Vol), P(C.c_float), P(Intr), P(Pose), P(Params), P(Pose), P(IterRec),
+                                      P(C.c_int32)]
         L.orc_grid_search.restype = C.c_int64
         L.orc_grid_search.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, C.c_double, C.c_double, C.c_int32, dp]
         _lib = L
@@ -343,16 +346,18 @@ class Volume:
         return R2, t2, sr.value, sm.value, E, nv, rec
 
     def track_frame(self, depth, intr, R0, t0, params: "Params"):
-        """Randomized optimization of one frame (Sec. III-B with the Sec. IV-A schedule)."""
+        """Randomized optimization of one frame (Sec. III-B with the Sec. IV-A schedule). Returns the
+        pose and the records of the iterations that ran (fewer than n_iters after an early exit)."""
         d = np.ascontiguousarray(depth, dtype=np.float32)
         out = Pose()
         recs = (IterRec * max(1, params.n_iters))()
+        done = C.c_int32(0)
         n = lib().orc_track_frame(C.byref(self.c()), d.ctypes.data_as(C.POINTER(C.c_float)), C.byref(Intr.of(intr)),
-                                  C.byref(Pose.of(R0, t0)), C.byref(params), C.byref(out), recs)
+                                  C.byref(Pose.of(R0, t0)), C.byref(params), C.byref(out), recs, C.byref(done))
         if n < 0:
             raise MemoryError("oracle track_frame: allocation failed")
         R, t = out.rt()
-        return R, t, [recs[i] for i in range(params.n_iters)]
+        return R, t, [recs[i] for i in range(done.value)]
 
     def grid_search(self, xyz, R, t, m, rot_step, trans_step, mode=COMPOSE_DECOUPLED):
         x = _f64(xyz)
@@ -375,9 +380,18 @@ def advantage_update(E, deltas, R, t, mode=COMPOSE_DECOUPLED):
 
 
 def make_params(seed=3, frame_index=1, n_iters=10, K=256, rates=(1,), pixel_stride=2, s1_deg=5.0, s1_m=0.03,
-                beta=0.1, compose_mode=COMPOSE_DECOUPLED, polish_steps=0, min_valid=0) -> Params:
+                beta=0.1, compose_mode=COMPOSE_DECOUPLED, polish_steps=0, min_valid=0, Ks=None, stop_deg=0.0,
+                stop_m=0.0) -> Params:
+    """Ks: particle counts paired with the rates (iteration i draws Ks[(i-1) mod n_rates]); stop_deg /
+    stop_m: early exit once the updated search size is below both (0 = run all n_iters)."""
     p = Params()
     p.seed, p.frame_index, p.n_iters, p.K = seed, frame_index, n_iters, K
+    if Ks is not None:
+        assert len(Ks) == len(rates)
+        p.alt_K = 1
+        p.Ks[:] = (list(Ks) + [0, 0, 0])[:3]
+        p.K = max(Ks)
+    p.stop_deg, p.stop_m = stop_deg, stop_m
     p.n_rates = len(rates)
     rr = list(rates) + [1] * (3 - len(rates))
     p.rates[:] = rr[:3]

@@ -390,12 +390,24 @@ typedef struct {
     int32_t pixel_stride;
     double s1_deg, s1_m, beta;
     int32_t compose_mode, polish_steps, min_valid;
+    /* the paper's own schedule (Sec. IV-A): the particle count alternates with the sampling rate,
+     * iteration i drawing Ks[(i - 1) mod n_rates] particles when alt_K is set; and the optimization
+     * stops once the updated search size is below (stop_deg, stop_m) in both parts (0 = never) */
+    int32_t alt_K;
+    int32_t Ks[3];
+    double stop_deg, stop_m;
 } orc_params;
+
+/* Particles drawn in iteration i. */
+static int32_t iter_K(const orc_params* prm, int32_t i) {
+    return prm->alt_K ? prm->Ks[(i - 1) % prm->n_rates] : prm->K;
+}
 
 typedef struct {      /* per-iteration record, filled for i = 1..n_iters */
     double E0, Estar, s_rad, s_m;
     int64_t n_adv, n_pts, nvalid0;
     orc_pose pose;
+    int64_t n_particles;  /* K of the iteration */
 } orc_iter_rec;
 
 /* Subsample view S_r of the compacted cloud: S_r[j] = M[j r], j = 0 .. ceil(n/r) - 1
@@ -423,7 +435,7 @@ void orc_draw_delta(uint64_t seed, int32_t t, int32_t i, int32_t k, double s_rad
  * components. If `Ek_out` is non-null the K+1 fitness values are stored (slot 0 = E_0). */
 void orc_ro_iteration(const orc_vol* V, const double* S, int64_t n, const orc_params* prm, int32_t i,
                       orc_pose* P, double* s_rad, double* s_m, double* Ek_out, int64_t* nv_out, orc_iter_rec* rec) {
-    int32_t K = prm->K;
+    int32_t K = iter_K(prm, i);
     orc_pose* poses = (orc_pose*)malloc(sizeof(orc_pose) * (size_t)(K + 1));
     double* dr = (double*)malloc(sizeof(double) * 6 * (size_t)(K + 1));
     double* E = (double*)malloc(sizeof(double) * (size_t)(K + 1));
@@ -467,6 +479,7 @@ void orc_ro_iteration(const orc_vol* V, const double* S, int64_t n, const orc_pa
         rec->s_rad = *s_rad;
         rec->s_m = *s_m;
         rec->pose = *P;
+        rec->n_particles = K;
     }
     *s_rad *= f;
     *s_m *= f;
@@ -791,7 +804,7 @@ int32_t orc_polish(const orc_vol* V, const double* xyz, int64_t n, orc_pose* P, 
  * Returns the number of points of the full cloud; -1 on allocation failure.
  * ---------------------------------------------------------------------------------------- */
 int64_t orc_track_frame(const orc_vol* V, const float* depth, const orc_intr* Kin, const orc_pose* init,
-                        const orc_params* prm, orc_pose* out, orc_iter_rec* recs) {
+                        const orc_params* prm, orc_pose* out, orc_iter_rec* recs, int32_t* iters_done) {
     int64_t npix = (int64_t)Kin->width * Kin->height;
     double* xyz = (double*)malloc(sizeof(double) * 3 * (size_t)npix);
     double* S = (double*)malloc(sizeof(double) * 3 * (size_t)npix);
@@ -799,8 +812,12 @@ int64_t orc_track_frame(const orc_vol* V, const float* depth, const orc_intr* Ki
     int64_t n = orc_backproject(depth, Kin, prm->pixel_stride, xyz, NULL);
     orc_pose P = *init;
     double s_rad = prm->s1_deg * M_PI / 180.0, s_m = prm->s1_m;
-    double* Ek = (double*)malloc(sizeof(double) * (size_t)(prm->K + 1));
+    const double stop_rad = prm->stop_deg * M_PI / 180.0;
+    int32_t Kmax = prm->K;
+    for (int q = 0; prm->alt_K && q < prm->n_rates; ++q) Kmax = prm->Ks[q] > Kmax ? prm->Ks[q] : Kmax;
+    double* Ek = (double*)malloc(sizeof(double) * (size_t)(Kmax + 1));
     orc_pose best = P;
+    int32_t done = 0;
     for (int32_t i = 1; i <= prm->n_iters; ++i) {
         int32_t r = prm->rates[(i - 1) % prm->n_rates];
         int64_t m = view(xyz, n, r, S);
@@ -809,20 +826,26 @@ int64_t orc_track_frame(const orc_vol* V, const float* depth, const orc_intr* Ki
         orc_iter_rec rec;
         orc_ro_iteration(V, S, m, prm, i, &P, &s_rad, &s_m, Ek, NULL, &rec);
         if (recs) recs[i - 1] = rec;
-        if (i == prm->n_iters) {
-            /* best of {P^(I)} (fitness E*) and the particles of iteration I (fitness E_k), all on
-             * S_I; ties go to P^(I), then to the lowest particle index */
+        done = i;
+        /* early exit: the updated search size s^(i+1) is below the stop size in both parts */
+        const int last = i == prm->n_iters ||
+                         (prm->stop_deg > 0.0 && prm->stop_m > 0.0 && s_rad < stop_rad && s_m < prm->stop_m);
+        if (last) {
+            /* best of {P^(i)} (fitness E*) and the particles of iteration i (fitness E_k), all on
+             * S_i; ties go to P^(i), then to the lowest particle index */
             double Eb = rec.Estar;
             best = P;
-            for (int32_t k = 1; k <= prm->K; ++k)
+            for (int32_t k = 1; k <= iter_K(prm, i); ++k)
                 if (Ek[k] < Eb) {
                     double dr[3], dt[3];
                     orc_draw_delta(prm->seed, prm->frame_index, i, k, sr_prev, sm_prev, dr, dt);
                     orc_compose(prm->compose_mode, dr, dt, &Pprev, &best);
                     Eb = Ek[k];
                 }
+            break;
         }
     }
+    if (iters_done) *iters_done = done;
     free(Ek);
     if (prm->polish_steps > 0 && n > 0 && prm->n_iters > 0) {
         /* polish the best candidate on the densest view */

@@ -53,7 +53,8 @@ class pf_track_params(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("frame_index", C.c_int32), ("n_iters", C.c_int32), ("K", C.c_int32),
                 ("n_rates", C.c_int32), ("rates", C.c_int32 * 3), ("pixel_stride", C.c_int32),
                 ("s1_deg", C.c_double), ("s1_m", C.c_double), ("beta", C.c_double), ("compose_mode", C.c_int32),
-                ("polish_steps", C.c_int32), ("min_valid", C.c_int32), ("reserved", C.c_int32)]
+                ("polish_steps", C.c_int32), ("min_valid", C.c_int32), ("alt_K", C.c_int32), ("Ks", C.c_int32 * 3),
+                ("reserved", C.c_int32), ("stop_deg", C.c_double), ("stop_m", C.c_double)]
 
 
 class pf_track_stats(C.Structure):
@@ -61,7 +62,8 @@ class pf_track_stats(C.Structure):
                 ("polish_accepted", C.c_int32), ("E0", C.c_float * MAX_ITERS), ("Estar", C.c_float * MAX_ITERS),
                 ("n_adv", C.c_int32 * MAX_ITERS), ("n_sub", C.c_int32 * MAX_ITERS),
                 ("n_valid", C.c_int32 * MAX_ITERS), ("s_rad", C.c_double * MAX_ITERS),
-                ("s_m", C.c_double * MAX_ITERS), ("E_final", C.c_float), ("n_valid_final", C.c_int32)]
+                ("s_m", C.c_double * MAX_ITERS), ("E_final", C.c_float), ("n_valid_final", C.c_int32),
+                ("n_particles", C.c_int32 * MAX_ITERS)]
 
 
 class pf_track_state(C.Structure):
@@ -70,7 +72,9 @@ class pf_track_state(C.Structure):
                 ("s_m_done", C.c_double), ("E0", C.c_double), ("Estar", C.c_double), ("mean", C.c_double * 6),
                 ("R_prev", C.c_double * 9), ("t_prev", C.c_double * 3), ("beta", C.c_double), ("seed", C.c_uint64), ("frame_index", C.c_int32), ("iter", C.c_int32),
                 ("iter_done", C.c_int32), ("K", C.c_int32), ("compose_mode", C.c_int32), ("n_adv", C.c_int32),
-                ("n_sub", C.c_int32), ("n_valid_star", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32)]
+                ("n_sub", C.c_int32), ("n_valid_star", C.c_int32), ("flags", C.c_int32), ("K_cur", C.c_int32),
+                ("done", C.c_int32), ("alt_K", C.c_int32), ("n_rates", C.c_int32), ("Ks", C.c_int32 * 3),
+                ("reserved", C.c_int32), ("stop_rad", C.c_double), ("stop_m", C.c_double)]
 
 
 class pf_batch_problem(C.Structure):
@@ -200,10 +204,20 @@ class TrackParams:
     compose_mode: int = COMPOSE_DECOUPLED
     polish_steps: int = 0
     min_valid: int = 0
+    Ks: Optional[Sequence[int]] = None   # particle counts paired with the rates (Sec. IV-A alternation)
+    stop_deg: float = 0.0                # early exit once s^(i+1) is below (stop_deg, stop_m); 0 = never
+    stop_m: float = 0.0
 
     def c(self) -> pf_track_params:
         p = pf_track_params()
         p.seed, p.frame_index, p.n_iters, p.K = self.seed, self.frame_index, self.n_iters, self.K
+        if self.Ks is not None:
+            if len(self.Ks) != len(self.rates):
+                raise ValueError("Ks pairs with the rates: give one particle count per rate")
+            p.alt_K = 1
+            p.Ks[:] = (list(self.Ks) + [0, 0, 0])[:3]
+            p.K = max(self.Ks)
+        p.stop_deg, p.stop_m = self.stop_deg, self.stop_m
         p.n_rates = len(self.rates)
         rr = list(self.rates) + [1] * (3 - len(self.rates))
         p.rates[:] = rr[:3]

@@ -138,6 +138,13 @@ int32_t check_params(const pf_track_params* p, const char* fn) {
     if (p->frame_index < 0 || p->frame_index >= (1 << 24))
         return set_error(PF_EINVAL, "%s: frame_index must be in 0..2^24-1", fn);
     if (p->polish_steps < 0 || p->polish_steps > 64) return set_error(PF_EINVAL, "%s: polish_steps not in 0..64", fn);
+    if (p->alt_K != 0 && p->alt_K != 1) return set_error(PF_EINVAL, "%s: alt_K must be 0 or 1", fn);
+    if (p->alt_K)
+        for (int r = 0; r < p->n_rates; ++r)
+            if (p->Ks[r] < 1 || p->Ks[r] > p->K)
+                return set_error(PF_EINVAL, "%s: Ks[%d] = %d not in 1..K (%d)", fn, r, p->Ks[r], p->K);
+    if (!(p->stop_deg >= 0.0) || !(p->stop_m >= 0.0) || !isfinite(p->stop_deg) || !isfinite(p->stop_m))
+        return set_error(PF_EINVAL, "%s: the stop size must be finite and >= 0", fn);
     if (p->reserved != 0) return set_error(PF_EINVAL, "%s: reserved field must be 0", fn);
     return PF_OK;
 }
@@ -154,6 +161,8 @@ int32_t check_problem(const pf_batch_problem& q, int idx) {
     if ((rc = check_params(&q.params, fn))) return rc;
     if (!q.depth) return set_error(PF_EINVAL, "%s: null depth", fn);
     if (q.params.polish_steps != 0) return set_error(PF_EUNSUPPORTED, "%s: polish is not batched", fn);
+    if (q.params.alt_K != 0 || q.params.stop_deg != 0.0 || q.params.stop_m != 0.0)
+        return set_error(PF_EUNSUPPORTED, "%s: the alternating particle count and the stop rule are not batched", fn);
     if (q.params.K < 64) return set_error(PF_EINVAL, "%s: K %d < 64", fn, q.params.K);
     return PF_OK;
 }

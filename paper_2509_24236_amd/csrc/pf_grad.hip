@@ -303,9 +303,9 @@ __device__ inline float fitness_of(const Partial2* pt, int S, int* cnt_out) {
 
 // Best candidate: the lowest fitness among P^(I) (E*) and the particles of iteration I (fit[1..K],
 // deltas in the state around P^(I-1)); ties go to P^(I), then to the lowest k.
-__global__ __launch_bounds__(256) void k_best(pf_track_state* st, int K, const float* __restrict__ fit,
-                                              PolishState* ps) {
+__global__ __launch_bounds__(256) void k_best(pf_track_state* st, const float* __restrict__ fit, PolishState* ps) {
     const double* dl = reinterpret_cast<const double*>(reinterpret_cast<const char*>(st) + PF_STATE_DELTAS_OFFSET);
+    const int K = st->K_cur;   // particles of the last iteration that ran
     float bv = INFINITY;
     int bk = K + 1;
     for (int k = 1 + threadIdx.x; k <= K; k += 256)
@@ -484,7 +484,7 @@ int32_t launch_polish(const VolView& vv, const Points& p, int S, pf_track_state*
     int* ps_stop = reinterpret_cast<int*>(base + offsetof(PolishState, stop));
     GradPartial* gp = reinterpret_cast<GradPartial*>(base + ((sizeof(PolishState) + 255) & ~(size_t)255));
     Partial2* cp = reinterpret_cast<Partial2*>(reinterpret_cast<char*>(gp) + ((S * sizeof(GradPartial) + 255) & ~(size_t)255));
-    hipLaunchKernelGGL(k_best, dim3(1), dim3(256), 0, s, st, K, fit, ps);
+    hipLaunchKernelGGL(k_best, dim3(1), dim3(256), 0, s, st, fit, ps);
     int32_t rc = check_launch("polish");
     if (rc) return rc;
     for (int it = 0; it < steps; ++it) {

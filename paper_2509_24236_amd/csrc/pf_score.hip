@@ -21,21 +21,12 @@
 namespace pf {
 namespace {
 
-template <int FMT, int LAYOUT, int TK, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_score(VolView vv, const float* __restrict__ px, const float* __restrict__ py,
-                                                 const float* __restrict__ pz, int n_host, const int* __restrict__ n_dev,
-                                                 const float* __restrict__ poses, int K, float* __restrict__ fitness,
-                                                 int* __restrict__ n_valid) {
-    score_step<FMT, LAYOUT, TK, BLOCK>(vv, px, py, pz, n_dev ? *n_dev : n_host, poses, K, blockIdx.x * TK, fitness,
-                                       n_valid);
-}
-
 // Spread regime of the particles being scored, from the search size that drew them: the largest
 // displacement of a point 2 m from the rotation centre, in voxels. Wide spreads gather from cells
 // scattered over the band and are bound by L2 misses; tight spreads revisit the same cells and are
 // bound by the vector memory pipeline. Each regime has its own launch shape; the choice changes
 // speed only, since the sums are exact.
-constexpr double kSpreadLever = 2.0;                 // metres
+constexpr double kSpreadLever = 2.0;                       // metres
 constexpr double kSpreadWide = 2.0, kSpreadTight = 0.05;   // voxels
 
 __device__ inline int spread_regime(const pf_track_state* st, double inv_vs) {
@@ -43,32 +34,24 @@ __device__ inline int spread_regime(const pf_track_state* st, double inv_vs) {
     return d > kSpreadWide ? 0 : (d > kSpreadTight ? 1 : 2);
 }
 
+// With an optimizer state, the launch returns at once when the stop rule has ended the
+// optimization, or when `regime` >= 0 and the particles' spread is in another regime.
 template <int FMT, int LAYOUT, int TK, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_score_regime(VolView vv, const float* __restrict__ px,
-                                                        const float* __restrict__ py, const float* __restrict__ pz,
-                                                        int n_host, const int* __restrict__ n_dev,
-                                                        const float* __restrict__ poses, int K,
-                                                        float* __restrict__ fitness, int* __restrict__ n_valid,
-                                                        const pf_track_state* st, int regime) {
-    if (spread_regime(st, (double)vv.inv_vs) != regime) return;
+__global__ __launch_bounds__(BLOCK) void k_score(VolView vv, const float* __restrict__ px, const float* __restrict__ py,
+                                                 const float* __restrict__ pz, int n_host, const int* __restrict__ n_dev,
+                                                 const float* __restrict__ poses, int K, float* __restrict__ fitness,
+                                                 int* __restrict__ n_valid, const pf_track_state* st, int regime) {
+    if (st && (st->done || (regime >= 0 && spread_regime(st, (double)vv.inv_vs) != regime))) return;
     score_step<FMT, LAYOUT, TK, BLOCK>(vv, px, py, pz, n_dev ? *n_dev : n_host, poses, K, blockIdx.x * TK, fitness,
                                        n_valid);
 }
 
 template <int FMT, int LAYOUT, int TK, int BLOCK>
-void launch_regime(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
-                   const pf_track_state* st, int regime, hipStream_t s) {
-    const int blocks = (K + TK - 1) / TK;
-    hipLaunchKernelGGL((k_score_regime<FMT, LAYOUT, TK, BLOCK>), dim3(blocks), dim3(BLOCK), 0, s, vv, p.x, p.y, p.z,
-                       p.n, p.n_dev, poses, K, fitness, n_valid, st, regime);
-}
-
-template <int FMT, int LAYOUT, int TK, int BLOCK>
 int32_t launch_t(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
-                 hipStream_t s) {
+                 const pf_track_state* st, int regime, hipStream_t s) {
     const int blocks = (K + TK - 1) / TK;
     hipLaunchKernelGGL((k_score<FMT, LAYOUT, TK, BLOCK>), dim3(blocks), dim3(BLOCK), 0, s, vv, p.x, p.y, p.z, p.n,
-                       p.n_dev, poses, K, fitness, n_valid);
+                       p.n_dev, poses, K, fitness, n_valid, st, regime);
     return check_launch("particles_score");
 }
 
@@ -76,42 +59,35 @@ int32_t launch_t(const VolView& vv, const Points& p, const float* poses, int K, 
 // workgroup size, or 0 and 0 for the shape by spread regime (the default).
 int g_tk = 0, g_block = 0;
 
+// The configured shape (pf_score_config); in automatic mode with an optimizer state, one launch
+// per spread regime, each reading the search size on the device (all but one return at once).
 template <int FMT, int LAYOUT>
 int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
-                  hipStream_t s) {
+                  const pf_track_state* st, hipStream_t s) {
     // few poses: spread the points over a wide workgroup
-    if (K <= 64) return launch_t<FMT, LAYOUT, 1, 1024>(vv, p, poses, K, fitness, n_valid, s);
-#define PF_SHAPE(TK, B) \
-    if (g_tk == TK && g_block == B) return launch_t<FMT, LAYOUT, TK, B>(vv, p, poses, K, fitness, n_valid, s);
+    if (K <= 64) return launch_t<FMT, LAYOUT, 1, 1024>(vv, p, poses, K, fitness, n_valid, st, -1, s);
+#define PF_SHAPE(TK, B)                 \
+    if (g_tk == TK && g_block == B)     \
+        return launch_t<FMT, LAYOUT, TK, B>(vv, p, poses, K, fitness, n_valid, st, -1, s);
     PF_SHAPE(1, 256) PF_SHAPE(2, 256) PF_SHAPE(8, 256)
     PF_SHAPE(1, 512) PF_SHAPE(2, 512) PF_SHAPE(4, 512) PF_SHAPE(8, 512)
     PF_SHAPE(2, 128) PF_SHAPE(4, 128) PF_SHAPE(8, 128)
     PF_SHAPE(2, 64) PF_SHAPE(4, 64) PF_SHAPE(8, 64)
 #undef PF_SHAPE
-    return launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, s);
-}
-
-// One launch per regime; each reads the search size and all but one return at once.
-template <int FMT, int LAYOUT>
-int32_t launch_fl_state(const VolView& vv, const Points& p, const float* poses, int K, float* fitness,
-                        int* n_valid, const pf_track_state* st, hipStream_t s) {
-    if (K <= 64 || g_tk != 0) return launch_fl<FMT, LAYOUT>(vv, p, poses, K, fitness, n_valid, s);
-    launch_regime<FMT, LAYOUT, 2, 64>(vv, p, poses, K, fitness, n_valid, st, 0, s);
-    launch_regime<FMT, LAYOUT, 4, 128>(vv, p, poses, K, fitness, n_valid, st, 1, s);
-    launch_regime<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, 2, s);
-    return check_launch("particles_score");
+    if (g_tk == 0 && st) {
+        int32_t rc = launch_t<FMT, LAYOUT, 2, 64>(vv, p, poses, K, fitness, n_valid, st, 0, s);
+        if (!rc) rc = launch_t<FMT, LAYOUT, 4, 128>(vv, p, poses, K, fitness, n_valid, st, 1, s);
+        if (!rc) rc = launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, 2, s);
+        return rc;
+    }
+    return launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, -1, s);
 }
 
 template <int FMT>
 int32_t launch_fmt(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
                    const pf_track_state* st, hipStream_t s) {
-    if (st) {
-        if (vv.layout == PF_LAYOUT_CELLS)
-            return launch_fl_state<FMT, PF_LAYOUT_CELLS>(vv, p, poses, K, fitness, n_valid, st, s);
-        return launch_fl_state<FMT, PF_LAYOUT_LINEAR>(vv, p, poses, K, fitness, n_valid, st, s);
-    }
-    if (vv.layout == PF_LAYOUT_CELLS) return launch_fl<FMT, PF_LAYOUT_CELLS>(vv, p, poses, K, fitness, n_valid, s);
-    return launch_fl<FMT, PF_LAYOUT_LINEAR>(vv, p, poses, K, fitness, n_valid, s);
+    if (vv.layout == PF_LAYOUT_CELLS) return launch_fl<FMT, PF_LAYOUT_CELLS>(vv, p, poses, K, fitness, n_valid, st, s);
+    return launch_fl<FMT, PF_LAYOUT_LINEAR>(vv, p, poses, K, fitness, n_valid, st, s);
 }
 
 }  // namespace

@@ -138,7 +138,7 @@ __device__ inline void view_step(const float* px, const float* py, const float* 
 // ------------------------------------------------------------------ optimizer state
 struct IterRec {
     float E0, Estar;
-    int n_adv, n_sub, n_valid, pad;
+    int n_adv, n_sub, n_valid, n_particles;
     double s_rad, s_m;
 };
 
@@ -181,15 +181,17 @@ __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px,
         if (blk == 0 && threadIdx.x == 0) st->flags |= 1;
         return;
     }
+    if (ADV && st->done) return;   // the stop rule ended the optimization
     __shared__ float pose_sh[12];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int n = n_dev ? *n_dev : n_host;
     if constexpr (ADV) {
         const double* dl = state_deltas(st);
         const float E0 = fitness[0];
+        const int Kc = st->K_cur;   // particles of the iteration just scored
         double acc[6] = {0, 0, 0, 0, 0, 0};
         int na = 0;
-        for (int k = 1 + threadIdx.x; k <= K; k += kAdvThreads) {
+        for (int k = 1 + threadIdx.x; k <= Kc; k += kAdvThreads) {
             if (fitness[k] < E0) {
 #pragma unroll
                 for (int d = 0; d < 6; ++d) acc[d] += dl[6 * k + d];
@@ -278,7 +280,7 @@ __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px,
 template <int FMT, bool FIRST>
 __device__ inline void next_step(pf_track_state* st, int K, int n_partials, int draw, float* next_poses, IterRec* recs,
                                  int blk) {
-    if (st->K != K) return;
+    if (st->K != K || st->done) return;
     __shared__ double sh_s[2];
     __shared__ int sh_cnt;
     __shared__ float sh_E;
@@ -314,6 +316,11 @@ __device__ inline void next_step(pf_track_state* st, int K, int n_partials, int 
         s_m = sh_s[1];
         it = (uint32_t)st->iter_done + 1u;
     }
+    // particles of iteration `it` (Sec. IV-A alternation pairs them with the sampling rate), and
+    // the stop rule on the updated search size s^(it)
+    const int K_it = st->alt_K ? st->Ks[(it - 1u) % (uint32_t)st->n_rates] : st->K;
+    const bool stop = !FIRST && st->stop_rad > 0.0 && st->stop_m > 0.0 && s_rad < st->stop_rad && s_m < st->stop_m;
+    if (stop) draw = 0;
     __syncthreads();   // every thread has read the state before it is rewritten below
     if (!FIRST && k == 0) {
         const int i = st->iter_done;
@@ -326,6 +333,7 @@ __device__ inline void next_step(pf_track_state* st, int K, int n_partials, int 
             r.n_valid = sh_cnt;
             r.s_rad = st->s_rad_done;
             r.s_m = st->s_m_done;
+            r.n_particles = st->K_cur;
         }
         st->Estar = (double)sh_E;
         st->n_valid_star = sh_cnt;
@@ -334,8 +342,10 @@ __device__ inline void next_step(pf_track_state* st, int K, int n_partials, int 
         st->s_rad = s_rad;
         st->s_m = s_m;
         st->iter = (int)it;
+        st->K_cur = K_it;
+        st->done = stop ? 1 : 0;
     }
-    if (draw && k <= K) {
+    if (draw && k <= K_it) {
         double* dl = state_deltas(st);
         if (k == 0) {
             store_pose12(next_poses, R, t);

@@ -144,6 +144,13 @@ pf_track_state make_state(const pf_pose* init, const pf_track_params* p) {
     h.iter = 1;
     h.K = p->K;
     h.compose_mode = p->compose_mode;
+    h.alt_K = p->alt_K;
+    h.n_rates = p->n_rates;
+    for (int r = 0; r < 3; ++r) h.Ks[r] = p->Ks[r];
+    h.K_cur = p->alt_K ? p->Ks[0] : p->K;
+    h.done = 0;
+    h.stop_rad = p->stop_deg * (M_PI / 180.0);
+    h.stop_m = p->stop_m;
     return h;
 }
 
@@ -285,8 +292,9 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
     for (int i = 1; i <= p->n_iters; ++i) {
         const int r = (i - 1) % p->n_rates;
         const Points& S = views[r];
+        const int K_i = p->alt_K ? p->Ks[r] : p->K;
         if (timed) (void)hipEventRecord(g_timing.ev[2 * (i - 1)], s);
-        if ((rc = launch_score(vv, S, poses, p->K + 1, fit, nv, s, st))) return rc;
+        if ((rc = launch_score(vv, S, poses, K_i + 1, fit, nv, s, st))) return rc;
         if (timed) (void)hipEventRecord(g_timing.ev[2 * (i - 1) + 1], s);
         if ((rc = launch_adv(true, vv, S, Gv[r], fit, st, p->K, s))) return rc;
         // the last iteration only completes (E*, s); its particles stay in `poses` / `fit`
@@ -320,12 +328,14 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return set_error(PF_EHIP, "track_frame: %s", hipGetErrorString(e));
     if (hs.flags) return set_error(PF_EINVAL, "track_frame: inconsistent optimizer state (flags %d)", hs.flags);
+    // iterations that ran (all n_iters unless the stop rule ended the optimization)
+    const int n_run = hs.iter_done;
     if (timed) {
-        for (int i = 0; i < p->n_iters; ++i) {
+        for (int i = 0; i < n_run; ++i) {
             float ms = 0.0f;
             if (hipEventElapsedTime(&ms, g_timing.ev[2 * i], g_timing.ev[2 * i + 1]) == hipSuccess) g_timing.ms += ms;
             g_timing.launches += 1;
-            g_timing.evals += (int64_t)(p->K + 1) * hr[i].n_sub;
+            g_timing.evals += (int64_t)(hr[i].n_particles + 1) * hr[i].n_sub;
         }
     }
     for (int q = 0; q < 9; ++q) out->R[q] = hs.R[q];
@@ -333,8 +343,8 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
     if (stats) {
         memset(stats, 0, sizeof *stats);
         stats->n_points = nall;
-        stats->n_iters = p->n_iters;
-        for (int i = 0; i < p->n_iters; ++i) {
+        stats->n_iters = n_run;
+        for (int i = 0; i < n_run; ++i) {
             stats->E0[i] = hr[i].E0;
             stats->Estar[i] = hr[i].Estar;
             stats->n_adv[i] = hr[i].n_adv;
@@ -342,6 +352,7 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
             stats->n_valid[i] = hr[i].n_valid;
             stats->s_rad[i] = hr[i].s_rad;
             stats->s_m[i] = hr[i].s_m;
+            stats->n_particles[i] = hr[i].n_particles;
         }
         stats->E_final = ef;
         stats->polish_accepted = accepted;

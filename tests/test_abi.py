@@ -167,6 +167,21 @@ def test_params_validation(pf):
     assert L.particles_state_bytes(0) == 0
     # header, then the FP64 deltas at 512, then 256-byte aligned per-workgroup partials
     assert L.particles_state_bytes(10) == 512 + 768 + 256 * 16
+    # the paper's schedule: Ks paired with the rates, each in 1..K; a finite, non-negative stop size
+    sched = pf.TrackParams(K=256, n_iters=10, rates=(1, 2, 3), pixel_stride=2, Ks=(64, 128, 256), stop_deg=0.05,
+                           stop_m=0.0005)
+    assert L.track_workspace_bytes(C.byref(intr), C.byref(sched.c())) > 0
+    for field, val in [("alt_K", 2), ("stop_deg", -1.0), ("stop_m", float("nan")), ("stop_deg", float("inf"))]:
+        c = sched.c()
+        setattr(c, field, val)
+        assert L.track_workspace_bytes(C.byref(intr), C.byref(c)) == 0, field
+    for r, val in [(0, 0), (1, 257), (2, -1)]:
+        c = sched.c()
+        c.Ks[r] = val
+        assert L.track_workspace_bytes(C.byref(intr), C.byref(c)) == 0, (r, val)
+    c = sched.c()
+    c.reserved = 1
+    assert L.track_workspace_bytes(C.byref(intr), C.byref(c)) == 0
 
 
 def test_batch_validation(pf):

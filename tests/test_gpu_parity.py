@@ -323,6 +323,26 @@ def test_track_frame_rates_and_stats(pf, orc, dev, cfg1, cfg1_vol):
     assert math.degrees(orc.rot_err(R, Ro)) <= 0.05 and np.linalg.norm(t - to) <= 1e-3
 
 
+def test_track_frame_paper_schedule_cfg1(pf, orc, dev, cfg1, cfg1_vol):
+    """Sec. IV-A's own schedule: the particle count alternates with the rate, and the optimization
+    stops once the updated search size is below (0.05 deg, 0.5 mm)."""
+    say("[schedule] cfg1, K 64/128/256 with rates 1/2/3, stop rule")
+    v, v32, T32 = cfg1_vol
+    gv = upload(pf, cfg1["vol"], T32, v.W, dev)
+    R0, t0 = cfg1["init2"]
+    kw = dict(seed=9, frame_index=2, n_iters=16, rates=(1, 2, 3), pixel_stride=2, s1_deg=5.0, s1_m=0.03,
+              stop_deg=0.05, stop_m=0.0005)
+    R, t, st = pf.Tracker(cfg1["intr"], pf.TrackParams(K=256, Ks=(64, 128, 256), **kw), device=dev).track(
+        gv, torch.as_tensor(cfg1["depth2"]).to(dev), R0, t0)
+    Ro, to, recs = v32.track_frame(cfg1["depth2"], cfg1["intr"], R0, t0, orc.make_params(Ks=(64, 128, 256), **kw))
+    dr, dt = math.degrees(orc.rot_err(R, Ro)), float(np.linalg.norm(t - to))
+    say(f"    iterations gpu {st.n_iters} oracle {len(recs)}; pose vs oracle {dr:.2e} deg {dt * 1e3:.3e} mm")
+    assert st.n_iters == len(recs) < 16
+    assert [st.n_particles[i] for i in range(st.n_iters)] == [r.n_particles for r in recs]
+    assert [st.n_sub[i] for i in range(st.n_iters)] == [r.n_pts for r in recs]
+    assert dr <= 0.05 and dt <= 1e-3
+
+
 SHAPES = [(1, 256), (2, 256), (4, 256), (8, 256), (1, 512), (2, 512), (4, 512), (8, 512), (2, 128), (4, 128),
           (8, 128), (2, 64), (4, 64), (8, 64)]
 
@@ -440,4 +460,24 @@ def test_fullsize_track_frame(pf, orc, dev, cfg2_full):
         f"{[r.n_adv for r in recs[:6]]}")
     assert dr <= 0.05 and dt <= 1e-3
     assert [st.n_sub[i] for i in range(20)] == [r.n_pts for r in recs]
+    del v32
+
+
+def test_fullsize_track_frame_paper_schedule(pf, orc, dev, cfg2_full):
+    say("[fullsize] track frame 1 with K 1024/3072/10240 at rates 8/16/32 and the stop rule")
+    f, ov = cfg2_full
+    T32 = ov.T.astype(np.float32)
+    gv = upload(pf, f["vol"], T32, ov.W, dev)
+    v32 = orc.Volume(f["vol"], T=T32.astype(np.float64), W=ov.W)
+    R0, t0 = f["rel"][1]
+    kw = dict(seed=14, frame_index=1, n_iters=20, rates=(8, 16, 32), pixel_stride=1, s1_deg=10.0, s1_m=0.10,
+              stop_deg=0.05, stop_m=0.0005)
+    R, t, st = pf.Tracker(f["intr"], pf.TrackParams(K=10240, Ks=(1024, 3072, 10240), **kw), device=dev).track(
+        gv, torch.as_tensor(f["depth"](1)).to(dev), R0, t0)
+    Ro, to, recs = v32.track_frame(f["depth"](1), f["intr"], R0, t0, orc.make_params(Ks=(1024, 3072, 10240), **kw))
+    dr, dt = math.degrees(orc.rot_err(R, Ro)), float(np.linalg.norm(t - to))
+    say(f"    iterations gpu {st.n_iters} oracle {len(recs)}; pose vs oracle {dr:.2e} deg {dt * 1e3:.3e} mm")
+    assert st.n_iters == len(recs)
+    assert [st.n_particles[i] for i in range(st.n_iters)] == [r.n_particles for r in recs]
+    assert dr <= 0.05 and dt <= 1e-3
     del v32

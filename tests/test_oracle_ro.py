@@ -263,3 +263,66 @@ def test_grad_interval_contains_exact(orc, mode):
     lo1, hi1 = vol.fitness_grad_interval_many(X, poses, mode, eps=1e-3, sign_eps=1e-3)
     assert np.all(lo1 <= lo + 1e-15) and np.all(hi1 >= hi - 1e-15)
     assert np.any(lo1 < lo) or np.any(hi1 > hi)
+
+
+# ----------------------------------------------------------------------------- the paper's schedule
+@pytest.fixture(scope="module")
+def cfg1_fused(orc):
+    d = synth.cfg1_inputs()
+    vol = orc.Volume(d["vol"])
+    vol.integrate(d["depth1"], d["intr"], np.eye(3), np.zeros(3))
+    return d, vol
+
+
+def _same_pose(a, b):
+    return np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_alternating_K_reduces_to_fixed_K(orc, cfg1_fused):
+    """Sec. IV-A alternates the particle count with the sampling rate. With every entry equal to
+    K the run is the fixed-K run bit for bit, and each iteration draws Ks[(i-1) mod 3]."""
+    d, vol = cfg1_fused
+    Ri, ti = d["init2"]
+    base = dict(seed=5, n_iters=6, rates=(1, 2, 3), pixel_stride=2)
+    fixed = vol.track_frame(d["depth2"], d["intr"], Ri, ti, orc.make_params(K=48, **base))
+    alt = vol.track_frame(d["depth2"], d["intr"], Ri, ti, orc.make_params(Ks=(48, 48, 48), **base))
+    assert _same_pose(fixed, alt)
+    assert [r.n_adv for r in fixed[2]] == [r.n_adv for r in alt[2]]
+    R, t, recs = vol.track_frame(d["depth2"], d["intr"], Ri, ti, orc.make_params(Ks=(16, 48, 80), **base))
+    assert [r.n_particles for r in recs] == [16, 48, 80, 16, 48, 80]
+    assert all(r.n_adv <= r.n_particles for r in recs)
+
+
+def test_alternating_K_first_iteration_is_the_fixed_run(orc, cfg1_fused):
+    """Iteration 1 only sees Ks[0]: the pose after it equals a one-iteration run with K = Ks[0]."""
+    d, vol = cfg1_fused
+    Ri, ti = d["init2"]
+    a = vol.track_frame(d["depth2"], d["intr"], Ri, ti,
+                        orc.make_params(seed=6, n_iters=3, Ks=(32, 64, 96), rates=(1, 1, 1)))
+    b = vol.track_frame(d["depth2"], d["intr"], Ri, ti, orc.make_params(seed=6, n_iters=3, K=32, rates=(1, 1, 1)))
+    assert a[2][0].n_adv == b[2][0].n_adv
+    assert np.array_equal(a[2][0].pose.rt()[0], b[2][0].pose.rt()[0])
+    assert a[2][0].Estar == b[2][0].Estar
+
+
+def test_early_exit_rule(orc, cfg1_fused):
+    """Stop once s^(i+1) = s^(i) (beta + (1 - beta) E*) is below the stop size in both parts: the run
+    ends at the first such i, and its pose is the fixed-I run with I = that i (same stream)."""
+    d, vol = cfg1_fused
+    Ri, ti = d["init2"]
+    base = dict(seed=7, K=64, rates=(1,), pixel_stride=2, s1_deg=5.0, s1_m=0.03)
+    full = vol.track_frame(d["depth2"], d["intr"], Ri, ti, orc.make_params(n_iters=12, **base))
+    assert len(full[2]) == 12                              # no stop size: all iterations run
+    stop_deg, stop_m = 0.05, 0.0005
+    R, t, recs = vol.track_frame(d["depth2"], d["intr"], Ri, ti,
+                                 orc.make_params(n_iters=12, stop_deg=stop_deg, stop_m=stop_m, **base))
+    n = len(recs)
+    nxt = [(r.s_rad * (0.1 + 0.9 * r.Estar), r.s_m * (0.1 + 0.9 * r.Estar)) for r in full[2]]
+    below = [sr < math.radians(stop_deg) and sm < stop_m for sr, sm in nxt]
+    assert n == below.index(True) + 1 and 1 < n < 12
+    ref = vol.track_frame(d["depth2"], d["intr"], Ri, ti, orc.make_params(n_iters=n, **base))
+    assert _same_pose((R, t), ref)
+    # a stop size above s^(2) ends the run after the first iteration
+    one = vol.track_frame(d["depth2"], d["intr"], Ri, ti, orc.make_params(n_iters=12, stop_deg=90.0, stop_m=1.0, **base))
+    assert len(one[2]) == 1
+    assert _same_pose(one[:2], vol.track_frame(d["depth2"], d["intr"], Ri, ti, orc.make_params(n_iters=1, **base))[:2])

@@ -79,12 +79,17 @@ SCORE_SOURCES = ("pf_sample.hpp", "pf_steps.hpp", "pf_score.hip", "pf_internal.h
 
 
 def score_source_hash():
-    """SHA-256 over the sources the scoring kernel is compiled from."""
+    """SHA-256 over the code (comments and blank space removed) of the sources the scoring kernel is
+    compiled from, so that an edit of a comment does not invalidate the counter summary."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in SCORE_SOURCES:
-        with open(os.path.join(ROOT, "paper_2509_24236_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2509_24236_amd", "csrc", name)) as f:
+            code = f.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()
 
 

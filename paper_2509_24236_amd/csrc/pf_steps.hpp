@@ -373,9 +373,8 @@ int n_partials_for(int cap);
 
 // ------------------------------------------------------------------ particle scoring
 // Workgroup of BLOCK threads scoring poses k0 .. k0+TK-1 over all n points: every lane keeps a
-// point in registers and evaluates it against the TK poses (uniform, in scalar registers); each
-// pose's (sum, count) is reduced once, in a fixed order that depends on BLOCK only, so the
-// result of a pose does not depend on TK or on which workgroup scores it.
+// point in registers and evaluates it against the TK poses (uniform, in scalar registers). The
+// sums are exact, so the result of a pose does not depend on TK, BLOCK or the workgroup.
 template <int FMT, int LAYOUT, int TK, int BLOCK>
 __device__ inline void score_step(const VolView& vv, const float* __restrict__ px, const float* __restrict__ py,
                                   const float* __restrict__ pz, int n, const float* __restrict__ poses, int K, int k0,

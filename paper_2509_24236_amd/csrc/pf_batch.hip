@@ -1,8 +1,9 @@
 // Batched tracking of many independent problems (frames or sequences with their own volumes,
-// resolutions and particle counts). Every step of the frame optimization is one launch over all
-// problems; the scoring launch is persistent (a fixed grid strides over the list of (problem,
-// pose group) items, longest problems first). The step bodies are the same device functions the
-// single-problem kernels run, so each problem reproduces track_frame bit for bit. The host
+// resolutions and particle counts). Every step of the frame optimization, and of the gradient
+// polish, is one launch over all problems; the scoring launch is persistent (a fixed grid strides
+// over the list of (problem, pose group) items, longest problems first). The step bodies are the
+// same device functions the single-problem kernels run, so each problem reproduces track_frame
+// bit for bit. The host
 // record holds the grid sizes, which makes track_batch_run a fixed kernel sequence: no host
 // synchronisation, copy or allocation, and therefore capturable into a HIP graph.
 #include <stdlib.h>
@@ -12,6 +13,7 @@
 #include <new>
 #include <vector>
 
+#include "pf_polish.hpp"
 #include "pf_steps.hpp"
 
 namespace pf {
@@ -44,6 +46,12 @@ struct BatchProb {
     IterRec* recs;
     float* efin;
     int* nfin;
+    // gradient polish (polish_steps > 0): state, gradient partials [S], candidate partials [6][S]
+    PolishState* ps;
+    GradPartial* gp;
+    Partial2* cp;
+    double vs;
+    int mode;
 };
 
 namespace {
@@ -131,10 +139,56 @@ __global__ void kb_final(const BatchProb* tab, int n) {
     *P.nfin = cnt;
 }
 
+// ---- gradient polish of every problem's best candidate (track_frame's launch_polish, batched)
+__global__ __launch_bounds__(256) void kb_best(const BatchProb* tab) {
+    const BatchProb& P = tab[blockIdx.x];
+    best_step(P.st, P.fit, P.ps);
+}
+
+template <int FMT, int LAYOUT>
+__global__ __launch_bounds__(kGradThreads) void kb_grad(const BatchProb* tab, const int4* items) {
+    const int4 w = items[blockIdx.x];
+    const BatchProb& P = tab[w.x];
+    if (P.ps->stop) return;   // a stopped polish ignores the gradient
+    const float *x, *y, *z;
+    const int* nd;
+    view_of(P, P.densest, x, y, z, nd);
+    grad_step<FMT, LAYOUT>(P.vv, x, y, z, *nd, P.ps->P, nullptr, P.mode, nullptr, nullptr, nullptr, P.gp, 0,
+                           P.G[P.densest], w.y);
+}
+
+template <int FMT>
+__global__ void kb_polish_prep(const BatchProb* tab) {
+    const BatchProb& P = tab[blockIdx.x];
+    polish_prep_step<FMT>(P.ps, P.gp, P.G[P.densest], P.mode, P.vs);
+}
+
+template <int FMT, int LAYOUT>
+__global__ __launch_bounds__(kGradThreads) void kb_pose_partials(const BatchProb* tab, const int4* items) {
+    const int4 w = items[blockIdx.x];
+    const BatchProb& P = tab[w.x];
+    if (P.ps->stop) return;
+    const float *x, *y, *z;
+    const int* nd;
+    view_of(P, P.densest, x, y, z, nd);
+    pose_partials_step<FMT, LAYOUT>(P.vv, x, y, z, *nd, &P.ps->cand[0][0], P.cp, w.y, P.G[P.densest], w.z);
+}
+
+template <int FMT>
+__global__ void kb_polish_pick(const BatchProb* tab) {
+    const BatchProb& P = tab[blockIdx.x];
+    polish_pick_step<FMT>(P.ps, P.cp, P.G[P.densest]);
+}
+
+__global__ void kb_polish_commit(const BatchProb* tab) {
+    const BatchProb& P = tab[blockIdx.x];
+    polish_commit_step(P.ps, P.st);
+}
+
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct ProbLayout {
-    size_t pts, counts, ncount, views[3], poses, fit, nv, state, recs, fin, end;
+    size_t pts, counts, ncount, views[3], poses, fit, nv, state, recs, fin, polish, end;
 };
 
 ProbLayout prob_layout(const pf_batch_problem& q, size_t off) {
@@ -163,6 +217,12 @@ ProbLayout prob_layout(const pf_batch_problem& q, size_t off) {
     off += al(PF_MAX_ITERS * sizeof(IterRec));
     L.fin = off;
     off += al(2 * sizeof(int));
+    L.polish = off;
+    if (p.polish_steps > 0) {
+        int rmin = p.rates[0];
+        for (int r = 1; r < p.n_rates; ++r) rmin = p.rates[r] < rmin ? p.rates[r] : rmin;
+        off += al(polish_scratch_bytes(n_partials_for((int)((npix + rmin - 1) / rmin))));
+    }
     L.end = off;
     return L;
 }
@@ -173,14 +233,15 @@ ProbLayout prob_layout(const pf_batch_problem& q, size_t off) {
 using namespace pf;
 
 struct pf_batch {
-    int n = 0, n_iters = 0, n_rates = 0, format = 0, layout = 0;
+    int n = 0, n_iters = 0, n_rates = 0, format = 0, layout = 0, polish_steps = 0;
     pf_batch_plan plan{};
     char* ws = nullptr;
     BatchProb* tab = nullptr;
     pf_track_state* init = nullptr;
     int4* items = nullptr;                  // all lists, back to back
     size_t off_bp = 0, off_view = 0, off_next = 0, off_score = 0, off_fin = 0, off_adv[3] = {0, 0, 0};
-    int n_bp = 0, n_view = 0, n_next = 0, n_score = 0, n_fin = 0, n_adv[3] = {0, 0, 0};
+    size_t off_grad = 0, off_pp = 0;
+    int n_bp = 0, n_view = 0, n_next = 0, n_score = 0, n_fin = 0, n_adv[3] = {0, 0, 0}, n_grad = 0, n_pp = 0;
     std::vector<BatchProb> host;
     std::vector<int> min_valid;
 };
@@ -216,6 +277,18 @@ int32_t run_t(pf_batch* b, hipStream_t s) {
         hipLaunchKernelGGL((kb_next<FMT, false>), dim3(b->n_next), dim3(256), 0, s, b->tab, b->items + b->off_next,
                            ph, i < b->n_iters ? 1 : 0);
     }
+    if (b->polish_steps > 0) {
+        hipLaunchKernelGGL(kb_best, dim3(b->n), dim3(256), 0, s, b->tab);
+        for (int it = 0; it < b->polish_steps; ++it) {
+            hipLaunchKernelGGL((kb_grad<FMT, LAYOUT>), dim3(b->n_grad), dim3(kGradThreads), 0, s, b->tab,
+                               b->items + b->off_grad);
+            hipLaunchKernelGGL(kb_polish_prep<FMT>, dim3(b->n), dim3(1), 0, s, b->tab);
+            hipLaunchKernelGGL((kb_pose_partials<FMT, LAYOUT>), dim3(b->n_pp), dim3(kGradThreads), 0, s, b->tab,
+                               b->items + b->off_pp);
+            hipLaunchKernelGGL(kb_polish_pick<FMT>, dim3(b->n), dim3(1), 0, s, b->tab);
+        }
+        hipLaunchKernelGGL(kb_polish_commit, dim3(b->n), dim3(1), 0, s, b->tab);
+    }
     hipLaunchKernelGGL((kb_adv<FMT, LAYOUT, false>), dim3(b->n_fin), dim3(256), 0, s, b->tab, b->items + b->off_fin,
                        0);
     hipLaunchKernelGGL(kb_final<FMT>, dim3((b->n + 63) / 64), dim3(64), 0, s, b->tab, b->n);
@@ -241,6 +314,7 @@ size_t track_batch_workspace_bytes(const pf_batch_problem* problems, int32_t n) 
         for (int r = 0; r < q.params.n_rates; ++r)
             items += (npix / q.params.rates[r] + 256) / 256 + (size_t)kMaxPartials;
         items += 2 * ((size_t)q.params.K + 256) / 256 + (size_t)q.params.K + 1 + kMaxPartials;
+        items += 7 * (size_t)kMaxPartials;   // polish: gradient and candidate chunks
     }
     return off + al(items * sizeof(int4));
 }
@@ -265,9 +339,10 @@ pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const 
     for (int p = 1; p < n; ++p) {
         const pf_batch_problem& q = problems[p];
         if (q.params.n_iters != q0.params.n_iters || q.params.n_rates != q0.params.n_rates ||
-            q.vol.format != q0.vol.format || q.vol.layout != q0.vol.layout) {
-            set_error(PF_EINVAL, "track_batch_create: problem %d differs from problem 0 in n_iters, n_rates, format "
-                                 "or layout", p);
+            q.params.polish_steps != q0.params.polish_steps || q.vol.format != q0.vol.format ||
+            q.vol.layout != q0.vol.layout) {
+            set_error(PF_EINVAL, "track_batch_create: problem %d differs from problem 0 in n_iters, n_rates, "
+                                 "polish_steps, format or layout", p);
             return nullptr;
         }
     }
@@ -286,6 +361,7 @@ pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const 
     b->n_rates = q0.params.n_rates;
     b->format = q0.vol.format;
     b->layout = q0.vol.layout;
+    b->polish_steps = q0.params.polish_steps;
     b->plan = *plan;
     b->ws = static_cast<char*>(workspace);
     b->tab = reinterpret_cast<BatchProb*>(b->ws);
@@ -334,6 +410,15 @@ pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const 
         P.recs = reinterpret_cast<IterRec*>(b->ws + L.recs);
         P.efin = reinterpret_cast<float*>(b->ws + L.fin);
         P.nfin = reinterpret_cast<int*>(b->ws + L.fin + sizeof(float));
+        P.vs = q.vol.voxel_size;
+        P.mode = q.params.compose_mode;
+        if (q.params.polish_steps > 0) {
+            // the same scratch layout as track_frame's polish
+            char* pb = b->ws + L.polish;
+            P.ps = reinterpret_cast<PolishState*>(pb);
+            P.gp = reinterpret_cast<GradPartial*>(pb + al(sizeof(PolishState)));
+            P.cp = reinterpret_cast<Partial2*>(reinterpret_cast<char*>(P.gp) + al(P.G[P.densest] * sizeof(GradPartial)));
+        }
         init[p] = initial_state(&q.init, &q.params);
         b->min_valid.push_back(q.params.min_valid);
     }
@@ -379,6 +464,17 @@ pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const 
         for (int k = 0; k < G; ++k) items.push_back(make_int4(p, k, G, 0));
     }
     b->n_fin = (int)(items.size() - b->off_fin);
+    if (b->polish_steps > 0) {
+        mark(b->off_grad);
+        for (int p = 0; p < n; ++p)
+            for (int k = 0; k < b->host[p].G[b->host[p].densest]; ++k) items.push_back(make_int4(p, k, 0, 0));
+        b->n_grad = (int)(items.size() - b->off_grad);
+        mark(b->off_pp);
+        for (int p = 0; p < n; ++p)
+            for (int h = 0; h < 6; ++h)
+                for (int k = 0; k < b->host[p].G[b->host[p].densest]; ++k) items.push_back(make_int4(p, h, k, 0));
+        b->n_pp = (int)(items.size() - b->off_pp);
+    }
     b->items = reinterpret_cast<int4*>(b->ws + off);
     if (off + items.size() * sizeof(int4) > ws_bytes) {
         delete b;
@@ -416,9 +512,13 @@ int32_t track_batch_results(pf_batch* b, pf_pose* out, pf_track_stats* stats, vo
     std::vector<pf_track_state> st(n);
     std::vector<IterRec> recs((size_t)n * PF_MAX_ITERS);
     std::vector<float> ef(n);
-    std::vector<int> nf(n), na(n);
+    std::vector<int> nf(n), na(n), acc(n, 0);
     for (int p = 0; p < n; ++p) {
         const BatchProb& P = b->host[p];
+        if (b->polish_steps > 0 &&
+            hipMemcpyAsync(&acc[p], reinterpret_cast<char*>(P.ps) + offsetof(PolishState, accepted), sizeof(int),
+                           hipMemcpyDeviceToHost, s) != hipSuccess)
+            return set_error(PF_EHIP, "track_batch_results: read-back failed");
         if (hipMemcpyAsync(&st[p], P.st, sizeof(pf_track_state), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipMemcpyAsync(&recs[(size_t)p * PF_MAX_ITERS], P.recs, sizeof(IterRec) * b->n_iters, hipMemcpyDeviceToHost,
                            s) != hipSuccess ||
@@ -450,6 +550,7 @@ int32_t track_batch_results(pf_batch* b, pf_pose* out, pf_track_stats* stats, vo
             }
             S.E_final = ef[p];
             S.n_valid_final = nf[p];
+            S.polish_accepted = acc[p];
             S.lost = nf[p] < b->min_valid[p] ? 1 : 0;
         }
     }

@@ -160,7 +160,6 @@ int32_t check_problem(const pf_batch_problem& q, int idx) {
     if ((rc = check_pose(&q.init, fn))) return rc;
     if ((rc = check_params(&q.params, fn))) return rc;
     if (!q.depth) return set_error(PF_EINVAL, "%s: null depth", fn);
-    if (q.params.polish_steps != 0) return set_error(PF_EUNSUPPORTED, "%s: polish is not batched", fn);
     if (q.params.alt_K != 0 || q.params.stop_deg != 0.0 || q.params.stop_m != 0.0)
         return set_error(PF_EUNSUPPORTED, "%s: the alternating particle count and the stop rule are not batched", fn);
     if (q.params.K < 64) return set_error(PF_EINVAL, "%s: K %d < 64", fn, q.params.K);

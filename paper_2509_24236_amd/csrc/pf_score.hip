@@ -59,6 +59,23 @@ int32_t launch_t(const VolView& vv, const Points& p, const float* poses, int K, 
 // workgroup size, or 0 and 0 for the shape by spread regime (the default).
 int g_tk = 0, g_block = 0;
 
+// Automatic shape of a regime for K poses: the regime's preferred shape (2x64 wide, 4x128 mid,
+// 4x256 tight, as measured at K = 3073), or, when that launch would hold fewer than one wave per
+// SIMD (1024 on MI355X), the first of 2x256, 1x256, 1x1024 that does: a few hundred poses must
+// spread their points over more waves to fill the chip. Shape codes: 0 = 2x64, 1 = 4x128,
+// 2 = 4x256, 3 = 2x256, 4 = 1x256, 5 = 1x1024.
+constexpr int kMinWaves = 1024;
+
+int auto_shape(int regime, int K) {
+    static const int tk[6] = {2, 4, 4, 2, 1, 1}, wpg[6] = {1, 2, 4, 4, 4, 16};
+    auto waves = [&](int c) { return (K + tk[c] - 1) / tk[c] * wpg[c]; };
+    const int pref = regime == 0 ? 0 : (regime == 1 ? 1 : 2);
+    if (waves(pref) >= kMinWaves) return pref;
+    for (int c : {3, 4, 5})
+        if (waves(c) >= kMinWaves) return c;
+    return 5;
+}
+
 // The configured shape (pf_score_config); in automatic mode with an optimizer state, one launch
 // per spread regime, each reading the search size on the device (all but one return at once).
 template <int FMT, int LAYOUT>
@@ -75,9 +92,17 @@ int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K,
     PF_SHAPE(2, 64) PF_SHAPE(4, 64) PF_SHAPE(8, 64)
 #undef PF_SHAPE
     if (g_tk == 0 && st) {
-        int32_t rc = launch_t<FMT, LAYOUT, 2, 64>(vv, p, poses, K, fitness, n_valid, st, 0, s);
-        if (!rc) rc = launch_t<FMT, LAYOUT, 4, 128>(vv, p, poses, K, fitness, n_valid, st, 1, s);
-        if (!rc) rc = launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, 2, s);
+        int32_t rc = PF_OK;
+        for (int regime = 0; regime < 3 && !rc; ++regime) {
+            switch (auto_shape(regime, K)) {
+                case 0: rc = launch_t<FMT, LAYOUT, 2, 64>(vv, p, poses, K, fitness, n_valid, st, regime, s); break;
+                case 1: rc = launch_t<FMT, LAYOUT, 4, 128>(vv, p, poses, K, fitness, n_valid, st, regime, s); break;
+                case 2: rc = launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, regime, s); break;
+                case 3: rc = launch_t<FMT, LAYOUT, 2, 256>(vv, p, poses, K, fitness, n_valid, st, regime, s); break;
+                case 4: rc = launch_t<FMT, LAYOUT, 1, 256>(vv, p, poses, K, fitness, n_valid, st, regime, s); break;
+                default: rc = launch_t<FMT, LAYOUT, 1, 1024>(vv, p, poses, K, fitness, n_valid, st, regime, s); break;
+            }
+        }
         return rc;
     }
     return launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, -1, s);

@@ -198,8 +198,15 @@ def test_batch_validation(pf):
     assert L.track_batch_workspace_bytes(q, 2) == 0
     assert "K 32 < 64" in pf.last_error()
     q[1].params.K = 256
-    q[1].params.polish_steps = 2
+    q[1].params.stop_deg, q[1].params.stop_m = 0.05, 0.0005     # the stop rule is not batched
     assert L.track_batch_workspace_bytes(q, 2) == 0
+    assert "not batched" in pf.last_error()
+    q[1].params.stop_deg, q[1].params.stop_m = 0.0, 0.0
+    q[1].params.polish_steps = 2               # polish is batched, with the same step count everywhere
+    assert L.track_batch_workspace_bytes(q, 2) > 0
+    h = L.track_batch_create(q, 2, C.byref(pf.pf_batch_plan(4, 1024, 1, 0)), C.c_void_p(0x6000),
+                             C.c_size_t(1 << 30), None)
+    assert not h and "differs" in pf.last_error()
     q[1].params.polish_steps = 0
     bad = pf.pf_batch_plan(3, 1024, 0, 0)
     h = L.track_batch_create(q, 2, C.byref(bad), C.c_void_p(0x6000), C.c_size_t(1 << 30), None)

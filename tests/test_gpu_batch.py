@@ -66,6 +66,22 @@ def test_batch_equals_plain(pf, problems, tk, grid, order):
     same(got, ref)
 
 
+def test_batch_polish_equals_plain(pf, problems):
+    """The batched gradient polish (form 3 inside form 2) reproduces track_frame's polish bit for bit."""
+    import dataclasses
+    say("[batch] 4 RO iterations + 5 polish steps, batched vs plain")
+    probs = [(v, d, k, R, t, dataclasses.replace(prm, n_iters=4, polish_steps=5)) for v, d, k, R, t, prm in problems]
+    ref = plain(pf, probs)
+    b = pf.Batch(probs, pf.BatchPlan(4, 1024, 1))
+    b.run()
+    got = b.results()
+    b.close()
+    same(got, ref)
+    assert [s.polish_accepted for _, _, s in got] == [s.polish_accepted for _, _, s in ref]
+    assert sum(s.polish_accepted for _, _, s in got) > 0
+    say(f"    accepted steps per problem {[s.polish_accepted for _, _, s in got]}")
+
+
 def test_batch_graph_replay(pf, problems):
     say("[batch] HIP graph capture and replay")
     b = pf.Batch(problems, pf.BatchPlan(4, 1024, 1))

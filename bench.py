@@ -340,6 +340,147 @@ def bench_combined(args):
     print(json.dumps(out), flush=True)
 
 
+_RENDER = {}
+
+
+def _render_init(n_frames):
+    import synth
+    _RENDER["frames"] = synth.cfg2_frames(n_frames)
+
+
+def _render_noisy(t):
+    return _RENDER["frames"]["depth"](t)
+
+
+def _render_clean(t):
+    import synth
+    f = _RENDER["frames"]
+    return synth.render_depth(f["scene"], f["intr"], *f["gt"][t])
+
+
+def surface_points(T, W, origin, vs):
+    """Zero crossings of a fused TSDF: between x-, y- or z-neighbouring voxels that are both observed
+    (W > 0) and inside the band (|T| < 1) with opposite signs, the linearly interpolated point."""
+    import numpy as np
+    pts = []
+    for axis in range(3):                      # arrays are (z, y, x)
+        a = [slice(None)] * 3
+        b = [slice(None)] * 3
+        a[2 - axis] = slice(0, -1)
+        b[2 - axis] = slice(1, None)
+        T0, T1 = T[tuple(a)], T[tuple(b)]
+        ok = (W[tuple(a)] > 0) & (W[tuple(b)] > 0) & (np.abs(T0) < 1) & (np.abs(T1) < 1) & ((T0 > 0) != (T1 > 0))
+        k, j, i = np.nonzero(ok)
+        f = T0[k, j, i] / (T0[k, j, i] - T1[k, j, i])
+        P = np.stack([i, j, k], 1).astype(np.float64)
+        P[:, axis] += f
+        pts.append(P * vs + np.asarray(origin, np.float64))
+    return np.concatenate(pts, 0)
+
+
+def bench_accuracy(args):
+    """Tracking and reconstruction accuracy on the paper-scale sequence against its analytic ground
+    truth (the synthetic stand-in for the paper's benchmarks): ATE-RMSE of the camera positions
+    (same world frame, and after a rigid alignment), the median rotation error, and the
+    reconstruction's accuracy (mean distance of the fused surface's zero crossings to the true
+    surfaces) and completeness (share of true surface samples, from noise-free renders of every 10th
+    frame, with a reconstructed point within 10 cm). Runs the fixed schedule, the paper's schedule,
+    fusion at the true poses (tracking-free reference) and the stand-in chained without any
+    optimization. Prints one JSON line."""
+    import multiprocessing as mp
+    import numpy as np
+    import torch
+    from scipy.spatial import cKDTree
+    import paper_2509_24236_amd as pf
+    import synth
+    n = args.frames
+    dev = torch.device("cuda:0")
+    f = synth.cfg2_frames(n)
+    intr, spec, gt, rel, scene = f["intr"], f["vol"], f["gt"], f["rel"], f["scene"]
+    workers = max(1, min(16, os.cpu_count() or 1))
+    log(f"[accuracy] rendering {n} frames with {workers} processes")
+    with mp.get_context("fork").Pool(workers, initializer=_render_init, initargs=(n,)) as pool:
+        depths = pool.map(_render_noisy, range(n))
+        clean = pool.map(_render_clean, range(0, n, 10))
+    gt_pts = np.concatenate([synth.backproject_world(d, intr, *gt[t], stride=4)
+                             for d, t in zip(clean, range(0, n, 10))], 0)
+    dev_depth = [torch.as_tensor(d).to(dev) for d in depths]
+
+    def rot_deg(Ra, Rb):
+        c = (np.trace(Ra.T @ Rb) - 1.0) / 2.0
+        return math.degrees(math.acos(max(-1.0, min(1.0, c))))
+
+    def traj_metrics(est):
+        P = np.stack([t for _, t in est])
+        G = np.stack([t for _, t in gt[:len(est)]])
+        e = np.linalg.norm(P - G, axis=1)
+        # rigid alignment (Umeyama, no scale) of the estimate onto the truth
+        mp_, mg = P.mean(0), G.mean(0)
+        U, _, Vt = np.linalg.svd((G - mg).T @ (P - mp_))
+        D = np.diag([1.0, 1.0, np.sign(np.linalg.det(U @ Vt))])
+        Ra = U @ D @ Vt
+        ea = np.linalg.norm((P - mp_) @ Ra.T + mg - G, axis=1)
+        rot = [rot_deg(R, g[0]) for (R, _), g in zip(est, gt)]
+        return {"ate_rmse_cm": 100 * float(np.sqrt(np.mean(e ** 2))),
+                "ate_rmse_aligned_cm": 100 * float(np.sqrt(np.mean(ea ** 2))),
+                "median_rot_err_deg": float(np.median(rot)), "max_trans_err_cm": 100 * float(e.max())}
+
+    def recon_metrics(vol):
+        T, W = vol.export_linear()
+        T, W = T.cpu().numpy(), W.cpu().numpy()
+        S = surface_points(T, W, spec.origin, spec.voxel_size)
+        del T, W
+        acc = synth.scene_distance(scene, S)
+        dist, _ = cKDTree(S).query(gt_pts, k=1, distance_upper_bound=0.10)
+        return {"surface_points": int(S.shape[0]), "accuracy_cm": 100 * float(acc.mean()),
+                "accuracy_median_cm": 100 * float(np.median(acc)),
+                "completeness_10cm": float(np.mean(np.isfinite(dist)))}
+
+    out = {"metric": "ATE-RMSE (cm) and reconstruction accuracy / completeness on the synthetic sequence",
+           "frames": n, "gt_surface_samples": int(gt_pts.shape[0]), "runs": {}}
+    for name in ("fixed", "paper", "gt_poses", "standin_only"):
+        vol = pf.Tsdf(spec, device=dev)
+        vol.integrate(dev_depth[0], intr, np.eye(3), np.zeros(3))
+        est = [(np.eye(3), np.zeros(3))]
+        trk = None
+        if name == "fixed":
+            trk = pf.Tracker(intr, pf.TrackParams(seed=14, n_iters=20, K=3072, rates=(8, 16, 32), pixel_stride=1,
+                                                  s1_deg=10.0, s1_m=0.10), device=dev)
+        elif name == "paper":
+            trk = pf.Tracker(intr, pf.TrackParams(seed=14, n_iters=20, K=10240, Ks=(1024, 3072, 10240),
+                                                  rates=(8, 16, 32), pixel_stride=1, s1_deg=10.0, s1_m=0.10,
+                                                  stop_deg=0.05, stop_m=0.0005), device=dev)
+        iters = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(1, n):
+            Rp, tp = est[-1]
+            Rr, tr = rel[t]
+            R0, t0_ = Rp @ Rr, Rp @ tr + tp
+            if name == "gt_poses":
+                R, tt = gt[t]
+            elif name == "standin_only":
+                R, tt = R0, t0_
+            else:
+                trk.set_frame(t)
+                R, tt, st = trk.track(vol, dev_depth[t], R0, t0_)
+                iters.append(st.n_iters)
+            vol.integrate(dev_depth[t], intr, R, tt)
+            est.append((R, tt))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        row = traj_metrics(est)
+        row.update(recon_metrics(vol))
+        row["ms_per_frame"] = 1e3 * wall / (n - 1)
+        if iters:
+            row["mean_iterations"] = float(np.mean(iters))
+        out["runs"][name] = row
+        log(f"[accuracy] {name}: {json.dumps(row)}")
+        del vol
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def dataclasses_asdict(x):
     import dataclasses
     return dataclasses.asdict(x)
@@ -353,10 +494,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true", help="run only a plain 1 GiB device copy")
-    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch", "regimes", "combined"],
+    ap.add_argument("--frames", type=int, default=200, help="accuracy: frames of the sequence")
+    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch", "regimes", "combined", "accuracy"],
                     help="sequence: the paper-scale sequence (the headline); batch: 64 heterogeneous problems; "
                          "regimes: the scoring kernel alone at four particle spreads (diagnostic); combined: "
-                         "batched + polish against plain at equal accuracy")
+                         "batched + polish against plain at equal accuracy; accuracy: ATE and reconstruction "
+                         "quality of the whole sequence against the analytic ground truth")
     ap.add_argument("--problems", type=int, default=64)
     ap.add_argument("--schedule", default="fixed", choices=["fixed", "paper"],
                     help="sequence: fixed = 3072 particles x 20 iterations (the headline configuration); paper = "
@@ -378,6 +521,9 @@ def main():
         return
     if args.workload == "combined":
         bench_combined(args)
+        return
+    if args.workload == "accuracy":
+        bench_accuracy(args)
         return
 
     import numpy as np

@@ -422,3 +422,35 @@ def fill_room_volume(vol: VolumeSpec, scene) -> np.ndarray:
     lo, hi = scene["room_lo"], scene["room_hi"]
     dist = np.minimum(P - lo, hi - P).min(axis=-1)
     return _band(dist, vol.trunc)
+
+
+# ----------------------------------------------------------------------------- evaluation helpers
+def _box_distance(P, lo, hi):
+    """Unsigned distance from points P (N, 3) to the surface of the axis-aligned box [lo, hi]."""
+    q = np.maximum(lo - P, P - hi)                       # > 0 outside along an axis
+    outside = np.linalg.norm(np.maximum(q, 0.0), axis=1)
+    inside = -np.max(q, axis=1)                          # distance to the nearest face from inside
+    return np.where(np.max(q, axis=1) > 0.0, outside, inside)
+
+
+def scene_distance(scene, P_world) -> np.ndarray:
+    """Unsigned distance from world points (N, 3) to the nearest surface of the analytic scene
+    (room walls, spheres, boxes), for reconstruction accuracy against the true geometry."""
+    P = np.asarray(P_world, np.float64) @ scene["R_rw"].T + scene["t_rw"]
+    d = _box_distance(P, scene["room_lo"], scene["room_hi"])
+    for c, r in scene["spheres"]:
+        d = np.minimum(d, np.abs(np.linalg.norm(P - c, axis=1) - r))
+    for lo, hi in scene["boxes"]:
+        d = np.minimum(d, _box_distance(P, lo, hi))
+    return d
+
+
+def backproject_world(depth, K: Intrinsics, R_wc, t_wc, stride: int = 1) -> np.ndarray:
+    """World points of the valid pixels of a depth map (every `stride`-th pixel in u and v)."""
+    d = np.asarray(depth, np.float64)[::stride, ::stride]
+    v, u = np.nonzero(d > 0)
+    z = d[v, u]
+    u = u * stride
+    v = v * stride
+    X = np.stack([(u - K.cx) * z / K.fx, (v - K.cy) * z / K.fy, z], 1)
+    return X @ np.asarray(R_wc, np.float64).T + np.asarray(t_wc, np.float64)

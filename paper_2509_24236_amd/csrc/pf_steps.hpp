@@ -191,12 +191,13 @@ __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px,
         const int Kc = st->K_cur;   // particles of the iteration just scored
         double acc[6] = {0, 0, 0, 0, 0, 0};
         int na = 0;
+        // branch-free so that the loads of all of a thread's particles are in flight together;
+        // adding an exact zero for non-members leaves the sums unchanged
         for (int k = 1 + threadIdx.x; k <= Kc; k += kAdvThreads) {
-            if (fitness[k] < E0) {
+            const bool in = fitness[k] < E0;
 #pragma unroll
-                for (int d = 0; d < 6; ++d) acc[d] += dl[6 * k + d];
-                na += 1;
-            }
+            for (int d = 0; d < 6; ++d) acc[d] += in ? dl[6 * k + d] : 0.0;
+            na += in ? 1 : 0;
         }
         __shared__ double dred[6][kAdvThreads / kWave];
         __shared__ int cred[kAdvThreads / kWave];
@@ -284,13 +285,34 @@ __device__ inline void next_step(pf_track_state* st, int K, int n_partials, int 
     __shared__ double sh_s[2];
     __shared__ int sh_cnt;
     __shared__ float sh_E;
-    if (!FIRST && threadIdx.x == 0) {
+    __shared__ FixSum rs[256 / kWave];
+    __shared__ int rc[256 / kWave];
+    if (!FIRST) {
+        // E* from the exact partials (integer sums, so the reduction order is free)
         const Partial* pt = state_partials(st, K);
         FixSum sum = 0;
         int cnt = 0;
-        for (int b = 0; b < n_partials; ++b) {
+        for (int b = threadIdx.x; b < n_partials; b += 256) {
             sum += pt[b].sum;
             cnt += pt[b].cnt;
+        }
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            sum += __shfl_xor(sum, off);
+            cnt += __shfl_xor(cnt, off);
+        }
+        if ((threadIdx.x & (kWave - 1)) == 0) {
+            rs[threadIdx.x / kWave] = sum;
+            rc[threadIdx.x / kWave] = cnt;
+        }
+        __syncthreads();
+    }
+    if (!FIRST && threadIdx.x == 0) {
+        FixSum sum = 0;
+        int cnt = 0;
+        for (int w = 0; w < 256 / kWave; ++w) {
+            sum += rs[w];
+            cnt += rc[w];
         }
         const float Es = fitness_from<FMT>(sum, cnt);
         const double f = st->beta + (1.0 - st->beta) * (double)Es;

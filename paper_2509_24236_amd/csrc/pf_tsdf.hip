@@ -115,6 +115,9 @@ struct FuseArgs {
     int width, height;
     float w_max;
     const float* depth;
+    // FP32 copies for the conservative pre-test: camera-frame depth and pixel coordinates of
+    // voxel (i, j, k) are q = Q0 + i Qi + j Qj + k Qk with Q0 = R^T (origin - t), Qi = R^T e_x vs, ...
+    float q0[3], qi[3], qj[3], qk[3];
 };
 
 // The projection is evaluated in FP64 with the same operation order as the plain definition,
@@ -122,8 +125,8 @@ struct FuseArgs {
 // (updated or not, which pixel) are those of an FP64 evaluation of the formula as written; the
 // running average is FP32.
 // Grid: x in workgroups of kBlock voxels, y and z one row per workgroup, so no index division.
-// A conservative FP32 pre-test drops voxels that lie outside the image by more than two pixels
-// (FP32 error here is far below a pixel), which the FP64 test would drop too.
+// Conservative FP32 pre-tests drop most voxels of the grid (behind the camera, or outside the image
+// by more than two pixels) before any FP64 work; each drops only voxels the FP64 test drops too.
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
     using S = Store<FMT>;
@@ -131,6 +134,23 @@ __global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
     const int j = blockIdx.y, k = blockIdx.z;
     if (i >= a.d.nx) return;
     const int64_t idx = ((int64_t)k * a.d.ny + j) * a.d.nx + i;
+    {
+        // FP32 pre-test, conservative: it drops only voxels the FP64 test below drops too. The FP32
+        // camera coordinates carry at most ~1e-5 m of error here (|q| < 10 m), so a voxel is
+        // dropped as behind the camera only at qz < -1e-3 m, and as outside the image only at
+        // qz > 0.2 m (pixel error < 0.5) and more than two pixels beyond the border.
+        const float fi = (float)i, fj = (float)j, fk = (float)k;
+        const float z32 = a.q0[2] + fi * a.qi[2] + fj * a.qj[2] + fk * a.qk[2];
+        if (z32 < -1e-3f) return;
+        if (z32 > 0.2f) {
+            const float x32 = a.q0[0] + fi * a.qi[0] + fj * a.qj[0] + fk * a.qk[0];
+            const float y32 = a.q0[1] + fi * a.qi[1] + fj * a.qj[1] + fk * a.qk[1];
+            const float iz = 1.0f / z32;
+            const float u32 = (float)a.fx * x32 * iz + (float)a.cx;
+            const float v32 = (float)a.fy * y32 * iz + (float)a.cy;
+            if (!(u32 > -2.5f && u32 < (float)a.width + 1.5f && v32 > -2.5f && v32 < (float)a.height + 1.5f)) return;
+        }
+    }
     const double px = a.ox + a.vs * (double)i;
     const double py = a.oy + a.vs * (double)j;
     const double pz = a.oz + a.vs * (double)k;
@@ -247,6 +267,12 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
     a.oz = v->origin[2];
     for (int q = 0; q < 9; ++q) a.R[q] = P->R[q];
     for (int q = 0; q < 3; ++q) a.t[q] = P->t[q];
+    for (int r = 0; r < 3; ++r) {   // camera axis r = column r of R
+        a.q0[r] = (float)(a.R[r] * (a.ox - a.t[0]) + a.R[3 + r] * (a.oy - a.t[1]) + a.R[6 + r] * (a.oz - a.t[2]));
+        a.qi[r] = (float)(a.R[r] * v->voxel_size);
+        a.qj[r] = (float)(a.R[3 + r] * v->voxel_size);
+        a.qk[r] = (float)(a.R[6 + r] * v->voxel_size);
+    }
     a.fx = K->fx;
     a.fy = K->fy;
     a.cx = K->cx;

@@ -327,7 +327,8 @@ def pr_standin(gt_prev, gt_cur, rng, sigma_rot_deg=3.0, sigma_t=0.03):
 CFG2_LENGTH = 200
 
 
-def cfg2_frames(n_frames=CFG2_LENGTH, traj_seed=11, scene_seed=10, noise_seed=12, pr_seed=13):
+def cfg2_frames(n_frames=CFG2_LENGTH, traj_seed=11, scene_seed=10, noise_seed=12, pr_seed=13, pr_sigma_deg=3.0,
+                pr_sigma_m=0.03):
     """The paper-scale sequence: scene, world GT poses, noisy depth maps (lazy) and PR stand-ins.
 
     The scene is always placed against the full 200-frame trajectory, so the first n_frames of
@@ -340,7 +341,7 @@ def cfg2_frames(n_frames=CFG2_LENGTH, traj_seed=11, scene_seed=10, noise_seed=12
     gt = world_trajectory(scene, traj_room)
     vol = VolumeSpec.centred(512, 0.01, 0.04, room_centre_world(scene))
     rng = np.random.default_rng(pr_seed)
-    rel = [None] + [pr_standin(gt[t - 1], gt[t], rng) for t in range(1, n_frames)]
+    rel = [None] + [pr_standin(gt[t - 1], gt[t], rng, pr_sigma_deg, pr_sigma_m) for t in range(1, n_frames)]
 
     def depth(t):
         d = render_depth(scene, CFG2_INTR, *gt[t])

@@ -191,13 +191,26 @@ __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px,
         const int Kc = st->K_cur;   // particles of the iteration just scored
         double acc[6] = {0, 0, 0, 0, 0, 0};
         int na = 0;
-        // branch-free so that the loads of all of a thread's particles are in flight together;
-        // adding an exact zero for non-members leaves the sums unchanged
-        for (int k = 1 + threadIdx.x; k <= Kc; k += kAdvThreads) {
-            const bool in = fitness[k] < E0;
+        // Four particles per pass with all their loads issued together: membership is a 0/1
+        // factor (adding an exact zero leaves a sum unchanged), so there is no branch to serialise
+        // the loads; indices past K_cur read in-bounds slots (the buffers hold K + 1) with factor 0.
+        constexpr int kU = 4;
+        for (int kb = 1 + threadIdx.x; kb <= Kc; kb += kU * kAdvThreads) {
+            double m[kU];
+            int kk[kU];
 #pragma unroll
-            for (int d = 0; d < 6; ++d) acc[d] += in ? dl[6 * k + d] : 0.0;
-            na += in ? 1 : 0;
+            for (int u = 0; u < kU; ++u) {
+                const int k = kb + u * kAdvThreads;
+                kk[u] = min(k, K);
+                const float fk = fitness[kk[u]];
+                m[u] = ((k <= Kc) & (fk < E0)) ? 1.0 : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+#pragma unroll
+                for (int d = 0; d < 6; ++d) acc[d] += dl[6 * kk[u] + d] * m[u];
+                na += m[u] != 0.0 ? 1 : 0;
+            }
         }
         __shared__ double dred[6][kAdvThreads / kWave];
         __shared__ int cred[kAdvThreads / kWave];

@@ -124,15 +124,11 @@ struct FuseArgs {
 // and this file is compiled without multiply-add contraction, so the per-voxel decisions
 // (updated or not, which pixel) are those of an FP64 evaluation of the formula as written; the
 // running average is FP32.
-// Grid: x in workgroups of kBlock voxels, y and z one row per workgroup, so no index division.
 // Conservative FP32 pre-tests drop most voxels of the grid (behind the camera, or outside the image
 // by more than two pixels) before any FP64 work; each drops only voxels the FP64 test drops too.
 template <int FMT>
-__global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
+__device__ inline void fuse_voxel(const FuseArgs& a, int i, int j, int k) {
     using S = Store<FMT>;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    const int j = blockIdx.y, k = blockIdx.z;
-    if (i >= a.d.nx) return;
     const int64_t idx = ((int64_t)k * a.d.ny + j) * a.d.nx + i;
     {
         // FP32 pre-test, conservative: it drops only voxels the FP64 test below drops too. The FP32
@@ -185,6 +181,45 @@ __global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
     if (!S::same(told, tnew)) T[idx] = tnew;
     W[idx] = S::encw(fminf(w + 1.0f, a.w_max));
     if (a.C && !S::same(told, tnew)) write_corners(static_cast<typename S::T*>(a.C), a.d, i, j, k, tnew);
+}
+
+// Grid: a workgroup owns a brick of kFuseX x kFuseY x kFuseZ voxels (a wave per x row, each thread
+// walking kFuseZ slices, so no index division and each wave lives long enough to amortise its
+// start). A brick whose 8 corners all lie behind the camera, or all beyond one side of the image
+// (a plane through the camera centre, two pixels out, with a margin far above the FP32 error), is
+// skipped as a whole: every voxel in it is a convex combination of the corners, so the per-voxel
+// tests would drop it too.
+constexpr int kFuseX = 64, kFuseY = kBlock / kFuseX, kFuseZ = 32;
+
+__device__ inline bool brick_outside(const FuseArgs& a, int i0, int j0, int k0, int i1, int j1, int k1) {
+    // the four side planes n . q >= 0 of the image widened by two pixels, q in camera coordinates
+    const float fx = (float)a.fx, fy = (float)a.fy, cx = (float)a.cx, cy = (float)a.cy;
+    const float W = (float)a.width, H = (float)a.height;
+    const float n[4][3] = {{fx, 0.0f, cx + 2.5f}, {-fx, 0.0f, W + 1.5f - cx},
+                           {0.0f, fy, cy + 2.5f}, {0.0f, -fy, H + 1.5f - cy}};
+    bool behind = true, out[4] = {true, true, true, true};
+    for (int c = 0; c < 8; ++c) {
+        const float fi = (float)((c & 1) ? i1 : i0), fj = (float)((c & 2) ? j1 : j0), fk = (float)((c & 4) ? k1 : k0);
+        float q[3];
+        for (int r = 0; r < 3; ++r) q[r] = a.q0[r] + fi * a.qi[r] + fj * a.qj[r] + fk * a.qk[r];
+        behind &= q[2] < -1e-3f;
+        for (int p = 0; p < 4; ++p) {
+            const float d = n[p][0] * q[0] + n[p][1] * q[1] + n[p][2] * q[2];
+            const float tol = 1e-3f * (fabsf(n[p][0]) + fabsf(n[p][1]) + fabsf(n[p][2]));
+            out[p] &= d < -tol;
+        }
+    }
+    return behind || out[0] || out[1] || out[2] || out[3];
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
+    const int i0 = blockIdx.x * kFuseX, j0 = blockIdx.y * kFuseY, k0 = blockIdx.z * kFuseZ;
+    const int i1 = min(a.d.nx, i0 + kFuseX) - 1, j1 = min(a.d.ny, j0 + kFuseY) - 1, k1 = min(a.d.nz, k0 + kFuseZ) - 1;
+    if (brick_outside(a, i0, j0, k0, i1, j1, k1)) return;
+    const int i = i0 + (int)(threadIdx.x % kFuseX), j = j0 + (int)(threadIdx.x / kFuseX);
+    if (i > i1 || j > j1) return;
+    for (int k = k0; k <= k1; ++k) fuse_voxel<FMT>(a, i, j, k);
 }
 
 template <int FMT>
@@ -281,7 +316,8 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
     a.height = K->height;
     a.w_max = (float)v->w_max;
     a.depth = depth;
-    const dim3 grid((unsigned)((a.d.nx + kBlock - 1) / kBlock), (unsigned)a.d.ny, (unsigned)a.d.nz);
+    const dim3 grid((unsigned)((a.d.nx + kFuseX - 1) / kFuseX), (unsigned)((a.d.ny + kFuseY - 1) / kFuseY),
+                    (unsigned)((a.d.nz + kFuseZ - 1) / kFuseZ));
     hipLaunchKernelGGL(k_integrate<FMT>, grid, dim3(kBlock), 0, s, a);
     return check_launch("tsdf_integrate");
 }

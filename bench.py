@@ -510,6 +510,10 @@ def main():
                     help="sequence: fixed = 3072 particles x 20 iterations (the headline configuration); paper = "
                          "the alternating particle counts and early exit of Sec. IV-A")
     ap.add_argument("--tune", action="store_true", help="batch: run the autotuner first and record the plan")
+    ap.add_argument("--volume", default="dense", choices=["dense", "bricks"],
+                    help="sequence: dense = the 512^3 cell-replica grid centred on the room (the headline); "
+                         "bricks = a sparse brick pool over the whole room at the same 1 cm voxels")
+    ap.add_argument("--max-bricks", type=int, default=120000, help="bricks: pool slots")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures the single-GPU path only (--gpus {args.gpus} requested); the multi-GPU "
@@ -553,7 +557,12 @@ def main():
     else:
         params = pf.TrackParams(seed=14, frame_index=1, n_iters=I, K=K, rates=rates, pixel_stride=1, s1_deg=10.0,
                                 s1_m=0.10)
-    vol = pf.Tsdf(spec, device=dev)
+    if args.volume == "bricks":
+        spec = synth.room_spec(frames["scene"], spec.voxel_size, spec.trunc)
+        vol = pf.Tsdf(spec, device=dev, layout=pf.LAYOUT_BRICKS, max_bricks=args.max_bricks)
+    else:
+        vol = pf.Tsdf(spec, device=dev)
+    vol_bytes = vol.T.numel() * vol.T.element_size() + vol.W.numel() * vol.W.element_size()
     trk = pf.Tracker(intr, params, device=dev)
     torch.cuda.synchronize()
 
@@ -561,6 +570,7 @@ def main():
     vol.integrate(depth[0], intr, *est[0])
 
     iters_run = []
+    fuse_events = []
 
     def step(t):
         Rp, tp = est[t - 1]
@@ -568,7 +578,11 @@ def main():
         R0, t0 = Rp @ Rr, Rp @ tr + tp            # P_t^(0) = P_{t-1} P_(t,t-1)
         trk.set_frame(t)
         R, tt, st = trk.track(vol, depth[t], R0, t0)
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ev[0].record()
         vol.integrate(depth[t], intr, R, tt)
+        ev[1].record()
+        fuse_events.append(ev)
         est.append((R, tt))
         iters_run.append(st.n_iters)
         return st
@@ -583,6 +597,7 @@ def main():
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     del iters_run[:]
+    del fuse_events[:]
     for t in range(args.warmup + 1, args.warmup + args.steps + 1):
         step(t)
     torch.cuda.synchronize()
@@ -593,6 +608,7 @@ def main():
     avg_launch_ms = score_ms / max(1, launches)
     achieved = BYTES_PER_EVAL * (evals / max(1, launches)) / (avg_launch_ms * 1e-3) / 1e9
     traffic, traffic_bytes = counter_traffic(avg_launch_ms)
+    fuse_ms = sum(a.elapsed_time(b) for a, b in fuse_events) / max(1, len(fuse_events))
     gt_err = [np.linalg.norm(est[t][1] - frames["gt"][t][1]) for t in range(1, len(est))]
     log(f"[bench] {ms_per_frame:.3f} ms/frame, scoring {avg_launch_ms:.4f} ms/launch avg, "
         f"{evals / max(score_ms, 1e-9) * 1e3:.3e} evals/s in-kernel; GT translation error median "
@@ -623,6 +639,8 @@ def main():
             "iterations": I,
             "mean_iterations_run": sum(iters_run) / max(1, len(iters_run)),
             "tsdf": "512^3 f32 T + f32 W, cell-major f32 replica for scoring",
+            "fusion_ms_per_frame": fuse_ms,
+            "volume_bytes": vol_bytes,
         },
         "roofline": {
             "bound": "hbm",
@@ -639,6 +657,20 @@ def main():
             "evals_per_launch": evals / max(1, launches),
         },
     }
+    if args.volume == "bricks":
+        used, overflow = vol.bricks_used()
+        if overflow:
+            raise SystemExit(f"the brick pool of {args.max_bricks} slots overflowed: raise --max-bricks")
+        c = out["config"]
+        c["workload"] = c["workload"].replace("512^3 FP32 TSDF at 1 cm", f"sparse FP32 TSDF over the whole room "
+                                              f"({spec.nx}x{spec.ny}x{spec.nz} at 1 cm, 8^3 bricks)")
+        c["tsdf"] = (f"brick pool: {used} of {args.max_bricks} slots in use after the last frame, f32 T + f32 W + "
+                     f"per-brick cell blocks; {spec.nx}x{spec.ny}x{spec.nz} grid ({spec.nx * spec.ny * spec.nz / 1e6:.1f}M "
+                     f"voxels), {used * 512 / (spec.nx * spec.ny * spec.nz):.1%} of them stored")
+        c["bricks_used"] = used
+        out["roofline"]["kernel"] = out["roofline"]["kernel"].replace("<f32, cells>", "<f32, bricks>")
+        out["roofline"]["traffic"] = out["roofline"]["traffic_bytes_per_launch"] = None
+        log(f"[bench] bricks {used}, fusion {fuse_ms:.3f} ms/frame, volume {vol_bytes / 2**30:.2f} GiB")
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(frames, spec, intr, n_frames, args.cpu_seconds, args.schedule)

@@ -55,8 +55,25 @@ extern "C" {
  *         one contiguous 32-byte (FP32) or 16-byte block instead of four rows; the replica is 8x
  *         the size of T and is kept equal to T by tsdf_init, tsdf_import_linear and
  *         tsdf_integrate (which rewrites only the cells of voxels whose stored value changed). */
+/* BRICKS: a sparse volume for scenes larger than a dense grid affords (nx, ny, nz multiples of 8).
+ *         Bricks of 8x8x8 voxels live in a pool of max_bricks slots behind a dense brick-index
+ *         grid (one int32 per brick: its slot, or -1); there is no hash table. The T buffer holds,
+ *         at the offsets tsdf_brick_offsets() returns: a 256-byte header (int32 bricks in use,
+ *         int32 overflow flag, int32 bricks in use before the last fusion; at byte 64 a cell of
+ *         +1 corners), the index grid (entry (bz * ny/8 + by) * nx/8 + bx for the brick of voxels
+ *         8bx..8bx+7, ...), the brick coordinates of every slot (int32 x4), the
+ *         slots' T (512 values each, x-fastest inside the brick) and their cells (512 per brick,
+ *         cell (x, y, z) local to the brick at x + 8y + 64z, its 8 corners in the CELLS order;
+ *         corners in the next brick along +x/+y/+z read that brick, or +1 where it has no slot).
+ *         The W buffer holds the slots' W. A voxel outside every allocated brick reads T = +1,
+ *         W = 0. tsdf_integrate first gives a slot to every brick that holds a voxel the frame
+ *         puts in the band (-tau <= eta < tau, the same FP64 test as the update), then updates
+ *         the voxels of all allocated bricks exactly as the dense layouts do; voxels of bricks
+ *         without a slot are not updated (free space far from any surface is not recorded).
+ *         When the pool is full further bricks are not allocated and the overflow flag is set. */
 #define PF_LAYOUT_LINEAR 0
 #define PF_LAYOUT_CELLS 1
+#define PF_LAYOUT_BRICKS 2
 
 /* Delta-pose composition, the reading of "Delta P_k P^(i-1)" (Sec. III-B):
  * DECOUPLED: (exp(r) R, t + tau) - rotate about the camera centre, then shift;
@@ -84,7 +101,9 @@ typedef struct pf_tsdf {
     double trunc;        /* truncation distance tau, metres, > 0 */
     double origin[3];    /* centre of voxel (0,0,0), world metres */
     int32_t w_max;       /* weight cap, 1..255 */
-    int32_t layout;      /* PF_LAYOUT_LINEAR or PF_LAYOUT_CELLS */
+    int32_t layout;      /* PF_LAYOUT_LINEAR, PF_LAYOUT_CELLS or PF_LAYOUT_BRICKS */
+    int32_t max_bricks;  /* BRICKS: pool slots (>= 1); 0 for the dense layouts */
+    int32_t reserved;    /* must be 0 */
     void* tsdf;          /* device, tsdf_bytes() bytes */
     void* weight;        /* device, *weight_bytes bytes */
 } pf_tsdf;
@@ -181,6 +200,13 @@ size_t tsdf_bytes(const pf_tsdf* v, size_t* weight_bytes);
 /* Byte offset of the cell-major replica inside v->tsdf (PF_LAYOUT_CELLS), 0 otherwise. */
 size_t tsdf_cells_offset(const pf_tsdf* v);
 
+/* BRICKS: byte offsets inside v->tsdf of the index grid, the slot coordinates, the slots' T and
+ * their cells (each may be NULL); returns PF_EINVAL for another layout or a bad description. */
+int32_t tsdf_brick_offsets(const pf_tsdf* v, size_t* index, size_t* coords, size_t* pool_t, size_t* pool_cells);
+
+/* BRICKS: bricks in use and the overflow flag (host ints). Synchronises the stream. */
+int32_t tsdf_bricks_used(const pf_tsdf* v, int32_t* n_bricks, int32_t* overflow, void* stream);
+
 /* Sets every voxel to the initial state T = +1 (unobserved), W = 0 (Sec. III overview: the
  * scene is a dense tensor of distance values; the first frame fills it). */
 int32_t tsdf_init(const pf_tsdf* v, void* stream);
@@ -199,11 +225,14 @@ int32_t tsdf_integrate(const pf_tsdf* v, const float* depth, const pf_intrinsics
                        const pf_pose* cam_to_world, void* stream);
 
 /* Copies the volume out as FP32 x-fastest arrays (T_out, W_out: device, nx*ny*nz floats;
- * W_out may be NULL). For the int16 format T = q/32767; for fp16, T = (float)half. */
+ * W_out may be NULL). For the int16 format T = q/32767; for fp16, T = (float)half. BRICKS:
+ * voxels outside allocated bricks come out as T = +1, W = 0. */
 int32_t tsdf_export_linear(const pf_tsdf* v, float* T_out, float* W_out, void* stream);
 
 /* Loads the volume from FP32 x-fastest arrays (device; W_in may be NULL = all 0), converting
- * to the storage format (int16: RNE(T*32767) clamped to +-32767; uint8: RNE, clamped). */
+ * to the storage format (int16: RNE(T*32767) clamped to +-32767; uint8: RNE, clamped).
+ * BRICKS: the volume is cleared and a slot is given to every brick holding a voxel other than
+ * (T, W) = (+1, 0); bricks that do not fit in the pool are dropped and set the overflow flag. */
 int32_t tsdf_import_linear(const pf_tsdf* v, const float* T_in, const float* W_in, void* stream);
 
 /* ------------------------------------------------------------------------------ points */

@@ -106,6 +106,8 @@ def lib():
         L.orc_vol_init.argtypes = [P(Vol)]
         L.orc_integrate.restype = C.c_int64
         L.orc_integrate.argtypes = [P(Vol), P(C.c_float), P(Intr), P(Pose), P(C.c_uint8), C.c_double, C.c_double]
+        L.orc_integrate_bricks.restype = C.c_int64
+        L.orc_integrate_bricks.argtypes = [P(Vol), P(C.c_uint8), C.c_int32, P(C.c_float), P(Intr), P(Pose)]
         L.orc_sample.restype = C.c_int
         L.orc_sample.argtypes = [P(Vol), dp, dp]
         L.orc_fitness.argtypes = [P(Vol), dp, C.c_int64, P(Pose), dp, i64p]
@@ -249,6 +251,19 @@ class Volume:
                                 flags.ctypes.data_as(C.POINTER(C.c_uint8)) if want_flags else None,
                                 pix_margin, eta_margin)
         return (int(n), flags) if want_flags else int(n)
+
+    def integrate_bricks(self, depth, intr, R, t, edge=8):
+        """Sparse reading of the fusion: bricks of edge^3 voxels recorded at the first frame that puts
+        one of their voxels in the band; only their voxels are updated. Returns the bricks recorded;
+        the flags are kept in self.bricks, shape (nz/edge, ny/edge, nx/edge)."""
+        s = self.spec
+        if getattr(self, "bricks", None) is None:
+            self.bricks = np.zeros((s.nz // edge, s.ny // edge, s.nx // edge), np.uint8)
+        d = np.ascontiguousarray(depth, dtype=np.float32)
+        n = lib().orc_integrate_bricks(C.byref(self.c()), self.bricks.ctypes.data_as(C.POINTER(C.c_uint8)), edge,
+                                       d.ctypes.data_as(C.POINTER(C.c_float)), C.byref(Intr.of(intr)),
+                                       C.byref(Pose.of(R, t)))
+        return int(n)
 
     def sample(self, y):
         y = _f64(y).reshape(3)

@@ -255,6 +255,74 @@ int64_t orc_integrate(orc_vol* V, const float* depth, const orc_intr* K, const o
 }
 
 /* ----------------------------------------------------------------------------------------
+ * Sparse reading of the same fusion, for scenes larger than a dense grid affords (the paper's
+ * tensor is dense; this is the bricked extension). The grid is cut into bricks of E x E x E
+ * voxels (dims multiples of E). A brick is recorded in the first frame that puts one of its
+ * voxels inside the truncation band, i.e. gives it an observation phi < 1 under exactly the
+ * decisions of orc_integrate above (-tau <= eta < tau). Only voxels of recorded bricks are
+ * updated, by the same running average; every other voxel keeps T = +1, W = 0, so free space
+ * far from any surface is not stored. `alloc` holds one flag per brick, brick (bx, by, bz) at
+ * (bz * ny/E + by) * nx/E + bx. Returns the number of bricks recorded by this frame.
+ * ---------------------------------------------------------------------------------------- */
+static int observe(const orc_vol* V, const float* depth, const orc_intr* K, const orc_pose* P, int i, int j, int k,
+                   double* phi_out) {
+    double p[3] = {V->origin[0] + V->vs * i, V->origin[1] + V->vs * j, V->origin[2] + V->vs * k};
+    double d[3] = {p[0] - P->t[0], p[1] - P->t[1], p[2] - P->t[2]};
+    double q[3];
+    for (int a = 0; a < 3; ++a) q[a] = P->R[0 * 3 + a] * d[0] + P->R[1 * 3 + a] * d[1] + P->R[2 * 3 + a] * d[2];
+    if (q[2] <= 0.0) return 0;
+    double uf = floor(K->fx * q[0] / q[2] + K->cx + 0.5), vf = floor(K->fy * q[1] / q[2] + K->cy + 0.5);
+    if (uf < 0.0 || uf >= K->width || vf < 0.0 || vf >= K->height) return 0;
+    double D = (double)depth[(int64_t)(int)vf * K->width + (int)uf];
+    if (!(isfinite(D) && D > 0.0)) return 0;
+    double eta = D - q[2];
+    if (eta < -V->tau) return 0;
+    double phi = eta / V->tau;
+    *phi_out = phi > 1.0 ? 1.0 : phi;
+    return 1;
+}
+
+int64_t orc_integrate_bricks(orc_vol* V, uint8_t* alloc, int32_t E, const float* depth, const orc_intr* K,
+                             const orc_pose* P) {
+    const int nbx = V->nx / E, nby = V->ny / E, nbz = V->nz / E;
+    uint8_t* fresh = (uint8_t*)calloc((size_t)nbx * nby * nbz, 1);
+    int64_t recorded = 0;
+    /* bricks the frame puts a band voxel into */
+#pragma omp parallel for reduction(+ : recorded) schedule(static)
+    for (int bz = 0; bz < nbz; ++bz)
+        for (int by = 0; by < nby; ++by)
+            for (int bx = 0; bx < nbx; ++bx) {
+                int64_t b = ((int64_t)bz * nby + by) * nbx + bx;
+                if (alloc[b]) continue;
+                int hit = 0;
+                for (int k = bz * E; k < (bz + 1) * E && !hit; ++k)
+                    for (int j = by * E; j < (by + 1) * E && !hit; ++j)
+                        for (int i = bx * E; i < (bx + 1) * E && !hit; ++i) {
+                            double phi;
+                            if (observe(V, depth, K, P, i, j, k, &phi) && phi < 1.0) hit = 1;
+                        }
+                fresh[b] = (uint8_t)hit;
+                recorded += hit;
+            }
+    for (int64_t b = 0; b < (int64_t)nbx * nby * nbz; ++b) alloc[b] |= fresh[b];
+    free(fresh);
+    /* the running average over the voxels of recorded bricks */
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < V->nz; ++k)
+        for (int j = 0; j < V->ny; ++j)
+            for (int i = 0; i < V->nx; ++i) {
+                if (!alloc[((int64_t)(k / E) * nby + j / E) * nbx + i / E]) continue;
+                double phi;
+                if (!observe(V, depth, K, P, i, j, k, &phi)) continue;
+                int64_t idx = ((int64_t)k * V->ny + j) * V->nx + i;
+                double w = V->W[idx];
+                V->T[idx] = (V->T[idx] * w + phi) / (w + 1.0);
+                V->W[idx] = (w + 1.0 < (double)V->w_max) ? w + 1.0 : (double)V->w_max;
+            }
+    return recorded;
+}
+
+/* ----------------------------------------------------------------------------------------
  * TSDF query at a world point (Sec. III-B, fitness equation; valid grids). Reading: the query
  * is trilinear over the 8 voxel centres around the point (lerp in x, then y, then z); the
  * point is in X_k iff the whole stencil is inside the grid and all 8 corners satisfy |T| < 1

@@ -23,7 +23,7 @@ PF_OK, PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED = 0, -1, -2, -3, -4
 F32_W_F32, F16_W_U8, I16_W_U8 = 0, 1, 2
 COMPOSE_DECOUPLED, COMPOSE_LITERAL = 0, 1
 MAX_ITERS = 64
-LAYOUT_LINEAR, LAYOUT_CELLS = 0, 1
+LAYOUT_LINEAR, LAYOUT_CELLS, LAYOUT_BRICKS = 0, 1, 2
 STATE_DELTAS_OFFSET = 512
 
 
@@ -46,7 +46,8 @@ class pf_intrinsics(C.Structure):
 class pf_tsdf(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("format", C.c_int32),
                 ("voxel_size", C.c_double), ("trunc", C.c_double), ("origin", C.c_double * 3),
-                ("w_max", C.c_int32), ("layout", C.c_int32), ("tsdf", C.c_void_p), ("weight", C.c_void_p)]
+                ("w_max", C.c_int32), ("layout", C.c_int32), ("max_bricks", C.c_int32), ("reserved", C.c_int32),
+                ("tsdf", C.c_void_p), ("weight", C.c_void_p)]
 
 
 class pf_track_params(C.Structure):
@@ -87,7 +88,7 @@ class pf_batch_plan(C.Structure):
 
 
 # every symbol include/profusion.h declares
-EXPORTS = ("pf_last_error", "tsdf_bytes", "tsdf_cells_offset", "tsdf_init", "tsdf_integrate", "tsdf_export_linear", "tsdf_import_linear",
+EXPORTS = ("pf_last_error", "tsdf_bytes", "tsdf_cells_offset", "tsdf_brick_offsets", "tsdf_bricks_used", "tsdf_init", "tsdf_integrate", "tsdf_export_linear", "tsdf_import_linear",
            "backproject", "particles_score", "particles_score_grad", "pf_score_config", "particles_state_bytes", "particles_state_init", "particles_update",
            "track_workspace_bytes", "track_frame", "track_batch_workspace_bytes", "track_batch_create",
            "track_batch_run", "track_batch_results", "track_batch_destroy", "pf_timing_enable", "pf_timing_read")
@@ -110,6 +111,8 @@ def lib() -> C.CDLL:
     L.tsdf_bytes.argtypes = [P(pf_tsdf), P(C.c_size_t)]
     L.tsdf_cells_offset.restype = C.c_size_t
     L.tsdf_cells_offset.argtypes = [P(pf_tsdf)]
+    L.tsdf_brick_offsets.argtypes = [P(pf_tsdf), P(C.c_size_t), P(C.c_size_t), P(C.c_size_t), P(C.c_size_t)]
+    L.tsdf_bricks_used.argtypes = [P(pf_tsdf), P(C.c_int32), P(C.c_int32), vp]
     for name in ("tsdf_init",):
         getattr(L, name).argtypes = [P(pf_tsdf), vp]
     L.tsdf_integrate.argtypes = [P(pf_tsdf), vp, P(pf_intrinsics), P(pf_pose), vp]
@@ -236,14 +239,14 @@ class Tsdf:
     """A device TSDF volume: torch tensors for T and W plus the pf_tsdf descriptor."""
 
     def __init__(self, spec, fmt: int = F32_W_F32, w_max: int = 255, device="cuda", init=True, stream=None,
-                 layout: int = LAYOUT_CELLS):
+                 layout: int = LAYOUT_CELLS, max_bricks: int = 0):
         torch = _torch()
         self.spec, self.format, self.layout = spec, fmt, layout
         d = pf_tsdf()
         d.nx, d.ny, d.nz, d.format = spec.nx, spec.ny, spec.nz, fmt
         d.voxel_size, d.trunc = float(spec.voxel_size), float(spec.trunc)
         d.origin[:] = [float(x) for x in spec.origin]
-        d.w_max, d.layout = w_max, layout
+        d.w_max, d.layout, d.max_bricks = w_max, layout, max_bricks
         wb = C.c_size_t(0)
         tb = lib().tsdf_bytes(C.byref(d), C.byref(wb))
         if tb == 0:
@@ -252,7 +255,7 @@ class Tsdf:
         tdt, wdt = getattr(torch, _T_DTYPE[fmt]), getattr(torch, _W_DTYPE[fmt])
         self.T = torch.empty(tb // torch.tensor([], dtype=tdt).element_size(), dtype=tdt, device=device)
         self.W = torch.empty(wb.value // torch.tensor([], dtype=wdt).element_size(), dtype=wdt, device=device)
-        assert self.T.numel() >= n and self.W.numel() >= n
+        assert layout == LAYOUT_BRICKS or (self.T.numel() >= n and self.W.numel() >= n)
         d.tsdf, d.weight = self.T.data_ptr(), self.W.data_ptr()
         self.desc = d
         if init:
@@ -265,6 +268,18 @@ class Tsdf:
         """KinectFusion-style fusion of one aligned frame (Sec. III overview)."""
         _check(lib().tsdf_integrate(C.byref(self.desc), _ptr(depth), C.byref(make_intrinsics(intr)),
                                     C.byref(make_pose(R, t)), _stream(stream)))
+
+    def bricks_used(self, stream=None):
+        """BRICKS: (bricks in use, overflow flag); synchronises the stream."""
+        n, ov = C.c_int32(0), C.c_int32(0)
+        _check(lib().tsdf_bricks_used(C.byref(self.desc), C.byref(n), C.byref(ov), _stream(stream)))
+        return int(n.value), int(ov.value)
+
+    def brick_offsets(self):
+        """BRICKS: byte offsets in the T buffer of (index grid, slot coordinates, slots' T, slots' cells)."""
+        o = [C.c_size_t(0) for _ in range(4)]
+        _check(lib().tsdf_brick_offsets(C.byref(self.desc), *[C.byref(x) for x in o]))
+        return tuple(int(x.value) for x in o)
 
     def export_linear(self, with_weight=True, stream=None):
         torch = _torch()

@@ -496,13 +496,9 @@ pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const 
 int32_t track_batch_run(pf_batch* b, void* stream) {
     if (!b) return set_error(PF_EINVAL, "track_batch_run: null batch");
     hipStream_t s = (hipStream_t)stream;
-    const bool cells = b->layout == PF_LAYOUT_CELLS;
-    switch (b->format) {
-        case PF_F32_W_F32: return cells ? run_t<PF_F32_W_F32, PF_LAYOUT_CELLS>(b, s) : run_t<PF_F32_W_F32, PF_LAYOUT_LINEAR>(b, s);
-        case PF_F16_W_U8: return cells ? run_t<PF_F16_W_U8, PF_LAYOUT_CELLS>(b, s) : run_t<PF_F16_W_U8, PF_LAYOUT_LINEAR>(b, s);
-        case PF_I16_W_U8: return cells ? run_t<PF_I16_W_U8, PF_LAYOUT_CELLS>(b, s) : run_t<PF_I16_W_U8, PF_LAYOUT_LINEAR>(b, s);
-        default: return set_error(PF_EUNSUPPORTED, "track_batch_run: unsupported format %d", b->format);
-    }
+    return with_volume(b->format, b->layout, [&](auto fmt, auto layout) {
+        return run_t<decltype(fmt)::value, decltype(layout)::value>(b, s);
+    });
 }
 
 int32_t track_batch_results(pf_batch* b, pf_pose* out, pf_track_stats* stats, void* stream) {

@@ -49,10 +49,40 @@ size_t cells_offset_bytes(const pf_tsdf* v) {
     return (n * t_elem_bytes(v->format) + 255) & ~(size_t)255;
 }
 
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+BrickLayout brick_layout(const pf_tsdf* v) {
+    BrickLayout L;
+    L.nbx = v->nx / kBrickEdge;
+    L.nby = v->ny / kBrickEdge;
+    L.nbz = v->nz / kBrickEdge;
+    const size_t nb = (size_t)L.nbx * L.nby * L.nbz, slots = (size_t)v->max_bricks, tb = t_elem_bytes(v->format);
+    L.index = 256;
+    L.coords = L.index + al256(nb * sizeof(int));
+    L.pool_t = L.coords + al256(slots * 4 * sizeof(int));
+    L.pool_cells = L.pool_t + al256(slots * kBrickVox * tb);
+    L.t_total = L.pool_cells + slots * kBrickVox * 8 * tb;
+    L.w_total = slots * kBrickVox * (v->format == PF_F32_W_F32 ? 4 : 1);
+    return L;
+}
+
 VolView make_view(const pf_tsdf* v) {
     VolView vv;
     vv.T = v->tsdf;
+    vv.bindex = nullptr;
+    vv.ones = nullptr;
+    vv.nbx = vv.nby = 0;
     vv.cells = v->layout == PF_LAYOUT_CELLS ? static_cast<const char*>(v->tsdf) + cells_offset_bytes(v) : nullptr;
+    if (v->layout == PF_LAYOUT_BRICKS) {
+        const BrickLayout L = brick_layout(v);
+        const char* base = static_cast<const char*>(v->tsdf);
+        vv.T = base + L.pool_t;
+        vv.cells = base + L.pool_cells;
+        vv.bindex = reinterpret_cast<const int*>(base + L.index);
+        vv.ones = base + kBrickOnes;
+        vv.nbx = L.nbx;
+        vv.nby = L.nby;
+    }
     vv.nx = v->nx;
     vv.ny = v->ny;
     vv.nz = v->nz;
@@ -71,11 +101,23 @@ int32_t check_tsdf(const pf_tsdf* v, const char* fn, bool need_weight = true) {
     if (!v) return set_error(PF_EINVAL, "%s: null volume", fn);
     if (v->nx < 2 || v->ny < 2 || v->nz < 2)
         return set_error(PF_EINVAL, "%s: volume dims %d x %d x %d (each must be >= 2)", fn, v->nx, v->ny, v->nz);
-    if (v->ny > 65535 || v->nz > 65535)
-        return set_error(PF_EINVAL, "%s: ny and nz must be <= 65535", fn);
-    if ((int64_t)v->nx * v->ny * v->nz >= ((int64_t)1 << 31))
-        return set_error(PF_EINVAL, "%s: volume of %lld voxels exceeds 2^31 - 1", fn,
-                         (long long)v->nx * v->ny * v->nz);
+    if (v->reserved != 0) return set_error(PF_EINVAL, "%s: reserved field must be 0", fn);
+    if (v->layout == PF_LAYOUT_BRICKS) {
+        if (v->nx % kBrickEdge || v->ny % kBrickEdge || v->nz % kBrickEdge)
+            return set_error(PF_EINVAL, "%s: BRICKS needs dims that are multiples of 8", fn);
+        if (v->ny / kBrickEdge > 65535 || v->nz / kBrickEdge > 65535)
+            return set_error(PF_EINVAL, "%s: ny/8 and nz/8 must be <= 65535", fn);
+        if ((int64_t)(v->nx / kBrickEdge) * (v->ny / kBrickEdge) * (v->nz / kBrickEdge) >= ((int64_t)1 << 31))
+            return set_error(PF_EINVAL, "%s: brick-index grid exceeds 2^31 - 1 entries", fn);
+        if (v->max_bricks < 1) return set_error(PF_EINVAL, "%s: BRICKS needs max_bricks >= 1", fn);
+    } else {
+        if (v->max_bricks != 0) return set_error(PF_EINVAL, "%s: max_bricks must be 0 for a dense layout", fn);
+        if (v->ny > 65535 || v->nz > 65535)
+            return set_error(PF_EINVAL, "%s: ny and nz must be <= 65535", fn);
+        if ((int64_t)v->nx * v->ny * v->nz >= ((int64_t)1 << 31))
+            return set_error(PF_EINVAL, "%s: volume of %lld voxels exceeds 2^31 - 1", fn,
+                             (long long)v->nx * v->ny * v->nz);
+    }
     if (v->format != PF_F32_W_F32 && v->format != PF_F16_W_U8 && v->format != PF_I16_W_U8)
         return set_error(PF_EINVAL, "%s: unknown format %d", fn, v->format);
     if (!(v->voxel_size > 0.0) || !isfinite(v->voxel_size))
@@ -84,7 +126,7 @@ int32_t check_tsdf(const pf_tsdf* v, const char* fn, bool need_weight = true) {
     for (int a = 0; a < 3; ++a)
         if (!isfinite(v->origin[a])) return set_error(PF_EINVAL, "%s: origin must be finite", fn);
     if (v->w_max < 1 || v->w_max > 255) return set_error(PF_EINVAL, "%s: w_max %d not in 1..255", fn, v->w_max);
-    if (v->layout != PF_LAYOUT_LINEAR && v->layout != PF_LAYOUT_CELLS)
+    if (v->layout != PF_LAYOUT_LINEAR && v->layout != PF_LAYOUT_CELLS && v->layout != PF_LAYOUT_BRICKS)
         return set_error(PF_EINVAL, "%s: unknown layout %d", fn, v->layout);
     if (!v->tsdf) return set_error(PF_EINVAL, "%s: null tsdf pointer", fn);
     if (need_weight && !v->weight) return set_error(PF_EINVAL, "%s: null weight pointer", fn);
@@ -177,9 +219,17 @@ const char* pf_last_error(void) { return g_err; }
 size_t tsdf_bytes(const pf_tsdf* v, size_t* weight_bytes) {
     if (weight_bytes) *weight_bytes = 0;
     if (!v || v->nx < 2 || v->ny < 2 || v->nz < 2) return 0;
+    if (v->format != PF_F32_W_F32 && v->format != PF_F16_W_U8 && v->format != PF_I16_W_U8) return 0;
+    if (v->layout == PF_LAYOUT_BRICKS) {
+        if (v->nx % kBrickEdge || v->ny % kBrickEdge || v->nz % kBrickEdge || v->max_bricks < 1 || v->reserved) return 0;
+        if ((int64_t)(v->nx / kBrickEdge) * (v->ny / kBrickEdge) * (v->nz / kBrickEdge) >= ((int64_t)1 << 31)) return 0;
+        const BrickLayout L = brick_layout(v);
+        if (weight_bytes) *weight_bytes = L.w_total;
+        return L.t_total;
+    }
+    if (v->max_bricks != 0 || v->reserved) return 0;
     const int64_t n = (int64_t)v->nx * v->ny * v->nz;
     if (n >= ((int64_t)1 << 31)) return 0;
-    if (v->format != PF_F32_W_F32 && v->format != PF_F16_W_U8 && v->format != PF_I16_W_U8) return 0;
     if (v->layout != PF_LAYOUT_LINEAR && v->layout != PF_LAYOUT_CELLS) return 0;
     const size_t tb = t_elem_bytes(v->format), wb = v->format == PF_F32_W_F32 ? 4 : 1;
     if (weight_bytes) *weight_bytes = (size_t)n * wb;
@@ -191,6 +241,30 @@ size_t tsdf_bytes(const pf_tsdf* v, size_t* weight_bytes) {
 size_t tsdf_cells_offset(const pf_tsdf* v) {
     if (!v || tsdf_bytes(v, nullptr) == 0) return 0;
     return cells_offset_bytes(v);
+}
+
+int32_t tsdf_brick_offsets(const pf_tsdf* v, size_t* index, size_t* coords, size_t* pool_t, size_t* pool_cells) {
+    if (!v || v->layout != PF_LAYOUT_BRICKS || tsdf_bytes(v, nullptr) == 0)
+        return set_error(PF_EINVAL, "tsdf_brick_offsets: not a valid BRICKS description");
+    const BrickLayout L = brick_layout(v);
+    if (index) *index = L.index;
+    if (coords) *coords = L.coords;
+    if (pool_t) *pool_t = L.pool_t;
+    if (pool_cells) *pool_cells = L.pool_cells;
+    return PF_OK;
+}
+
+int32_t tsdf_bricks_used(const pf_tsdf* v, int32_t* n_bricks, int32_t* overflow, void* stream) {
+    int32_t rc = check_tsdf(v, "tsdf_bricks_used", false);
+    if (rc) return rc;
+    if (v->layout != PF_LAYOUT_BRICKS) return set_error(PF_EINVAL, "tsdf_bricks_used: not a BRICKS volume");
+    BrickHeader h;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(&h, v->tsdf, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return set_error(PF_EHIP, "tsdf_bricks_used: read-back failed");
+    if (n_bricks) *n_bricks = h.n < v->max_bricks ? h.n : v->max_bricks;
+    if (overflow) *overflow = h.overflow;
+    return PF_OK;
 }
 
 int32_t tsdf_init(const pf_tsdf* v, void* stream) {
@@ -213,6 +287,8 @@ int32_t tsdf_export_linear(const pf_tsdf* v, float* T_out, float* W_out, void* s
     int32_t rc = check_tsdf(v, "tsdf_export_linear", W_out != nullptr);
     if (rc) return rc;
     if (!T_out) return set_error(PF_EINVAL, "tsdf_export_linear: null T_out");
+    if ((int64_t)v->nx * v->ny * v->nz >= ((int64_t)1 << 31))
+        return set_error(PF_EUNSUPPORTED, "tsdf_export_linear: a linear copy needs < 2^31 voxels");
     return launch_tsdf_export(v, T_out, W_out, (hipStream_t)stream);
 }
 
@@ -220,6 +296,8 @@ int32_t tsdf_import_linear(const pf_tsdf* v, const float* T_in, const float* W_i
     int32_t rc = check_tsdf(v, "tsdf_import_linear");
     if (rc) return rc;
     if (!T_in) return set_error(PF_EINVAL, "tsdf_import_linear: null T_in");
+    if ((int64_t)v->nx * v->ny * v->nz >= ((int64_t)1 << 31))
+        return set_error(PF_EUNSUPPORTED, "tsdf_import_linear: a linear copy needs < 2^31 voxels");
     return launch_tsdf_import(v, T_in, W_in, (hipStream_t)stream);
 }
 

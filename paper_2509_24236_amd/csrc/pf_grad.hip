@@ -73,22 +73,10 @@ int32_t pose_partials_t(const VolView& vv, const Points& p, const double* poses,
 
 }  // namespace
 
-#define PF_DISPATCH(vv, FN, ...)                                                                        \
-    do {                                                                                                \
-        const bool cells_ = (vv).layout == PF_LAYOUT_CELLS;                                             \
-        switch ((vv).format) {                                                                          \
-            case PF_F32_W_F32:                                                                          \
-                return cells_ ? FN<PF_F32_W_F32, PF_LAYOUT_CELLS>(__VA_ARGS__)                          \
-                              : FN<PF_F32_W_F32, PF_LAYOUT_LINEAR>(__VA_ARGS__);                        \
-            case PF_F16_W_U8:                                                                           \
-                return cells_ ? FN<PF_F16_W_U8, PF_LAYOUT_CELLS>(__VA_ARGS__)                           \
-                              : FN<PF_F16_W_U8, PF_LAYOUT_LINEAR>(__VA_ARGS__);                         \
-            case PF_I16_W_U8:                                                                           \
-                return cells_ ? FN<PF_I16_W_U8, PF_LAYOUT_CELLS>(__VA_ARGS__)                           \
-                              : FN<PF_I16_W_U8, PF_LAYOUT_LINEAR>(__VA_ARGS__);                         \
-            default: return set_error(PF_EUNSUPPORTED, "unsupported format %d", (vv).format);          \
-        }                                                                                               \
-    } while (0)
+#define PF_DISPATCH(vv, FN, ...)                                                                 \
+    return with_volume((vv).format, (vv).layout, [&](auto fmt_, auto layout_) {                      \
+        return FN<decltype(fmt_)::value, decltype(layout_)::value>(__VA_ARGS__);                     \
+    })
 
 int32_t launch_grad(const VolView& vv, const Points& p, const double* base, const double* xi, int B, int S, int mode,
                     float* E, float* g, int* nv, GradPartial* partials, hipStream_t s) {

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/profusion.h"
 
 namespace pf {
@@ -85,14 +87,59 @@ __device__ inline void store_pose12(float* dst, const double R[9], const double 
 
 // ------------------------------------------------------------------ volume view for kernels
 struct VolView {
-    const void* T;       // x-fastest storage
-    const void* cells;   // cell-major replica (PF_LAYOUT_CELLS), else nullptr
+    const void* T;       // x-fastest storage (dense layouts) or the slots' T (BRICKS)
+    const void* cells;   // cell-major replica (PF_LAYOUT_CELLS) or the slots' cells (BRICKS), else nullptr
+    const int* bindex;   // BRICKS: brick-index grid, else nullptr
+    const void* ones;    // BRICKS: one cell block of +1 (read for cells of bricks without a slot)
+    int nbx, nby;        // BRICKS: bricks along x and y
     int nx, ny, nz, format, layout;
     float inv_vs;        // 1 / voxel_size
     float gx0, gy0, gz0; // -origin / voxel_size: grid coordinate of the world origin
 };
 
 VolView make_view(const pf_tsdf* v);
+
+// Byte layout of a BRICKS T buffer (offsets from v->tsdf) and of its W buffer.
+constexpr int kBrickEdge = 8, kBrickVox = 512;
+struct BrickLayout {
+    int nbx, nby, nbz;
+    size_t index, coords, pool_t, pool_cells, t_total, w_total;
+};
+BrickLayout brick_layout(const pf_tsdf* v);
+
+// Header at the start of a BRICKS T buffer; a cell block of +1 follows at kBrickOnes.
+struct BrickHeader {
+    int n;          // slots in use
+    int overflow;   // 1 once an allocation found the pool full
+    int n_prev;     // slots in use before the current fusion
+    int pad;
+};
+constexpr size_t kBrickOnes = 64;
+
+// Calls fn(fmt, layout) with the volume's format and layout as std::integral_constant values,
+// so one generic lambda reaches the kernel instantiation of every supported pair.
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+template <int FMT, typename Fn>
+inline int32_t with_layout(int layout, Fn&& fn) {
+    switch (layout) {
+        case PF_LAYOUT_LINEAR: return fn(IC<FMT>{}, IC<PF_LAYOUT_LINEAR>{});
+        case PF_LAYOUT_CELLS: return fn(IC<FMT>{}, IC<PF_LAYOUT_CELLS>{});
+        case PF_LAYOUT_BRICKS: return fn(IC<FMT>{}, IC<PF_LAYOUT_BRICKS>{});
+        default: return set_error(PF_EUNSUPPORTED, "unsupported layout %d", layout);
+    }
+}
+
+template <typename Fn>
+inline int32_t with_volume(int format, int layout, Fn&& fn) {
+    switch (format) {
+        case PF_F32_W_F32: return with_layout<PF_F32_W_F32>(layout, fn);
+        case PF_F16_W_U8: return with_layout<PF_F16_W_U8>(layout, fn);
+        case PF_I16_W_U8: return with_layout<PF_I16_W_U8>(layout, fn);
+        default: return set_error(PF_EUNSUPPORTED, "unsupported format %d", format);
+    }
+}
 
 // Element size of T and W for a format, and the byte offset of the cell replica in the T buffer.
 size_t t_elem_bytes(int format);

@@ -88,7 +88,31 @@ struct Gather<FMT, PF_LAYOUT_LINEAR> {
     }
 };
 
-// Cell-major replica: the 8 corners of a cell are one aligned block (32 B in FP32, 16 B otherwise).
+// The 8 corners of a cell stored as one aligned block (32 B in FP32, 16 B otherwise).
+template <int FMT>
+__device__ inline void load_cell8(const typename Fmt<FMT>::T* p, float (&c)[8]) {
+    using ST = typename Fmt<FMT>::T;
+    if constexpr (FMT == PF_F32_W_F32) {
+        const float4 a = reinterpret_cast<const float4*>(p)[0];
+        const float4 b = reinterpret_cast<const float4*>(p)[1];
+        c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
+        c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
+    } else {
+        const uint4 w = reinterpret_cast<const uint4*>(p)[0];
+        const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            ST lo, hi;
+            const uint16_t l16 = (uint16_t)(q[e] & 0xffffu), h16 = (uint16_t)(q[e] >> 16);
+            __builtin_memcpy(&lo, &l16, 2);
+            __builtin_memcpy(&hi, &h16, 2);
+            c[2 * e] = Fmt<FMT>::val(lo);
+            c[2 * e + 1] = Fmt<FMT>::val(hi);
+        }
+    }
+}
+
+// Cell-major replica: the 8 corners of a cell are one aligned block.
 template <int FMT>
 struct Gather<FMT, PF_LAYOUT_CELLS> {
     using ST = typename Fmt<FMT>::T;
@@ -97,26 +121,25 @@ struct Gather<FMT, PF_LAYOUT_CELLS> {
     __device__ inline const ST* addr(int cx, int cy, int cz) const {
         return C + ((size_t)((cz * cnxy) + cy * cnx + cx) << 3);
     }
-    __device__ inline void load(const ST* p, float (&c)[8]) const {
-        if constexpr (FMT == PF_F32_W_F32) {
-            const float4 a = reinterpret_cast<const float4*>(p)[0];
-            const float4 b = reinterpret_cast<const float4*>(p)[1];
-            c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
-            c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
-        } else {
-            const uint4 w = reinterpret_cast<const uint4*>(p)[0];
-            const uint32_t q[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                ST lo, hi;
-                const uint16_t l16 = (uint16_t)(q[e] & 0xffffu), h16 = (uint16_t)(q[e] >> 16);
-                __builtin_memcpy(&lo, &l16, 2);
-                __builtin_memcpy(&hi, &h16, 2);
-                c[2 * e] = Fmt<FMT>::val(lo);
-                c[2 * e + 1] = Fmt<FMT>::val(hi);
-            }
-        }
+    __device__ inline void load(const ST* p, float (&c)[8]) const { load_cell8<FMT>(p, c); }
+};
+
+// Sparse bricks: the brick-index grid names the slot of the cell's 8x8x8 brick, whose cell
+// blocks are stored like the replica's; a cell of a brick without a slot reads a block of +1
+// (outside the band, so the sample is not valid), as the dense layouts would.
+template <int FMT>
+struct Gather<FMT, PF_LAYOUT_BRICKS> {
+    using ST = typename Fmt<FMT>::T;
+    const ST* __restrict__ C;     // the slots' cells
+    const ST* ones;               // one block of +1
+    const int* __restrict__ idx;  // brick-index grid
+    int nbx, nbxy;
+    __device__ inline const ST* addr(int cx, int cy, int cz) const {
+        const int slot = idx[(cz >> 3) * nbxy + (cy >> 3) * nbx + (cx >> 3)];
+        const int local = (cx & 7) | ((cy & 7) << 3) | ((cz & 7) << 6);
+        return slot < 0 ? ones : C + ((((size_t)slot << 9) | (size_t)local) << 3);
     }
+    __device__ inline void load(const ST* p, float (&c)[8]) const { load_cell8<FMT>(p, c); }
 };
 
 // Folds a float32 row-major 3x4 pose [R | t] into grid units: g = R (x / vs) + (t / vs + g0).
@@ -251,10 +274,16 @@ __host__ __device__ inline Gather<FMT, LAYOUT> make_gather(const VolView& vv) {
         G.T = static_cast<const typename Fmt<FMT>::T*>(vv.T);
         G.nx = vv.nx;
         G.nxy = vv.nx * vv.ny;
-    } else {
+    } else if constexpr (LAYOUT == PF_LAYOUT_CELLS) {
         G.C = static_cast<const typename Fmt<FMT>::T*>(vv.cells);
         G.cnx = vv.nx - 1;
         G.cnxy = (vv.nx - 1) * (vv.ny - 1);
+    } else {
+        G.C = static_cast<const typename Fmt<FMT>::T*>(vv.cells);
+        G.ones = static_cast<const typename Fmt<FMT>::T*>(vv.ones);
+        G.idx = vv.bindex;
+        G.nbx = vv.nbx;
+        G.nbxy = vv.nbx * vv.nby;
     }
     return G;
 }

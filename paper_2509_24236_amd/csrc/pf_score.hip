@@ -108,13 +108,6 @@ int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K,
     return launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, -1, s);
 }
 
-template <int FMT>
-int32_t launch_fmt(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
-                   const pf_track_state* st, hipStream_t s) {
-    if (vv.layout == PF_LAYOUT_CELLS) return launch_fl<FMT, PF_LAYOUT_CELLS>(vv, p, poses, K, fitness, n_valid, st, s);
-    return launch_fl<FMT, PF_LAYOUT_LINEAR>(vv, p, poses, K, fitness, n_valid, st, s);
-}
-
 }  // namespace
 
 int32_t score_config(int tk, int block) {
@@ -133,12 +126,9 @@ int32_t score_config(int tk, int block) {
 
 int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
                      hipStream_t s, const pf_track_state* st) {
-    switch (vv.format) {
-        case PF_F32_W_F32: return launch_fmt<PF_F32_W_F32>(vv, p, poses, K, fitness, n_valid, st, s);
-        case PF_F16_W_U8: return launch_fmt<PF_F16_W_U8>(vv, p, poses, K, fitness, n_valid, st, s);
-        case PF_I16_W_U8: return launch_fmt<PF_I16_W_U8>(vv, p, poses, K, fitness, n_valid, st, s);
-        default: return set_error(PF_EUNSUPPORTED, "particles_score: unsupported format %d", vv.format);
-    }
+    return with_volume(vv.format, vv.layout, [&](auto fmt, auto layout) {
+        return launch_fl<decltype(fmt)::value, decltype(layout)::value>(vv, p, poses, K, fitness, n_valid, st, s);
+    });
 }
 
 }  // namespace pf

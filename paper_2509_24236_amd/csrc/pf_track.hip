@@ -96,19 +96,9 @@ int32_t launch_adv_t(bool adv, const VolView& vv, const Points& p, int G, const 
 // adv = true: advantage set, P^(i) and the partials of E*; false: partials of the pending pose.
 int32_t launch_adv(bool adv, const VolView& vv, const Points& p, int G, const float* fitness, pf_track_state* st,
                    int K, hipStream_t s) {
-    const bool cells = vv.layout == PF_LAYOUT_CELLS;
-    switch (vv.format) {
-        case PF_F32_W_F32:
-            return cells ? launch_adv_t<PF_F32_W_F32, PF_LAYOUT_CELLS>(adv, vv, p, G, fitness, st, K, s)
-                         : launch_adv_t<PF_F32_W_F32, PF_LAYOUT_LINEAR>(adv, vv, p, G, fitness, st, K, s);
-        case PF_F16_W_U8:
-            return cells ? launch_adv_t<PF_F16_W_U8, PF_LAYOUT_CELLS>(adv, vv, p, G, fitness, st, K, s)
-                         : launch_adv_t<PF_F16_W_U8, PF_LAYOUT_LINEAR>(adv, vv, p, G, fitness, st, K, s);
-        case PF_I16_W_U8:
-            return cells ? launch_adv_t<PF_I16_W_U8, PF_LAYOUT_CELLS>(adv, vv, p, G, fitness, st, K, s)
-                         : launch_adv_t<PF_I16_W_U8, PF_LAYOUT_LINEAR>(adv, vv, p, G, fitness, st, K, s);
-        default: return set_error(PF_EUNSUPPORTED, "unsupported format %d", vv.format);
-    }
+    return with_volume(vv.format, vv.layout, [&](auto fmt, auto layout) {
+        return launch_adv_t<decltype(fmt)::value, decltype(layout)::value>(adv, vv, p, G, fitness, st, K, s);
+    });
 }
 
 int32_t launch_next(int format, bool first, pf_track_state* st, int K, int G, bool draw, float* next_poses,

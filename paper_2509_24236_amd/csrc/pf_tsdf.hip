@@ -126,10 +126,8 @@ struct FuseArgs {
 // running average is FP32.
 // Conservative FP32 pre-tests drop most voxels of the grid (behind the camera, or outside the image
 // by more than two pixels) before any FP64 work; each drops only voxels the FP64 test drops too.
-template <int FMT>
-__device__ inline void fuse_voxel(const FuseArgs& a, int i, int j, int k) {
-    using S = Store<FMT>;
-    const int64_t idx = ((int64_t)k * a.d.ny + j) * a.d.nx + i;
+// Returns whether voxel (i, j, k) is updated by this frame, and its observation phi.
+__device__ inline bool fuse_decide(const FuseArgs& a, int i, int j, int k, double& phi_out) {
     {
         // FP32 pre-test, conservative: it drops only voxels the FP64 test below drops too. The FP32
         // camera coordinates carry at most ~1e-5 m of error here (|q| < 10 m), so a voxel is
@@ -137,14 +135,14 @@ __device__ inline void fuse_voxel(const FuseArgs& a, int i, int j, int k) {
         // qz > 0.2 m (pixel error < 0.5) and more than two pixels beyond the border.
         const float fi = (float)i, fj = (float)j, fk = (float)k;
         const float z32 = a.q0[2] + fi * a.qi[2] + fj * a.qj[2] + fk * a.qk[2];
-        if (z32 < -1e-3f) return;
+        if (z32 < -1e-3f) return false;
         if (z32 > 0.2f) {
             const float x32 = a.q0[0] + fi * a.qi[0] + fj * a.qj[0] + fk * a.qk[0];
             const float y32 = a.q0[1] + fi * a.qi[1] + fj * a.qj[1] + fk * a.qk[1];
             const float iz = 1.0f / z32;
             const float u32 = (float)a.fx * x32 * iz + (float)a.cx;
             const float v32 = (float)a.fy * y32 * iz + (float)a.cy;
-            if (!(u32 > -2.5f && u32 < (float)a.width + 1.5f && v32 > -2.5f && v32 < (float)a.height + 1.5f)) return;
+            if (!(u32 > -2.5f && u32 < (float)a.width + 1.5f && v32 > -2.5f && v32 < (float)a.height + 1.5f)) return false;
         }
     }
     const double px = a.ox + a.vs * (double)i;
@@ -152,35 +150,54 @@ __device__ inline void fuse_voxel(const FuseArgs& a, int i, int j, int k) {
     const double pz = a.oz + a.vs * (double)k;
     const double dx = px - a.t[0], dy = py - a.t[1], dz = pz - a.t[2];
     const double qz = a.R[2] * dx + a.R[5] * dy + a.R[8] * dz;
-    if (!(qz > 0.0)) return;
+    if (!(qz > 0.0)) return false;
     const double qx = a.R[0] * dx + a.R[3] * dy + a.R[6] * dz;
     const double qy = a.R[1] * dx + a.R[4] * dy + a.R[7] * dz;
     if (qz > 1e-6) {   // (below, FP32 could overflow; the FP64 test decides alone)
         const float iz = 1.0f / (float)qz;
         const float uf32 = (float)a.fx * (float)qx * iz + (float)a.cx;
         const float vf32 = (float)a.fy * (float)qy * iz + (float)a.cy;
-        if (!(uf32 > -2.5f && uf32 < (float)a.width + 1.5f && vf32 > -2.5f && vf32 < (float)a.height + 1.5f)) return;
+        if (!(uf32 > -2.5f && uf32 < (float)a.width + 1.5f && vf32 > -2.5f && vf32 < (float)a.height + 1.5f)) return false;
     }
     const double u = a.fx * qx / qz + a.cx;
     const double v = a.fy * qy / qz + a.cy;
     const double uf = floor(u + 0.5), vf = floor(v + 0.5);
-    if (uf < 0.0 || uf >= (double)a.width || vf < 0.0 || vf >= (double)a.height) return;
+    if (uf < 0.0 || uf >= (double)a.width || vf < 0.0 || vf >= (double)a.height) return false;
     const int ui = (int)uf, vi = (int)vf;
     const double D = (double)a.depth[(int64_t)vi * a.width + ui];
-    if (!(isfinite(D) && D > 0.0)) return;
+    if (!(isfinite(D) && D > 0.0)) return false;
     const double eta = D - qz;
-    if (eta < -a.tau) return;
+    if (eta < -a.tau) return false;
     double phi = eta / a.tau;
     if (phi > 1.0) phi = 1.0;
+    phi_out = phi;
+    return true;
+}
+
+// The running-average update of one stored voxel (T[e], W[e]); returns whether T changed.
+template <int FMT>
+__device__ inline bool fuse_apply(const FuseArgs& a, int64_t e, double phi, typename Store<FMT>::T& tnew) {
+    using S = Store<FMT>;
     auto* T = static_cast<typename S::T*>(a.T);
     auto* W = static_cast<typename S::W*>(a.W);
-    const typename S::T told = T[idx];
-    const float w = S::decw(W[idx]);
+    const typename S::T told = T[e];
+    const float w = S::decw(W[e]);
     const float tn = (S::dec(told) * w + (float)phi) / (w + 1.0f);
-    const typename S::T tnew = S::enc(tn);
-    if (!S::same(told, tnew)) T[idx] = tnew;
-    W[idx] = S::encw(fminf(w + 1.0f, a.w_max));
-    if (a.C && !S::same(told, tnew)) write_corners(static_cast<typename S::T*>(a.C), a.d, i, j, k, tnew);
+    tnew = S::enc(tn);
+    const bool changed = !S::same(told, tnew);
+    if (changed) T[e] = tnew;
+    W[e] = S::encw(fminf(w + 1.0f, a.w_max));
+    return changed;
+}
+
+template <int FMT>
+__device__ inline void fuse_voxel(const FuseArgs& a, int i, int j, int k) {
+    double phi;
+    if (!fuse_decide(a, i, j, k, phi)) return;
+    typename Store<FMT>::T tnew;
+    const int64_t idx = ((int64_t)k * a.d.ny + j) * a.d.nx + i;
+    if (fuse_apply<FMT>(a, idx, phi, tnew) && a.C)
+        write_corners(static_cast<typename Store<FMT>::T*>(a.C), a.d, i, j, k, tnew);
 }
 
 // Grid: a workgroup owns a brick of kFuseX x kFuseY x kFuseZ voxels (a wave per x row, each thread
@@ -272,6 +289,218 @@ __global__ __launch_bounds__(kBlock) void k_build_cells(const void* Tv, void* Cv
     }
 }
 
+// ---------------------------------------------------------------- sparse bricks (PF_LAYOUT_BRICKS)
+// Bricks of 8x8x8 voxels in a pool behind a dense brick-index grid. A fusion first marks the bricks
+// the frame puts a band voxel into (one workgroup per brick of the grid, culled like the dense
+// path, then the same FP64 decision per voxel) and gives each a pool slot, initialises the new
+// slots, and then updates every allocated brick exactly as the dense layouts update a voxel.
+struct BrickArgs {
+    BrickHeader* hdr;
+    int* index;     // brick-index grid: slot or -1
+    int4* coords;   // slot -> brick coordinates
+    void* T;        // slots' T, 512 each
+    void* C;        // slots' cells, 512 x 8 each
+    void* W;        // slots' W
+    int nbx, nby, nbz, max_bricks;
+};
+
+BrickArgs brick_args(const pf_tsdf* v) {
+    const BrickLayout L = brick_layout(v);
+    char* base = static_cast<char*>(v->tsdf);
+    BrickArgs b;
+    b.hdr = reinterpret_cast<BrickHeader*>(base);
+    b.index = reinterpret_cast<int*>(base + L.index);
+    b.coords = reinterpret_cast<int4*>(base + L.coords);
+    b.T = base + L.pool_t;
+    b.C = base + L.pool_cells;
+    b.W = v->weight;
+    b.nbx = L.nbx;
+    b.nby = L.nby;
+    b.nbz = L.nbz;
+    b.max_bricks = v->max_bricks;
+    return b;
+}
+
+__device__ inline int brick_slot(const BrickArgs& b, int bx, int by, int bz) {
+    if (bx < 0 || by < 0 || bz < 0 || bx >= b.nbx || by >= b.nby || bz >= b.nbz) return -1;
+    return b.index[((int64_t)bz * b.nby + by) * b.nbx + bx];
+}
+
+__device__ inline int brick_local(int i, int j, int k) { return (i & 7) | ((j & 7) << 3) | ((k & 7) << 6); }
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_bricks_reset(BrickArgs b, int64_t n_index) {
+    if (blockIdx.x == 0 && threadIdx.x < 8) {
+        if (threadIdx.x == 0) *b.hdr = BrickHeader{0, 0, 0, 0};
+        reinterpret_cast<typename Store<FMT>::T*>(reinterpret_cast<char*>(b.hdr) + kBrickOnes)[threadIdx.x] =
+            Store<FMT>::enc(1.0f);
+    }
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n_index; i += stride) b.index[i] = -1;
+}
+
+// Start of a fusion: the count comes back to the pool size after an overflow, and the slots
+// in use so far are recorded.
+__global__ void k_bricks_prep(BrickArgs b) {
+    const int n = min(b.hdr->n, b.max_bricks);
+    b.hdr->n = n;
+    b.hdr->n_prev = n;
+}
+
+// Gives a slot to a brick that has none and holds a voxel this frame puts in the band
+// (-tau <= eta < tau: updated with phi < 1). Only the brick's own workgroup touches its entry.
+__global__ __launch_bounds__(kBlock) void k_bricks_mark(FuseArgs a, BrickArgs b) {
+    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    const int64_t e_idx = ((int64_t)bz * b.nby + by) * b.nbx + bx;
+    if (b.index[e_idx] >= 0) return;
+    const int i0 = bx * kBrickEdge, j0 = by * kBrickEdge, k0 = bz * kBrickEdge;
+    if (brick_outside(a, i0, j0, k0, i0 + 7, j0 + 7, k0 + 7)) return;
+    int band = 0;
+    for (int e = threadIdx.x; e < kBrickVox; e += kBlock) {
+        double phi;
+        if (fuse_decide(a, i0 + (e & 7), j0 + ((e >> 3) & 7), k0 + (e >> 6), phi) && phi < 1.0) band = 1;
+    }
+    if (!__syncthreads_or(band)) return;
+    if (threadIdx.x == 0) {
+        const int slot = atomicAdd(&b.hdr->n, 1);
+        if (slot < b.max_bricks) {
+            b.coords[slot] = make_int4(bx, by, bz, 0);
+            b.index[e_idx] = slot;
+        } else {
+            atomicOr(&b.hdr->overflow, 1);
+        }
+    }
+}
+
+// Value of voxel (i, j, k) for a cell corner: from slot s < src_limit, +1 elsewhere.
+template <int FMT>
+__device__ inline typename Store<FMT>::T brick_voxel(const BrickArgs& b, const Dims& d, int i, int j, int k,
+                                                     int src_limit) {
+    using S = Store<FMT>;
+    if (i >= d.nx || j >= d.ny || k >= d.nz) return S::enc(1.0f);
+    const int s2 = brick_slot(b, i >> 3, j >> 3, k >> 3);
+    if (s2 < 0 || s2 >= src_limit) return S::enc(1.0f);
+    return static_cast<const typename S::T*>(b.T)[((int64_t)s2 << 9) + brick_local(i, j, k)];
+}
+
+// Cells of slots [begin, end), corners read from slots below src_limit (+1 elsewhere). With
+// init, the slots' own T and W are first set to +1 and 0 (their corners read +1 either way).
+template <int FMT, bool INIT>
+__global__ __launch_bounds__(kBlock) void k_bricks_cells(BrickArgs b, Dims d, int first_new) {
+    using S = Store<FMT>;
+    const int n_now = min(b.hdr->n, b.max_bricks);
+    const int begin = first_new ? b.hdr->n_prev : 0, src_limit = INIT ? b.hdr->n_prev : n_now;
+    auto* T = static_cast<typename S::T*>(b.T);
+    auto* W = static_cast<typename S::W*>(b.W);
+    auto* C = static_cast<typename S::T*>(b.C);
+    for (int slot = begin + blockIdx.x; slot < n_now; slot += gridDim.x) {
+        const int4 c = b.coords[slot];
+        for (int e = threadIdx.x; e < kBrickVox; e += kBlock) {
+            if (INIT) {
+                T[((int64_t)slot << 9) + e] = S::enc(1.0f);
+                W[((int64_t)slot << 9) + e] = S::encw(0.0f);
+            }
+            const int i = c.x * kBrickEdge + (e & 7), j = c.y * kBrickEdge + ((e >> 3) & 7), k = c.z * kBrickEdge + (e >> 6);
+            typename S::T* o = C + ((((int64_t)slot << 9) + e) << 3);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                o[q] = brick_voxel<FMT>(b, d, i + (q & 1), j + ((q >> 1) & 1), k + (q >> 2), src_limit);
+        }
+    }
+}
+
+// Writes voxel (i, j, k)'s value into every allocated cell that has it as a corner.
+template <typename T>
+__device__ inline void write_corners_bricks(const BrickArgs& b, const Dims& d, int i, int j, int k, T val) {
+    T* C = static_cast<T*>(b.C);
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int ci = i - dx, cj = j - dy, ck = k - dz;
+                if (ci < 0 || cj < 0 || ck < 0 || ci >= d.nx - 1 || cj >= d.ny - 1 || ck >= d.nz - 1) continue;
+                const int s2 = brick_slot(b, ci >> 3, cj >> 3, ck >> 3);
+                if (s2 < 0) continue;
+                C[((((int64_t)s2 << 9) + brick_local(ci, cj, ck)) << 3) + (dx + 2 * dy + 4 * dz)] = val;
+            }
+}
+
+// Fusion of every allocated brick (persistent over the slots in use).
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_bricks_integrate(FuseArgs a, BrickArgs b) {
+    const int n_now = min(b.hdr->n, b.max_bricks);
+    for (int slot = blockIdx.x; slot < n_now; slot += gridDim.x) {
+        const int4 c = b.coords[slot];
+        const int i0 = c.x * kBrickEdge, j0 = c.y * kBrickEdge, k0 = c.z * kBrickEdge;
+        if (brick_outside(a, i0, j0, k0, i0 + 7, j0 + 7, k0 + 7)) continue;
+        for (int e = threadIdx.x; e < kBrickVox; e += kBlock) {
+            const int i = i0 + (e & 7), j = j0 + ((e >> 3) & 7), k = k0 + (e >> 6);
+            double phi;
+            if (!fuse_decide(a, i, j, k, phi)) continue;
+            typename Store<FMT>::T tnew;
+            if (fuse_apply<FMT>(a, ((int64_t)slot << 9) + e, phi, tnew)) write_corners_bricks(b, a.d, i, j, k, tnew);
+        }
+    }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_bricks_export(BrickArgs b, Dims d, float* To, float* Wo) {
+    using S = Store<FMT>;
+    const auto* T = static_cast<const typename S::T*>(b.T);
+    const auto* W = static_cast<const typename S::W*>(b.W);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < d.n; v += stride) {
+        const int i = (int)(v % d.nx), j = (int)((v / d.nx) % d.ny), k = (int)(v / ((int64_t)d.nx * d.ny));
+        const int s2 = brick_slot(b, i >> 3, j >> 3, k >> 3);
+        const int64_t e = ((int64_t)max(s2, 0) << 9) + brick_local(i, j, k);   // slot 0 always exists
+        To[v] = s2 < 0 ? 1.0f : S::dec(T[e]);
+        if (Wo) Wo[v] = s2 < 0 ? 0.0f : S::decw(W[e]);
+    }
+}
+
+// Import: one workgroup per brick gives a slot to bricks holding any voxel other than
+// (T, W) = (+1, 0), then the slots are filled from the linear arrays.
+__global__ __launch_bounds__(kBlock) void k_bricks_import_mark(BrickArgs b, Dims d, const float* Ti, const float* Wi) {
+    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    int need = 0;
+    for (int e = threadIdx.x; e < kBrickVox; e += kBlock) {
+        const int i = bx * kBrickEdge + (e & 7), j = by * kBrickEdge + ((e >> 3) & 7), k = bz * kBrickEdge + (e >> 6);
+        const int64_t v = ((int64_t)k * d.ny + j) * d.nx + i;
+        if (Ti[v] != 1.0f || (Wi && Wi[v] != 0.0f)) need = 1;
+    }
+    if (!__syncthreads_or(need)) return;
+    if (threadIdx.x == 0) {
+        const int slot = atomicAdd(&b.hdr->n, 1);
+        if (slot < b.max_bricks) {
+            b.coords[slot] = make_int4(bx, by, bz, 0);
+            b.index[((int64_t)bz * b.nby + by) * b.nbx + bx] = slot;
+        } else {
+            atomicOr(&b.hdr->overflow, 1);
+        }
+    }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_bricks_import_fill(BrickArgs b, Dims d, const float* Ti, const float* Wi) {
+    using S = Store<FMT>;
+    auto* T = static_cast<typename S::T*>(b.T);
+    auto* W = static_cast<typename S::W*>(b.W);
+    const int n_now = min(b.hdr->n, b.max_bricks);
+    for (int slot = blockIdx.x; slot < n_now; slot += gridDim.x) {
+        const int4 c = b.coords[slot];
+        for (int e = threadIdx.x; e < kBrickVox; e += kBlock) {
+            const int i = c.x * kBrickEdge + (e & 7), j = c.y * kBrickEdge + ((e >> 3) & 7), k = c.z * kBrickEdge + (e >> 6);
+            const int64_t v = ((int64_t)k * d.ny + j) * d.nx + i;
+            T[((int64_t)slot << 9) + e] = S::enc(Ti[v]);
+            W[((int64_t)slot << 9) + e] = S::encw(Wi ? Wi[v] : 0.0f);
+        }
+    }
+}
+
+constexpr int kBrickGrid = 4096;   // persistent workgroups over the slots
+
 int grid_for(int64_t n) {
     const int64_t b = (n + kBlock - 1) / kBlock;
     return (int)(b < 65536 ? b : 65536);
@@ -282,7 +511,16 @@ void* cells_ptr(const pf_tsdf* v) {
 }
 
 template <int FMT>
+int32_t bricks_reset(const pf_tsdf* v, hipStream_t s) {
+    const BrickArgs b = brick_args(v);
+    const int64_t n_index = (int64_t)b.nbx * b.nby * b.nbz;
+    hipLaunchKernelGGL(k_bricks_reset<FMT>, dim3(grid_for(n_index)), dim3(kBlock), 0, s, b, n_index);
+    return check_launch("tsdf_init (bricks)");
+}
+
+template <int FMT>
 int32_t init_t(const pf_tsdf* v, hipStream_t s) {
+    if (v->layout == PF_LAYOUT_BRICKS) return bricks_reset<FMT>(v, s);
     const Dims d = dims_of(v);
     hipLaunchKernelGGL(k_init<FMT>, dim3(grid_for(d.n * 8)), dim3(kBlock), 0, s, v->tsdf, v->weight, cells_ptr(v), d);
     return check_launch("tsdf_init");
@@ -316,6 +554,18 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
     a.height = K->height;
     a.w_max = (float)v->w_max;
     a.depth = depth;
+    if (v->layout == PF_LAYOUT_BRICKS) {
+        const BrickArgs b = brick_args(v);
+        a.T = b.T;
+        a.W = b.W;
+        a.C = nullptr;
+        hipLaunchKernelGGL(k_bricks_prep, dim3(1), dim3(1), 0, s, b);
+        hipLaunchKernelGGL(k_bricks_mark, dim3((unsigned)b.nbx, (unsigned)b.nby, (unsigned)b.nbz), dim3(kBlock), 0, s,
+                           a, b);
+        hipLaunchKernelGGL((k_bricks_cells<FMT, true>), dim3(kBrickGrid), dim3(kBlock), 0, s, b, a.d, 1);
+        hipLaunchKernelGGL(k_bricks_integrate<FMT>, dim3(kBrickGrid), dim3(kBlock), 0, s, a, b);
+        return check_launch("tsdf_integrate (bricks)");
+    }
     const dim3 grid((unsigned)((a.d.nx + kFuseX - 1) / kFuseX), (unsigned)((a.d.ny + kFuseY - 1) / kFuseY),
                     (unsigned)((a.d.nz + kFuseZ - 1) / kFuseZ));
     hipLaunchKernelGGL(k_integrate<FMT>, grid, dim3(kBlock), 0, s, a);
@@ -325,6 +575,10 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
 template <int FMT>
 int32_t export_t(const pf_tsdf* v, float* T, float* W, hipStream_t s) {
     const Dims d = dims_of(v);
+    if (v->layout == PF_LAYOUT_BRICKS) {
+        hipLaunchKernelGGL(k_bricks_export<FMT>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, brick_args(v), d, T, W);
+        return check_launch("tsdf_export_linear (bricks)");
+    }
     hipLaunchKernelGGL(k_export<FMT>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, v->tsdf, v->weight, d, T, W);
     return check_launch("tsdf_export_linear");
 }
@@ -332,6 +586,16 @@ int32_t export_t(const pf_tsdf* v, float* T, float* W, hipStream_t s) {
 template <int FMT>
 int32_t import_t(const pf_tsdf* v, const float* T, const float* W, hipStream_t s) {
     const Dims d = dims_of(v);
+    if (v->layout == PF_LAYOUT_BRICKS) {
+        int32_t rc = bricks_reset<FMT>(v, s);
+        if (rc) return rc;
+        const BrickArgs b = brick_args(v);
+        hipLaunchKernelGGL(k_bricks_import_mark, dim3((unsigned)b.nbx, (unsigned)b.nby, (unsigned)b.nbz), dim3(kBlock),
+                           0, s, b, d, T, W);
+        hipLaunchKernelGGL(k_bricks_import_fill<FMT>, dim3(kBrickGrid), dim3(kBlock), 0, s, b, d, T, W);
+        hipLaunchKernelGGL((k_bricks_cells<FMT, false>), dim3(kBrickGrid), dim3(kBlock), 0, s, b, d, 0);
+        return check_launch("tsdf_import_linear (bricks)");
+    }
     hipLaunchKernelGGL(k_import<FMT>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, v->tsdf, v->weight, d, T, W);
     int32_t rc = check_launch("tsdf_import_linear");
     if (rc || v->layout != PF_LAYOUT_CELLS) return rc;

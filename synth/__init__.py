@@ -350,6 +350,18 @@ def cfg2_frames(n_frames=CFG2_LENGTH, traj_seed=11, scene_seed=10, noise_seed=12
     return {"scene": scene, "intr": CFG2_INTR, "vol": vol, "gt": gt, "rel": rel, "depth": depth}
 
 
+def room_spec(scene, voxel_size: float, trunc: float, edge: int = 8) -> VolumeSpec:
+    """A grid over the whole room of a scene whose room frame is axis-aligned with the world (as
+    cfg2's is: its frame-0 camera has no rotation), with one truncation distance of margin beyond
+    every wall, each dimension rounded up to a multiple of `edge` (the brick edge)."""
+    assert np.allclose(scene["R_wr"], np.eye(3)), "the room must be axis-aligned with the world"
+    ext = scene["room_hi"] - scene["room_lo"] + 2.0 * trunc
+    n = [int(math.ceil(e / voxel_size / edge - 1e-9)) * edge for e in ext]
+    c = room_centre_world(scene)
+    o = tuple(float(c[a]) - 0.5 * n[a] * voxel_size + 0.5 * voxel_size for a in range(3))
+    return VolumeSpec(n[0], n[1], n[2], float(voxel_size), float(trunc), o)
+
+
 # ----------------------------------------------------------------------------- batched problems
 def random_depth_for_batch(p: int, base_seed=40):
     """One of the 64 heterogeneous tracking problems: its own small room, resolution drawn

@@ -93,7 +93,14 @@ def test_tsdf_bytes(pf):
         assert off >= 16 * 8 * 4 * tb and off % 256 == 0
         assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == off + 15 * 7 * 3 * 8 * tb
     assert L.tsdf_cells_offset(C.byref(_desc(pf, 16, 8, 4, 0, layout=0))) == 0
-    assert L.tsdf_bytes(C.byref(_desc(pf, layout=2)), C.byref(wb)) == 0
+    assert L.tsdf_bytes(C.byref(_desc(pf, layout=5)), C.byref(wb)) == 0
+    assert L.tsdf_bytes(C.byref(_desc(pf, layout=2)), C.byref(wb)) == 0    # BRICKS without a pool
+    d = _desc(pf)
+    d.max_bricks = 4
+    assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == 0                      # a pool on a dense layout
+    d = _desc(pf)
+    d.reserved = 1
+    assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == 0
     assert L.tsdf_bytes(C.byref(_desc(pf, 1, 8, 8)), C.byref(wb)) == 0
     assert L.tsdf_bytes(C.byref(_desc(pf, fmt=7)), C.byref(wb)) == 0
     assert L.tsdf_bytes(None, None) == 0
@@ -230,3 +237,44 @@ def test_score_config_validation(pf):
             assert b"pf_score_config" in L.pf_last_error()
     finally:
         L.pf_score_config(0, 0)
+
+
+def _al(x):
+    return (x + 255) // 256 * 256
+
+
+def test_brick_pool_bytes_and_offsets(pf):
+    """BRICKS: 256-byte header, index grid, slot coordinates, the slots' T and cells in the T
+    buffer, the slots' W in the W buffer; dims must be multiples of 8 and the pool non-empty."""
+    L = pf.lib()
+    wb = C.c_size_t()
+    for fmt, (tb, wbb) in {0: (4, 4), 1: (2, 1), 2: (2, 1)}.items():
+        d = _desc(pf, 64, 40, 24, fmt, layout=2)
+        d.max_bricks = 37
+        nb = 8 * 5 * 3
+        o = [C.c_size_t() for _ in range(4)]
+        assert L.tsdf_brick_offsets(C.byref(d), *[C.byref(x) for x in o]) == pf.PF_OK
+        index, coords, pool_t, pool_cells = (x.value for x in o)
+        assert index == 256
+        assert coords == index + _al(nb * 4)
+        assert pool_t == coords + _al(37 * 16)
+        assert pool_cells == pool_t + _al(37 * 512 * tb)
+        assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == pool_cells + 37 * 512 * 8 * tb
+        assert wb.value == 37 * 512 * wbb
+        assert all(x % 256 == 0 for x in (index, coords, pool_t, pool_cells))
+    for nx, ny, nz, mb in ((60, 40, 24, 4), (64, 40, 20, 4), (64, 40, 24, 0), (64, 40, 24, -1)):
+        d = _desc(pf, nx, ny, nz, 0, layout=2)
+        d.max_bricks = mb
+        assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == 0
+        _rc(pf, L.tsdf_init(C.byref(d), None), "BRICKS")
+        _rc(pf, L.tsdf_brick_offsets(C.byref(d), None, None, None, None), "BRICKS")
+    # larger than a dense grid may be: 4096^3 voxels, 2^27 index entries
+    d = _desc(pf, 4096, 4096, 4096, 1, layout=2)
+    d.max_bricks = 1 << 20
+    assert L.tsdf_bytes(C.byref(d), C.byref(wb)) > 0
+    d = _desc(pf, 8, 8, 8, 0, layout=1)
+    _rc(pf, L.tsdf_brick_offsets(C.byref(d), None, None, None, None), "BRICKS")
+    _rc(pf, L.tsdf_bricks_used(C.byref(d), None, None, None), "BRICKS")
+    d = _desc(pf, 8, 8, 8, 0, layout=1)
+    d.reserved = 3
+    _rc(pf, L.tsdf_init(C.byref(d), None), "reserved")

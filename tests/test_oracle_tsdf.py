@@ -244,3 +244,83 @@ def test_fitness_interval_contains_value(orc):
     lo0, hi0, na0 = vol.fitness_interval_many(X, poses, eps=0.0)
     assert np.all(na0 == 0) and np.array_equal(lo0, hi0)
     assert np.abs(lo0 - E).max() <= 1e-15
+
+
+# ----------------------------------------------------------------------------- sparse bricks
+def test_integrate_bricks_matches_dense_per_brick(orc):
+    """The bricked reading, rebuilt from the dense fusion: a brick is recorded at the first frame
+    whose dense fusion into an empty volume leaves one of its voxels below +1 (phi < 1: in the
+    band), and from then on its voxels hold the dense fusion of exactly the frames since then;
+    every other voxel stays (+1, 0)."""
+    d = synth.cfg1_inputs()
+    E = 8
+    spec = synth.VolumeSpec.centred(48, 0.05, 0.15, synth.room_centre_world(d["scene"]))
+    rng = np.random.default_rng(21)
+    frames = []
+    for f in range(4):
+        R = Rotation.from_rotvec(rng.normal(size=3) * 0.15).as_matrix()
+        t = rng.normal(size=3) * 0.1
+        frames.append((synth.render_depth(d["scene"], d["intr"], R, t), R, t))
+    sparse = orc.Volume(spec)
+    nb = (spec.nz // E, spec.ny // E, spec.nx // E)
+
+    def per_brick(mask_vox):
+        return mask_vox.reshape(nb[0], E, nb[1], E, nb[2], E).any(axis=(1, 3, 5))
+
+    first = np.full(nb, -1)
+    for f, (depth, R, t) in enumerate(frames):
+        fresh = orc.Volume(spec)
+        fresh.integrate(depth, d["intr"], R, t)
+        band = per_brick(fresh.T < 1.0)
+        new = band & (first < 0)
+        first[new] = f
+        assert sparse.integrate_bricks(depth, d["intr"], R, t, edge=E) == int(new.sum())
+        assert np.array_equal(sparse.bricks.astype(bool), first >= 0)
+    assert 0 < (first >= 0).sum() < first.size            # some bricks stay free space
+    assert len(set(first[first >= 0].tolist())) > 1        # and some are recorded late
+    # expected volume: per brick, the dense fusion of the frames from its first one on
+    exp_T, exp_W = np.ones(sparse.T.shape), np.zeros(sparse.T.shape)
+    for f0 in sorted(set(first[first >= 0].tolist())):
+        dense = orc.Volume(spec)
+        for depth, R, t in frames[f0:]:
+            dense.integrate(depth, d["intr"], R, t)
+        m = np.repeat(np.repeat(np.repeat(first == f0, E, 0), E, 1), E, 2)
+        exp_T[m], exp_W[m] = dense.T[m], dense.W[m]
+    assert np.array_equal(sparse.T, exp_T) and np.array_equal(sparse.W, exp_W)
+    # the dense fusion also updates free space in front of surfaces, which the bricks leave out
+    dense_all = orc.Volume(spec)
+    for depth, R, t in frames:
+        dense_all.integrate(depth, d["intr"], R, t)
+    assert ((dense_all.W > 0) & (sparse.W == 0)).sum() > 100
+
+
+def test_integrate_bricks_plane_records_only_the_band(orc):
+    """A fronto-parallel plane filling the image: the recorded bricks are exactly those that hold
+    a voxel with -tau <= eta < tau inside the view, from the closed-form projective distance
+    (bricks whose only such voxels sit within 1e-6 of a decision boundary are not judged)."""
+    K = synth.Intrinsics(40.0, 40.0, 15.5, 11.5, 32, 24)
+    spec = synth.VolumeSpec(48, 40, 32, 0.02, 0.08, (-0.47, -0.39, 0.61))
+    dpl = 0.9
+    vol = orc.Volume(spec)
+    assert vol.integrate_bricks(np.full((24, 32), dpl, np.float32), K, np.eye(3), np.zeros(3), edge=8) > 0
+    P = centres(spec)
+    z = P[..., 2]
+    u = 40.0 * P[..., 0] / z + 15.5
+    v = 40.0 * P[..., 1] / z + 11.5
+    eta = dpl - z
+    margin = 1e-6
+    sure_in = (u > -0.5 + margin) & (u < 31.5 - margin) & (v > -0.5 + margin) & (v < 23.5 - margin)
+    maybe_in = (u > -0.5 - margin) & (u < 31.5 + margin) & (v > -0.5 - margin) & (v < 23.5 + margin)
+    sure_band = (eta >= -0.08 + margin) & (eta < 0.08 - margin)
+    maybe_band = (eta >= -0.08 - margin) & (eta < 0.08 + margin)
+    nb = (spec.nz // 8, spec.ny // 8, spec.nx // 8)
+    red = lambda m: m.reshape(nb[0], 8, nb[1], 8, nb[2], 8).any(axis=(1, 3, 5))
+    must = red(sure_in & sure_band)
+    may = red(maybe_in & maybe_band)
+    got = vol.bricks.astype(bool)
+    assert must.sum() > 4 and np.all(got[must]) and not np.any(got[~may])
+    # in recorded bricks every viewed voxel in front of the plane is updated, beyond the band too
+    rec = np.repeat(np.repeat(np.repeat(got, 8, 0), 8, 1), 8, 2)
+    front = rec & sure_in & (eta >= 0.08 + margin)
+    assert front.sum() > 0 and np.all(vol.W[front] == 1) and np.all(vol.T[front] == 1.0)
+    assert np.all(vol.W[~rec] == 0) and np.all(vol.T[~rec] == 1.0)

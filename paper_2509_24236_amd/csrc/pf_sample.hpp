@@ -134,11 +134,13 @@ struct Gather<FMT, PF_LAYOUT_BRICKS> {
     const ST* ones;               // one block of +1
     const int* __restrict__ idx;  // brick-index grid
     int nbx, nbxy;
-    __device__ inline const ST* addr(int cx, int cy, int cz) const {
-        const int slot = idx[(cz >> 3) * nbxy + (cy >> 3) * nbx + (cx >> 3)];
+    __device__ inline int key(int cx, int cy, int cz) const { return (cz >> 3) * nbxy + (cy >> 3) * nbx + (cx >> 3); }
+    __device__ inline int slot(int k) const { return idx[k]; }
+    __device__ inline const ST* at(int s, int cx, int cy, int cz) const {
         const int local = (cx & 7) | ((cy & 7) << 3) | ((cz & 7) << 6);
-        return slot < 0 ? ones : C + ((((size_t)slot << 9) | (size_t)local) << 3);
+        return s < 0 ? ones : C + ((((size_t)s << 9) | (size_t)local) << 3);
     }
+    __device__ inline const ST* addr(int cx, int cy, int cz) const { return at(slot(key(cx, cy, cz)), cx, cy, cz); }
     __device__ inline void load(const ST* p, float (&c)[8]) const { load_cell8<FMT>(p, c); }
 };
 
@@ -172,6 +174,7 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     const ST* p[NP];
     float f[NP][3];
     bool inb[NP];
+    int cl[NP][3];
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const float gx = fmaf(g[j].r[0], x, fmaf(g[j].r[1], y, fmaf(g[j].r[2], z, g[j].t[0])));
@@ -186,7 +189,35 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
         f[j][0] = gx - fx0;
         f[j][1] = gy - fy0;
         f[j][2] = gz - fz0;
-        p[j] = G.addr(cx, cy, cz);
+        cl[j][0] = cx;
+        cl[j][1] = cy;
+        cl[j][2] = cz;
+        if constexpr (LAYOUT != PF_LAYOUT_BRICKS) p[j] = G.addr(cx, cy, cz);
+    }
+    if constexpr (LAYOUT == PF_LAYOUT_BRICKS) {
+        // The brick of a cell comes from the index grid: a pose whose cell lies in the same brick
+        // as the previous pose's takes that pose's slot instead of loading the entry again (the
+        // same selection through an empty asm statement as for the corners below).
+        int key[NP], slot[NP], kd[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) key[j] = G.key(cl[j][0], cl[j][1], cl[j][2]);
+        slot[0] = G.slot(key[0]);
+        kd[0] = 0;
+#pragma unroll
+        for (int j = 1; j < NP; ++j) {
+            kd[j] = key[j] == key[j - 1] ? 1 : 0;
+            slot[j] = -1;
+            if (!kd[j]) slot[j] = G.slot(key[j]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 1; j < NP; ++j) {
+            int d = kd[j];
+            asm volatile("" : "+v"(d));
+            slot[j] = d ? slot[j - 1] : slot[j];
+        }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) p[j] = G.at(slot[j], cl[j][0], cl[j][1], cl[j][2]);
     }
     // keep the phases apart: the scheduler would otherwise interleave them pose by pose and
     // leave only one pose's gathers in flight

@@ -343,6 +343,89 @@ def bench_combined(args):
 _RENDER = {}
 
 
+def bench_precision(args):
+    """Precision workload (form 1): the paper-scale room in a 1024^3 grid at 0.5 cm (tau 2 cm), 640x480
+    depth, 4096 particles x 20 iterations at rates 1/8, 1/16, 1/32, then fusion, in each storage format
+    (FP32 T + FP32 W, FP16 T + uint8 W, int16 T + uint8 W; sums FP32-exact, pose math FP64). Frame 0
+    is fused at the true pose, later frames start from the previous estimate composed with the stand-in.
+    Reports per format the tracked frames' throughput, and for the first tracked frame the pose and
+    final-fitness error against the FP64 oracle tracking from the same init with the same random
+    stream on its own FP64 fusion of frame 0, and the FP64 fitness of the tracked pose on that fusion.
+    Prints one JSON line."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2509_24236_amd as pf
+    import synth
+    dev = torch.device("cuda:0")
+    n_frames = args.warmup + args.steps + 1
+    log(f"[precision] rendering {n_frames} frames")
+    f = synth.cfg2_frames(n_frames)
+    intr, rel = f["intr"], f["rel"]
+    spec = synth.VolumeSpec.centred(1024, 0.005, 0.02, synth.room_centre_world(f["scene"]))
+    depth = [torch.as_tensor(f["depth"](t)).to(dev) for t in range(n_frames)]
+    K, I, rates = 4096, 20, (8, 16, 32)
+    params = pf.TrackParams(seed=15, frame_index=1, n_iters=I, K=K, rates=rates, pixel_stride=1, s1_deg=10.0,
+                            s1_m=0.10)
+    R1, t1 = f["gt"][0][0] @ rel[1][0], f["gt"][0][0] @ rel[1][1] + f["gt"][0][1]
+    log("[precision] FP64 oracle: fusion of frame 0 and tracking of frame 1")
+    ov = oracle.Volume(spec)
+    ov.integrate(f["depth"](0), intr, *f["gt"][0])
+    oprm = oracle.make_params(seed=15, frame_index=1, n_iters=I, K=K, rates=rates, pixel_stride=1, s1_deg=10.0,
+                              s1_m=0.10)
+    Ro, to, _ = ov.track_frame(f["depth"](1), intr, R1, t1, oprm)
+    X1, _ = oracle.backproject(f["depth"](1), intr, 1)
+    S8 = oracle.subsample(X1, min(rates))          # the densest view, on which E_final is reported
+    names = {pf.F32_W_F32: "f32", pf.F16_W_U8: "f16+u8", pf.I16_W_U8: "i16+u8"}
+    res = {}
+    for fmt in (pf.F32_W_F32, pf.F16_W_U8, pf.I16_W_U8):
+        vol = pf.Tsdf(spec, fmt=fmt, device=dev)
+        trk = pf.Tracker(intr, params, device=dev)
+        vol.integrate(depth[0], intr, *f["gt"][0])
+        est = [f["gt"][0]]
+        first = None
+        evals = 0
+        for t in range(1, n_frames):
+            if t == args.warmup + 1:
+                torch.cuda.synchronize()
+                t_start = time.perf_counter()
+            Rp, tp = est[-1]
+            R0, t0 = Rp @ rel[t][0], Rp @ rel[t][1] + tp
+            trk.set_frame(t)
+            R, tt, st = trk.track(vol, depth[t], R0, t0)
+            vol.integrate(depth[t], intr, R, tt)
+            est.append((R, tt))
+            if t == 1:
+                first = (R, tt, st)
+            if t > args.warmup:
+                evals += sum((K + 1) * st.n_sub[i] for i in range(st.n_iters))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t_start
+        R, tt, st = first
+        dr = math.degrees(oracle.rot_err(R, Ro))
+        E64, _ = ov.fitness(S8, R, tt)             # the FP64 fitness of the same pose on the FP64 fusion
+        res[names[fmt]] = {"ms_per_frame": 1e3 * el / args.steps, "evals_per_s": evals / el,
+                           "frame1_vs_oracle_deg": dr, "frame1_vs_oracle_mm": 1e3 * float(np.linalg.norm(tt - to)),
+                           "frame1_E_final": float(st.E_final), "frame1_E_fp64": float(E64),
+                           "frame1_E_rel_err": abs(float(st.E_final) - E64) / E64,
+                           "volume_bytes": vol.T.numel() * vol.T.element_size() + vol.W.numel() * vol.W.element_size()}
+        log(f"[precision] {names[fmt]}: {res[names[fmt]]}")
+        del vol, trk
+        torch.cuda.empty_cache()
+    del ov
+    base = res["f32"]["ms_per_frame"]
+    for v in res.values():
+        v["speedup_vs_f32"] = base / v["ms_per_frame"]
+    out = {"metric": "particle-point fitness evals/s + ms/frame (track+fuse) at 640x480, 4096 particles, by TSDF format",
+           "value": res["i16+u8"]["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res["i16+u8"]["ms_per_frame"], "higher_is_better": True,
+           "dtype": "i16", "data": "synthetic",
+           "config": {"workload": "paper-scale room, 1024^3 TSDF at 0.5 cm (tau 2 cm), 640x480, 4096 particles x 20 "
+                                  "iterations at rates 1/8, 1/16, 1/32, then fusion; value = the int16 form",
+                      "formats": res}}
+    print(json.dumps(out), flush=True)
+
+
 def _render_init(n_frames):
     import synth
     _RENDER["frames"] = synth.cfg2_frames(n_frames)
@@ -500,11 +583,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true", help="run only a plain 1 GiB device copy")
     ap.add_argument("--frames", type=int, default=200, help="accuracy: frames of the sequence")
-    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch", "regimes", "combined", "accuracy"],
+    ap.add_argument("--workload", default="sequence", choices=["sequence", "batch", "regimes", "combined", "accuracy", "precision"],
                     help="sequence: the paper-scale sequence (the headline); batch: 64 heterogeneous problems; "
                          "regimes: the scoring kernel alone at four particle spreads (diagnostic); combined: "
                          "batched + polish against plain at equal accuracy; accuracy: ATE and reconstruction "
-                         "quality of the whole sequence against the analytic ground truth")
+                         "quality of the whole sequence against the analytic ground truth; precision: the "
+                         "1024^3 grid in FP32, FP16 and int16 storage against each other and the FP64 oracle")
     ap.add_argument("--problems", type=int, default=64)
     ap.add_argument("--schedule", default="fixed", choices=["fixed", "paper"],
                     help="sequence: fixed = 3072 particles x 20 iterations (the headline configuration); paper = "
@@ -533,6 +617,9 @@ def main():
         return
     if args.workload == "accuracy":
         bench_accuracy(args)
+        return
+    if args.workload == "precision":
+        bench_precision(args)
         return
 
     import numpy as np

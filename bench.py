@@ -348,9 +348,10 @@ def bench_precision(args):
     depth, 4096 particles x 20 iterations at rates 1/8, 1/16, 1/32, then fusion, in each storage format
     (FP32 T + FP32 W, FP16 T + uint8 W, int16 T + uint8 W; sums FP32-exact, pose math FP64). Frame 0
     is fused at the true pose, later frames start from the previous estimate composed with the stand-in.
-    Reports per format the tracked frames' throughput, and for the first tracked frame the pose and
-    final-fitness error against the FP64 oracle tracking from the same init with the same random
-    stream on its own FP64 fusion of frame 0, and the FP64 fitness of the tracked pose on that fusion.
+    Reports per format the tracked frames' throughput, and for the first tracked frame: the pose
+    against the FP64 oracle tracking from the same init with the same random stream (a) on this
+    format's own volume, dequantized, and (b) on the oracle's own FP64 fusion of frame 0; and the
+    fitness of the tracked pose against its FP64 value on that fusion.
     Prints one JSON line."""
     import numpy as np
     import torch
@@ -382,6 +383,13 @@ def bench_precision(args):
         vol = pf.Tsdf(spec, fmt=fmt, device=dev)
         trk = pf.Tracker(intr, params, device=dev)
         vol.integrate(depth[0], intr, *f["gt"][0])
+        # the oracle on this format's own volume (dequantized), tracking frame 1 from the same init:
+        # isolates the kernels' arithmetic from the storage format's rounding
+        Tq, Wq = vol.export_linear()
+        oq = oracle.Volume(spec, T=Tq.cpu().numpy(), W=Wq.cpu().numpy())
+        del Tq, Wq
+        Rq, tq, _ = oq.track_frame(f["depth"](1), intr, R1, t1, oprm)
+        del oq
         est = [f["gt"][0]]
         first = None
         evals = 0
@@ -405,6 +413,8 @@ def bench_precision(args):
         dr = math.degrees(oracle.rot_err(R, Ro))
         E64, _ = ov.fitness(S8, R, tt)             # the FP64 fitness of the same pose on the FP64 fusion
         res[names[fmt]] = {"ms_per_frame": 1e3 * el / args.steps, "evals_per_s": evals / el,
+                           "frame1_vs_oracle_same_volume_deg": math.degrees(oracle.rot_err(R, Rq)),
+                           "frame1_vs_oracle_same_volume_mm": 1e3 * float(np.linalg.norm(tt - tq)),
                            "frame1_vs_oracle_deg": dr, "frame1_vs_oracle_mm": 1e3 * float(np.linalg.norm(tt - to)),
                            "frame1_E_final": float(st.E_final), "frame1_E_fp64": float(E64),
                            "frame1_E_rel_err": abs(float(st.E_final) - E64) / E64,

@@ -256,3 +256,46 @@ def test_bricks_batch_equals_cells(pf, dev, cfg1):
         b.close()
     for (R1, t1, s1), (R2, t2, s2) in zip(*out):
         assert np.array_equal(R1, R2) and np.array_equal(t1, t2) and s1.E_final == s2.E_final
+
+
+# ----------------------------------------------------------------------------- full size
+def test_fullsize_bricks_whole_room(pf, orc, dev):
+    """The paper-scale sequence's room as one bricked grid at 1 cm (608 x 312 x 512 voxels, the
+    walls the dense 512^3 cube leaves out included): three fusions at the true poses against the
+    oracle's bricked fusion over the whole grid, then scoring 3073 poses on a full 640x480 frame
+    bitwise equal to the dense replica loaded with the same values."""
+    f = synth.cfg2_frames(3)
+    spec = synth.room_spec(f["scene"], 0.01, 0.04)
+    say(f"[bricks] whole room {spec.nx}x{spec.ny}x{spec.nz}, three fusions")
+    intr = f["intr"]
+    ov = orc.Volume(spec)
+    gv = pf.Tsdf(spec, device=dev, layout=pf.LAYOUT_BRICKS, max_bricks=120000)
+    for t in range(3):
+        depth = f["depth"](t)
+        ov.integrate_bricks(depth, intr, *f["gt"][t], edge=E)
+        gv.integrate(torch.as_tensor(depth).to(dev), intr, *f["gt"][t])
+    n, overflow = gv.bricks_used()
+    assert overflow == 0 and n == int(ov.bricks.sum())
+    T, W = gv.export_linear()
+    W = W.cpu().numpy()
+    assert np.array_equal(W, ov.W.astype(np.float32))
+    T = T.cpu().numpy()
+    upd = ov.W > 0
+    assert np.abs(T.astype(np.float64) - ov.T)[upd].max() <= T_TOL[0]
+    assert np.all(T[~upd] == 1.0)
+    say(f"    {n} bricks of {ov.bricks.size}, {int(upd.sum())} voxels observed")
+    del ov
+    gc = pf.Tsdf(spec, device=dev, layout=pf.LAYOUT_CELLS, init=False)
+    gc.import_linear(torch.as_tensor(T).to(dev), torch.as_tensor(W).to(dev))
+    del T, W
+    px, py, pz, nd = pf.backproject(torch.as_tensor(f["depth"](2)).to(dev), intr, 1)
+    npts = int(nd[0].item())
+    rng = np.random.default_rng(9)
+    R0, t0 = f["gt"][2]
+    poses = [(R0, t0)] + [orc.compose(rng.uniform(-1, 1, 3) * math.radians(5), rng.uniform(-1, 1, 3) * 0.05, R0, t0)
+                          for _ in range(3072)]
+    P = torch.as_tensor(pf.poses_to_f32(poses)).to(dev)
+    a = pf.particles_score(gv, px, py, pz, P, n_pts=npts)
+    b = pf.particles_score(gc, px, py, pz, P, n_pts=npts)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert int(a[1][0].item()) > npts // 2

@@ -68,7 +68,30 @@ def cpu_baseline(frames, vol_spec, intr, n_frames, seconds, schedule="fixed"):
         log(f"[bench] oracle frame {t}: {track_s:.1f} s so far")
         if time.perf_counter() - t0 >= seconds:
             break
-    return {"value": evals / track_s, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+    # one core: the oracle's fitness of 256 poses around the last estimate on the 1/8 view
+    cores = oracle.num_threads()
+    X, _ = oracle.backproject(frames["depth"](1), intr, 1)
+    S8 = oracle.subsample(X, 8)
+    rng = np.random.default_rng(1)
+    Rp, tp = est[-1]
+    poses = [oracle.compose(rng.uniform(-1, 1, 3) * math.radians(10.0), rng.uniform(-1, 1, 3) * 0.1, Rp, tp)
+             for _ in range(256)]
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    ov.fitness_many(S8, poses)
+    one = 256 * S8.shape[0] / (time.perf_counter() - t1)
+    oracle.set_num_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": evals / track_s, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "host_logical_cpus": os.cpu_count(),
+            "one_core": {"value": one, "unit": "evals/s",
+                         "sample": f"FP64 fitness of 256 poses (10 deg / 10 cm box) on the 1/8 view of frame 1, "
+                                   f"{S8.shape[0]} points, one thread"},
             "ms_per_frame": 1e3 * track_s / done,
             "sample": f"FP64 oracle, same sequence and schedule: fusion of frame 0, then track + fuse of frames "
                       f"1..{done} on a 512^3 volume ({track_s:.1f} s timed)"}

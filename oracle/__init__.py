@@ -97,6 +97,8 @@ def lib():
         L.orc_counter.restype = C.c_uint64
         L.orc_counter.argtypes = [C.c_int64] * 4
         L.orc_uniform_pm1.restype = C.c_double
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [C.c_int32]
         L.orc_uniform_pm1.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int64, C.c_int64]
         L.orc_so3_exp.argtypes = [dp, dp]
         L.orc_so3_log.argtypes = [dp, dp]
@@ -143,6 +145,11 @@ def _dp(a: np.ndarray):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's later parallel loops (used to time it on one core)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def num_threads() -> int:

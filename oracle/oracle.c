@@ -45,6 +45,15 @@ int32_t orc_num_threads(void) {
 #endif
 }
 
+/* Sets the threads of later OpenMP loops (for timing on one core); no effect without OpenMP. */
+void orc_set_num_threads(int32_t n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /* ----------------------------------------------------------------------------------------
  * Counter-based random numbers (reading: the paper does not name a generator).
  * SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the n-th output (n = 0, 1, ...) of the

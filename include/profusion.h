@@ -61,8 +61,9 @@ extern "C" {
  *         at the offsets tsdf_brick_offsets() returns: a 256-byte header (int32 bricks in use,
  *         int32 overflow flag, int32 bricks in use before the last fusion; at byte 64 a cell of
  *         +1 corners), the index grid (entry (bz * ny/8 + by) * nx/8 + bx for the brick of voxels
- *         8bx..8bx+7, ...), the brick coordinates of every slot (int32 x4), the
- *         slots' T (512 values each, x-fastest inside the brick) and their cells (512 per brick,
+ *         8bx..8bx+7, ...), a candidate list of the same size (scratch of tsdf_integrate), the
+ *         brick coordinates of every slot (int32 x4), the slots' T (512 values each, x-fastest
+ *         inside the brick) and their cells (512 per brick,
  *         cell (x, y, z) local to the brick at x + 8y + 64z, its 8 corners in the CELLS order;
  *         corners in the next brick along +x/+y/+z read that brick, or +1 where it has no slot).
  *         The W buffer holds the slots' W. A voxel outside every allocated brick reads T = +1,

@@ -58,7 +58,8 @@ BrickLayout brick_layout(const pf_tsdf* v) {
     L.nbz = v->nz / kBrickEdge;
     const size_t nb = (size_t)L.nbx * L.nby * L.nbz, slots = (size_t)v->max_bricks, tb = t_elem_bytes(v->format);
     L.index = 256;
-    L.coords = L.index + al256(nb * sizeof(int));
+    L.cand = L.index + al256(nb * sizeof(int));
+    L.coords = L.cand + al256(nb * sizeof(int));
     L.pool_t = L.coords + al256(slots * 4 * sizeof(int));
     L.pool_cells = L.pool_t + al256(slots * kBrickVox * tb);
     L.t_total = L.pool_cells + slots * kBrickVox * 8 * tb;

@@ -103,7 +103,7 @@ VolView make_view(const pf_tsdf* v);
 constexpr int kBrickEdge = 8, kBrickVox = 512;
 struct BrickLayout {
     int nbx, nby, nbz;
-    size_t index, coords, pool_t, pool_cells, t_total, w_total;
+    size_t index, cand, coords, pool_t, pool_cells, t_total, w_total;
 };
 BrickLayout brick_layout(const pf_tsdf* v);
 
@@ -112,7 +112,7 @@ struct BrickHeader {
     int n;          // slots in use
     int overflow;   // 1 once an allocation found the pool full
     int n_prev;     // slots in use before the current fusion
-    int pad;
+    int ncand;      // bricks listed as candidates by the current fusion
 };
 constexpr size_t kBrickOnes = 64;
 

@@ -296,7 +296,8 @@ __global__ __launch_bounds__(kBlock) void k_build_cells(const void* Tv, void* Cv
 // slots, and then updates every allocated brick exactly as the dense layouts update a voxel.
 struct BrickArgs {
     BrickHeader* hdr;
-    int* index;     // brick-index grid: slot or -1
+    int* index;     // brick-index grid: slot or -1 (kCandidate while a fusion lists candidates)
+    int* cand;      // candidate list, one entry per brick at most
     int4* coords;   // slot -> brick coordinates
     void* T;        // slots' T, 512 each
     void* C;        // slots' cells, 512 x 8 each
@@ -310,6 +311,7 @@ BrickArgs brick_args(const pf_tsdf* v) {
     BrickArgs b;
     b.hdr = reinterpret_cast<BrickHeader*>(base);
     b.index = reinterpret_cast<int*>(base + L.index);
+    b.cand = reinterpret_cast<int*>(base + L.cand);
     b.coords = reinterpret_cast<int4*>(base + L.coords);
     b.T = base + L.pool_t;
     b.C = base + L.pool_cells;
@@ -345,29 +347,84 @@ __global__ void k_bricks_prep(BrickArgs b) {
     const int n = min(b.hdr->n, b.max_bricks);
     b.hdr->n = n;
     b.hdr->n_prev = n;
+    b.hdr->ncand = 0;
 }
 
-// Gives a slot to a brick that has none and holds a voxel this frame puts in the band
-// (-tau <= eta < tau: updated with phi < 1). Only the brick's own workgroup touches its entry.
-__global__ __launch_bounds__(kBlock) void k_bricks_mark(FuseArgs a, BrickArgs b) {
-    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-    const int64_t e_idx = ((int64_t)bz * b.nby + by) * b.nbx + bx;
-    if (b.index[e_idx] >= 0) return;
-    const int i0 = bx * kBrickEdge, j0 = by * kBrickEdge, k0 = bz * kBrickEdge;
-    if (brick_outside(a, i0, j0, k0, i0 + 7, j0 + 7, k0 + 7)) return;
-    int band = 0;
-    for (int e = threadIdx.x; e < kBrickVox; e += kBlock) {
-        double phi;
-        if (fuse_decide(a, i0 + (e & 7), j0 + ((e >> 3) & 7), k0 + (e >> 6), phi) && phi < 1.0) band = 1;
+// Candidates for new slots, found from the depth image. A voxel the frame puts in the band has a
+// nearest pixel (u, v) with valid depth D and a camera depth qz in (D - tau, D + tau], so its
+// centre lies in the frustum segment of that pixel's footprint [u - 1/2, u + 1/2] x
+// [v - 1/2, v + 1/2] between those depths. The grid coordinates are an affine function of the
+// camera coordinates, so the segment's 8 corners bound the voxel's index; one thread per pixel
+// lists every brick without a slot that this box (widened by kCandMargin voxels against rounding)
+// touches, each brick once (its entry is claimed from -1 to kCandidate). The exact per-voxel test
+// then runs on the listed bricks only.
+constexpr int kCandidate = -2;
+constexpr double kCandMargin = 0.01;   // voxels
+
+__global__ __launch_bounds__(kBlock) void k_bricks_candidates(FuseArgs a, BrickArgs b) {
+    const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= (int64_t)a.width * a.height) return;
+    const int u = (int)(pix % a.width), v = (int)(pix / a.width);
+    const double D = (double)a.depth[pix];
+    if (!(isfinite(D) && D > 0.0)) return;
+    const double z0 = fmax(D - a.tau, 0.0), z1 = D + a.tau;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    const double org[3] = {a.ox, a.oy, a.oz};
+    for (int c = 0; c < 8; ++c) {
+        const double z = (c & 4) ? z1 : z0;
+        const double x = ((double)u + ((c & 1) ? 0.5 : -0.5) - a.cx) / a.fx * z;
+        const double y = ((double)v + ((c & 2) ? 0.5 : -0.5) - a.cy) / a.fy * z;
+        for (int r = 0; r < 3; ++r) {
+            const double p = a.t[r] + a.R[3 * r] * x + a.R[3 * r + 1] * y + a.R[3 * r + 2] * z;
+            const double g = (p - org[r]) / a.vs;
+            lo[r] = fmin(lo[r], g);
+            hi[r] = fmax(hi[r], g);
+        }
     }
-    if (!__syncthreads_or(band)) return;
-    if (threadIdx.x == 0) {
-        const int slot = atomicAdd(&b.hdr->n, 1);
-        if (slot < b.max_bricks) {
-            b.coords[slot] = make_int4(bx, by, bz, 0);
-            b.index[e_idx] = slot;
-        } else {
-            atomicOr(&b.hdr->overflow, 1);
+    const int nv[3] = {a.d.nx, a.d.ny, a.d.nz};
+    int b0[3], b1[3];
+    for (int r = 0; r < 3; ++r) {
+        const double l = ceil(lo[r] - kCandMargin), h = floor(hi[r] + kCandMargin);
+        if (h < 0.0 || l > (double)(nv[r] - 1)) return;   // the segment misses the grid
+        b0[r] = (int)fmax(l, 0.0) >> 3;
+        b1[r] = (int)fmin(h, (double)(nv[r] - 1)) >> 3;
+    }
+    for (int bz = b0[2]; bz <= b1[2]; ++bz)
+        for (int by = b0[1]; by <= b1[1]; ++by)
+            for (int bx = b0[0]; bx <= b1[0]; ++bx) {
+                const int64_t e = ((int64_t)bz * b.nby + by) * b.nbx + bx;
+                if (b.index[e] == -1 && atomicCAS(&b.index[e], -1, kCandidate) == -1)
+                    b.cand[atomicAdd(&b.hdr->ncand, 1)] = (int)e;
+            }
+}
+
+// Gives a slot to every listed candidate that holds a voxel this frame puts in the band
+// (-tau <= eta < tau: updated with phi < 1), and returns the others to -1. Persistent over the list;
+// only the workgroup of a candidate touches its entry.
+__global__ __launch_bounds__(kBlock) void k_bricks_mark(FuseArgs a, BrickArgs b) {
+    const int nc = b.hdr->ncand;
+    for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+        const int e_idx = b.cand[c];
+        const int bx = e_idx % b.nbx, by = (e_idx / b.nbx) % b.nby, bz = e_idx / (b.nbx * b.nby);
+        const int i0 = bx * kBrickEdge, j0 = by * kBrickEdge, k0 = bz * kBrickEdge;
+        int band = 0;
+        for (int e = threadIdx.x; e < kBrickVox; e += kBlock) {
+            double phi;
+            if (fuse_decide(a, i0 + (e & 7), j0 + ((e >> 3) & 7), k0 + (e >> 6), phi) && phi < 1.0) band = 1;
+        }
+        band = __syncthreads_or(band);
+        if (threadIdx.x == 0) {
+            int entry = -1;
+            if (band) {
+                const int slot = atomicAdd(&b.hdr->n, 1);
+                if (slot < b.max_bricks) {
+                    b.coords[slot] = make_int4(bx, by, bz, 0);
+                    entry = slot;
+                } else {
+                    atomicOr(&b.hdr->overflow, 1);
+                }
+            }
+            b.index[e_idx] = entry;
         }
     }
 }
@@ -560,8 +617,9 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
         a.W = b.W;
         a.C = nullptr;
         hipLaunchKernelGGL(k_bricks_prep, dim3(1), dim3(1), 0, s, b);
-        hipLaunchKernelGGL(k_bricks_mark, dim3((unsigned)b.nbx, (unsigned)b.nby, (unsigned)b.nbz), dim3(kBlock), 0, s,
-                           a, b);
+        const int64_t npix = (int64_t)a.width * a.height;
+        hipLaunchKernelGGL(k_bricks_candidates, dim3((unsigned)((npix + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a, b);
+        hipLaunchKernelGGL(k_bricks_mark, dim3(kBrickGrid), dim3(kBlock), 0, s, a, b);
         hipLaunchKernelGGL((k_bricks_cells<FMT, true>), dim3(kBrickGrid), dim3(kBlock), 0, s, b, a.d, 1);
         hipLaunchKernelGGL(k_bricks_integrate<FMT>, dim3(kBrickGrid), dim3(kBlock), 0, s, a, b);
         return check_launch("tsdf_integrate (bricks)");

@@ -256,7 +256,7 @@ def test_brick_pool_bytes_and_offsets(pf):
         assert L.tsdf_brick_offsets(C.byref(d), *[C.byref(x) for x in o]) == pf.PF_OK
         index, coords, pool_t, pool_cells = (x.value for x in o)
         assert index == 256
-        assert coords == index + _al(nb * 4)
+        assert coords == index + 2 * _al(nb * 4)          # the index grid, then the candidate list
         assert pool_t == coords + _al(37 * 16)
         assert pool_cells == pool_t + _al(37 * 512 * tb)
         assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == pool_cells + 37 * 512 * 8 * tb

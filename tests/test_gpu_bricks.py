@@ -299,3 +299,80 @@ def test_fullsize_bricks_whole_room(pf, orc, dev):
     b = pf.particles_score(gc, px, py, pz, P, n_pts=npts)
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
     assert int(a[1][0].item()) > npts // 2
+
+
+def test_bricks_grid_beyond_dense_limit(pf, dev):
+    """A 2048 x 1024 x 2048 grid at 0.5 cm (4.3e9 voxels: more than the dense layouts address)
+    around the paper-scale room, against a bricked grid that covers only the room plus two bricks
+    of margin on the same lattice: after two fusions both hold the same bricks with identical
+    weights and T within FP32 rounding (the voxel centres, origin + vs i, round differently in FP64
+    from the two origins), and score 512 poses alike (sample positions round differently in FP32)."""
+    f = synth.cfg2_frames(2)
+    intr, sc = f["intr"], f["scene"]
+    vs, tau = 0.005, 0.02
+    c = synth.room_centre_world(sc)
+    big = synth.VolumeSpec(2048, 1024, 2048, vs, tau, tuple(float(c[a]) - 0.5 * n * vs + 0.5 * vs
+                                                              for a, n in enumerate((2048, 1024, 2048))))
+    lo_w = sc["R_wr"] @ sc["room_lo"] + sc["t_wr"] - 2 * E * vs
+    hi_w = sc["R_wr"] @ sc["room_hi"] + sc["t_wr"] + 2 * E * vs
+    o = np.array(big.origin)
+    start = (np.floor((lo_w - o) / vs / E) * E).astype(int)
+    end = (np.ceil((hi_w - o) / vs / E) * E).astype(int)
+    n = end - start
+    small = synth.VolumeSpec(int(n[0]), int(n[1]), int(n[2]), vs, tau, tuple(float(x) for x in o + start * vs))
+    say(f"[bricks] {big.nx}x{big.ny}x{big.nz} grid vs {small.nx}x{small.ny}x{small.nz} at offset {start.tolist()}")
+    gb = pf.Tsdf(big, device=dev, layout=pf.LAYOUT_BRICKS, max_bricks=300000)
+    gs = pf.Tsdf(small, device=dev, layout=pf.LAYOUT_BRICKS, max_bricks=300000)
+    with pytest.raises(pf.PFError):
+        gb.export_linear()
+    # Frame 0 sits at the identity and this lattice is axis-aligned with it, so many voxel centres
+    # project exactly onto pixel borders; the two grids compute those centres from different
+    # origins (origin + vs i rounds differently in FP64) and would break such ties differently.
+    # A small generic rotation and shift of both fusion poses removes the exact ties.
+    Rp, tp = synth.rot(np.array([0.0031, -0.0047, 0.0023])), np.array([0.00123, -0.00077, 0.00051])
+    ms = {}
+    for t in range(2):
+        d = torch.as_tensor(f["depth"](t)).to(dev)
+        Rt, tt = f["gt"][t]
+        for name, vol in (("big", gb), ("small", gs)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            vol.integrate(d, intr, Rp @ Rt, Rp @ tt + tp)
+            e1.record()
+            torch.cuda.synchronize()
+            ms[name] = e0.elapsed_time(e1)
+    say(f"    second fusion: {ms['big']:.2f} ms on the big grid, {ms['small']:.2f} ms on the room grid")
+    ib, cb, Tb, Cb, nb_, ob = raw_pool(pf, gb)
+    is_, cs, Ts, Cs, ns_, os_ = raw_pool(pf, gs)
+    assert ob == 0 and os_ == 0 and nb_ == ns_ > 1000
+    say(f"    {ns_} bricks in both")
+    Wb = gb.W[:512 * nb_].cpu().numpy().reshape(nb_, 512)
+    Ws = gs.W[:512 * ns_].cpu().numpy().reshape(ns_, 512)
+    off = start // E
+    qb = ib[cs[:, 2] + off[2], cs[:, 1] + off[1], cs[:, 0] + off[0]]      # big slot of every small slot
+    assert np.all(qb >= 0) and np.unique(qb).size == ns_
+    assert np.array_equal(Ws, Wb[qb])
+    assert np.abs(Ts - Tb[qb]).max() <= 2e-6
+    # cells of the room grid's last voxel row along an axis have corners outside it; they are never
+    # read (sample cells are clamped one voxel inside) and are left out
+    lz, ly, lx = np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij")
+    gi = cs[:, :1] * 8 + lx.reshape(1, -1)
+    gj = cs[:, 1:2] * 8 + ly.reshape(1, -1)
+    gk = cs[:, 2:3] * 8 + lz.reshape(1, -1)
+    inner = (gi < small.nx - 1) & (gj < small.ny - 1) & (gk < small.nz - 1)
+    assert np.abs(Cs - Cb[qb])[inner].max() <= 2e-6
+    # scoring reads the same cells through either index grid
+    px, py, pz, nd = pf.backproject(torch.as_tensor(f["depth"](1)).to(dev), intr, 1)
+    npts = int(nd[0].item())
+    rng = np.random.default_rng(4)
+    R0, t0 = Rp @ f["gt"][1][0], Rp @ f["gt"][1][1] + tp      # the pose frame 1 was fused at
+    poses = [(R0, t0)] + [(synth.rot(rng.uniform(-1, 1, 3) * math.radians(2.0)) @ R0, t0 + rng.uniform(-1, 1, 3) * 0.02)
+                          for _ in range(511)]
+    P = torch.as_tensor(pf.poses_to_f32(poses)).to(dev)
+    a = pf.particles_score(gb, px, py, pz, P, n_pts=npts)
+    b = pf.particles_score(gs, px, py, pz, P, n_pts=npts)
+    Ea, Eb = a[0].cpu().numpy().astype(np.float64), b[0].cpu().numpy().astype(np.float64)
+    na, nb2 = a[1].cpu().numpy(), b[1].cpu().numpy()
+    assert int(na[0]) > npts // 2
+    assert np.all(np.abs(na - nb2) <= 1 + na // 2000)
+    assert np.all(np.abs(Ea - Eb) <= 1e-4 * Eb)

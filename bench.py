@@ -514,6 +514,9 @@ def bench_accuracy(args):
     dev = torch.device("cuda:0")
     f = synth.cfg2_frames(n)
     intr, spec, gt, rel, scene = f["intr"], f["vol"], f["gt"], f["rel"], f["scene"]
+    bricks = args.volume == "bricks"
+    if bricks:   # the whole room, walls included, as a sparse volume at the same voxel size
+        spec = synth.room_spec(scene, spec.voxel_size, spec.trunc)
     # the configured stand-in (3 deg / 3 cm per frame) and one at about the regression network's own
     # accuracy (Table VIII: median 0.26 cm), same scene, depth and seeds
     rel_fine = synth.cfg2_frames(n, pr_sigma_deg=0.3, pr_sigma_m=0.003)["rel"]
@@ -557,10 +560,13 @@ def bench_accuracy(args):
                 "completeness_10cm": float(np.mean(np.isfinite(dist)))}
 
     out = {"metric": "ATE-RMSE (cm) and reconstruction accuracy / completeness on the synthetic sequence",
-           "frames": n, "gt_surface_samples": int(gt_pts.shape[0]), "runs": {}}
+           "frames": n, "gt_surface_samples": int(gt_pts.shape[0]), "runs": {},
+           "volume": (f"bricks over the whole room, {spec.nx}x{spec.ny}x{spec.nz} at {spec.voxel_size * 100:g} cm"
+                      if bricks else f"dense {spec.nx}x{spec.ny}x{spec.nz} at {spec.voxel_size * 100:g} cm")}
     for name in ("fixed", "paper", "gt_poses", "standin_only", "fixed_pr0.3", "paper_pr0.3", "standin_only_pr0.3"):
         rel_run = rel_fine if name.endswith("_pr0.3") else rel
-        vol = pf.Tsdf(spec, device=dev)
+        vol = (pf.Tsdf(spec, device=dev, layout=pf.LAYOUT_BRICKS, max_bricks=args.max_bricks) if bricks
+               else pf.Tsdf(spec, device=dev))
         vol.integrate(dev_depth[0], intr, np.eye(3), np.zeros(3))
         est = [(np.eye(3), np.zeros(3))]
         trk = None
@@ -592,6 +598,8 @@ def bench_accuracy(args):
         wall = time.perf_counter() - t0
         row = traj_metrics(est)
         row.update(recon_metrics(vol))
+        if bricks:
+            row["bricks_used"], row["brick_overflow"] = vol.bricks_used()
         row["ms_per_frame"] = 1e3 * wall / (n - 1)
         if iters:
             row["mean_iterations"] = float(np.mean(iters))
@@ -628,8 +636,8 @@ def main():
                          "the alternating particle counts and early exit of Sec. IV-A")
     ap.add_argument("--tune", action="store_true", help="batch: run the autotuner first and record the plan")
     ap.add_argument("--volume", default="dense", choices=["dense", "bricks"],
-                    help="sequence: dense = the 512^3 cell-replica grid centred on the room (the headline); "
-                         "bricks = a sparse brick pool over the whole room at the same 1 cm voxels")
+                    help="sequence, accuracy: dense = the 512^3 cell-replica grid centred on the room (the "
+                         "headline); bricks = a sparse brick pool over the whole room at the same 1 cm voxels")
     ap.add_argument("--max-bricks", type=int, default=120000, help="bricks: pool slots")
     args = ap.parse_args()
     if args.gpus != 1:

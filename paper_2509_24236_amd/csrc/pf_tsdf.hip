@@ -290,10 +290,10 @@ __global__ __launch_bounds__(kBlock) void k_build_cells(const void* Tv, void* Cv
 }
 
 // ---------------------------------------------------------------- sparse bricks (PF_LAYOUT_BRICKS)
-// Bricks of 8x8x8 voxels in a pool behind a dense brick-index grid. A fusion first marks the bricks
-// the frame puts a band voxel into (one workgroup per brick of the grid, culled like the dense
-// path, then the same FP64 decision per voxel) and gives each a pool slot, initialises the new
-// slots, and then updates every allocated brick exactly as the dense layouts update a voxel.
+// Bricks of 8x8x8 voxels in a pool behind a dense brick-index grid. A fusion first lists candidate
+// bricks from the depth image, gives a pool slot to every candidate the frame puts a band voxel into
+// (the same FP64 decision per voxel as the update), initialises the new slots, and then updates
+// every allocated brick exactly as the dense layouts update a voxel.
 struct BrickArgs {
     BrickHeader* hdr;
     int* index;     // brick-index grid: slot or -1 (kCandidate while a fusion lists candidates)
@@ -341,8 +341,8 @@ __global__ __launch_bounds__(kBlock) void k_bricks_reset(BrickArgs b, int64_t n_
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n_index; i += stride) b.index[i] = -1;
 }
 
-// Start of a fusion: the count comes back to the pool size after an overflow, and the slots
-// in use so far are recorded.
+// Start of a fusion: the count comes back to the pool size after an overflow, the slots in use so
+// far are recorded, and the candidate list is emptied.
 __global__ void k_bricks_prep(BrickArgs b) {
     const int n = min(b.hdr->n, b.max_bricks);
     b.hdr->n = n;

@@ -503,7 +503,9 @@ def bench_accuracy(args):
     frame, with a reconstructed point within 10 cm). Runs the fixed schedule, the paper's schedule,
     fusion at the true poses (tracking-free reference) and the stand-in chained without any
     optimization, each with the configured stand-in (3 deg / 3 cm per frame) and, suffix _pr0.3, with
-    one at about the regression network's reported accuracy (0.3 deg / 0.3 cm). Prints one JSON line."""
+    one at about the regression network's reported accuracy (0.3 deg / 0.3 cm), and the fixed
+    schedule with no stand-in at all (each frame starts from the previous estimate). Prints one JSON
+    line."""
     import multiprocessing as mp
     import numpy as np
     import torch
@@ -563,14 +565,18 @@ def bench_accuracy(args):
            "frames": n, "gt_surface_samples": int(gt_pts.shape[0]), "runs": {},
            "volume": (f"bricks over the whole room, {spec.nx}x{spec.ny}x{spec.nz} at {spec.voxel_size * 100:g} cm"
                       if bricks else f"dense {spec.nx}x{spec.ny}x{spec.nz} at {spec.voxel_size * 100:g} cm")}
-    for name in ("fixed", "paper", "gt_poses", "standin_only", "fixed_pr0.3", "paper_pr0.3", "standin_only_pr0.3"):
-        rel_run = rel_fine if name.endswith("_pr0.3") else rel
+    identity = [None] + [(np.eye(3), np.zeros(3))] * (n - 1)
+    for name in ("fixed", "paper", "gt_poses", "standin_only", "fixed_pr0.3", "paper_pr0.3", "standin_only_pr0.3",
+                 "ro_only"):
+        # ro_only: no pose regression at all, each frame starts from the previous estimate (the
+        # analogue of running the optimization alone)
+        rel_run = rel_fine if name.endswith("_pr0.3") else (identity if name == "ro_only" else rel)
         vol = (pf.Tsdf(spec, device=dev, layout=pf.LAYOUT_BRICKS, max_bricks=args.max_bricks) if bricks
                else pf.Tsdf(spec, device=dev))
         vol.integrate(dev_depth[0], intr, np.eye(3), np.zeros(3))
         est = [(np.eye(3), np.zeros(3))]
         trk = None
-        if name.startswith("fixed"):
+        if name.startswith("fixed") or name == "ro_only":
             trk = pf.Tracker(intr, pf.TrackParams(seed=14, n_iters=20, K=3072, rates=(8, 16, 32), pixel_stride=1,
                                                   s1_deg=10.0, s1_m=0.10), device=dev)
         elif name.startswith("paper"):

@@ -778,8 +778,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "particles_score per iteration: k_score_regime<f32, cells> launched as 2x64, 4x128 and "
-                      "4x256 (poses x threads), one of which runs for the spread of the particles",
+            "kernel": "particles_score per iteration: k_score<f32, cells> in the shape of the particles' spread "
+                      "regime (2x64, 4x128 or 4x256 poses x threads), forecast from the previous frame",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -164,7 +164,10 @@ int32_t launch_tsdf_import(const pf_tsdf* v, const float* T, const float* W, hip
 // Scores poses [K][12] (camera -> world float32) into fitness / n_valid. With an optimizer state,
 // the launch shape follows the spread of the search size that drew the poses.
 int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
-                     hipStream_t s, const pf_track_state* st = nullptr);
+                     hipStream_t s, const pf_track_state* st = nullptr, int expect = -1);
+// Spread regime (0 wide, 1 mid, 2 tight) of particles drawn with search size (s_rad, s_m): the
+// host-side twin of the test the scoring launches make on the device.
+int spread_regime_of(double s_rad, double s_m, float inv_vs);
 
 // Largest number of per-workgroup partial sums the single-pose passes use.
 constexpr int kMaxPartials = 256;

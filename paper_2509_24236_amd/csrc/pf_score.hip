@@ -76,11 +76,13 @@ int auto_shape(int regime, int K) {
     return 5;
 }
 
-// The configured shape (pf_score_config); in automatic mode with an optimizer state, one launch
-// per spread regime, each reading the search size on the device (all but one return at once).
+// The configured shape (pf_score_config); in automatic mode with an optimizer state, either the
+// one shape of the expected regime (`expect` >= 0, the caller's forecast; the launch then runs
+// whatever the spread, so a wrong forecast costs speed only), or one launch per spread regime, each
+// reading the search size on the device (all but one return at once).
 template <int FMT, int LAYOUT>
 int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
-                  const pf_track_state* st, hipStream_t s) {
+                  const pf_track_state* st, hipStream_t s, int expect) {
     // few poses: spread the points over a wide workgroup
     if (K <= 64) return launch_t<FMT, LAYOUT, 1, 1024>(vv, p, poses, K, fitness, n_valid, st, -1, s);
 #define PF_SHAPE(TK, B)                 \
@@ -94,13 +96,15 @@ int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K,
     if (g_tk == 0 && st) {
         int32_t rc = PF_OK;
         for (int regime = 0; regime < 3 && !rc; ++regime) {
+            if (expect >= 0 && regime != expect) continue;
+            const int gate = expect >= 0 ? -1 : regime;
             switch (auto_shape(regime, K)) {
-                case 0: rc = launch_t<FMT, LAYOUT, 2, 64>(vv, p, poses, K, fitness, n_valid, st, regime, s); break;
-                case 1: rc = launch_t<FMT, LAYOUT, 4, 128>(vv, p, poses, K, fitness, n_valid, st, regime, s); break;
-                case 2: rc = launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, regime, s); break;
-                case 3: rc = launch_t<FMT, LAYOUT, 2, 256>(vv, p, poses, K, fitness, n_valid, st, regime, s); break;
-                case 4: rc = launch_t<FMT, LAYOUT, 1, 256>(vv, p, poses, K, fitness, n_valid, st, regime, s); break;
-                default: rc = launch_t<FMT, LAYOUT, 1, 1024>(vv, p, poses, K, fitness, n_valid, st, regime, s); break;
+                case 0: rc = launch_t<FMT, LAYOUT, 2, 64>(vv, p, poses, K, fitness, n_valid, st, gate, s); break;
+                case 1: rc = launch_t<FMT, LAYOUT, 4, 128>(vv, p, poses, K, fitness, n_valid, st, gate, s); break;
+                case 2: rc = launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, gate, s); break;
+                case 3: rc = launch_t<FMT, LAYOUT, 2, 256>(vv, p, poses, K, fitness, n_valid, st, gate, s); break;
+                case 4: rc = launch_t<FMT, LAYOUT, 1, 256>(vv, p, poses, K, fitness, n_valid, st, gate, s); break;
+                default: rc = launch_t<FMT, LAYOUT, 1, 1024>(vv, p, poses, K, fitness, n_valid, st, gate, s); break;
             }
         }
         return rc;
@@ -125,10 +129,16 @@ int32_t score_config(int tk, int block) {
 }
 
 int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
-                     hipStream_t s, const pf_track_state* st) {
+                     hipStream_t s, const pf_track_state* st, int expect) {
     return with_volume(vv.format, vv.layout, [&](auto fmt, auto layout) {
-        return launch_fl<decltype(fmt)::value, decltype(layout)::value>(vv, p, poses, K, fitness, n_valid, st, s);
+        return launch_fl<decltype(fmt)::value, decltype(layout)::value>(vv, p, poses, K, fitness, n_valid, st, s,
+                                                                          expect);
     });
+}
+
+int spread_regime_of(double s_rad, double s_m, float inv_vs) {
+    const double d = (s_rad * kSpreadLever + s_m) * (double)inv_vs;
+    return d > kSpreadWide ? 0 : (d > kSpreadTight ? 1 : 2);
 }
 
 }  // namespace pf

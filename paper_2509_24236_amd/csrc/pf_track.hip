@@ -237,6 +237,32 @@ int32_t update(const VolView& vv, const Points& pts, const float* fitness, void*
 
 size_t workspace_bytes(const pf_intrinsics* K, const pf_track_params* p) { return ws_layout(K, p).total; }
 
+namespace {
+
+// The spread regime of every iteration of the last call on this thread, and the parameters it ran
+// with. The search size contracts along much the same path frame after frame, so a call with the
+// same parameters launches, per iteration, only the scoring shape of the regime that iteration had
+// last time, instead of the three regime-gated launches (two of which return at once). A wrong
+// forecast costs speed only: the sums are exact whatever the shape.
+struct RegimeForecast {
+    bool valid = false;
+    int K = 0, n_iters = 0, n_rates = 0, alt_K = 0, rates[3] = {}, Ks[3] = {};
+    float inv_vs = 0.0f;
+    int regime[PF_MAX_ITERS] = {};
+};
+thread_local RegimeForecast g_forecast;
+
+bool forecast_matches(const RegimeForecast& f, const pf_track_params* p, float inv_vs) {
+    if (!f.valid || f.K != p->K || f.n_iters != p->n_iters || f.n_rates != p->n_rates || f.alt_K != p->alt_K ||
+        f.inv_vs != inv_vs)
+        return false;
+    for (int r = 0; r < 3; ++r)
+        if (f.rates[r] != p->rates[r] || f.Ks[r] != p->Ks[r]) return false;
+    return true;
+}
+
+}  // namespace
+
 int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* init,
               const pf_track_params* p, pf_pose* out, pf_track_stats* stats, void* workspace, size_t ws_bytes,
               hipStream_t s) {
@@ -277,6 +303,7 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
     }
     if ((rc = state_init(st, init, p, vv.format, poses, s))) return rc;
     const bool timed = g_timing.on;
+    const bool forecast = forecast_matches(g_forecast, p, vv.inv_vs);
     int Gv[3];
     for (int r = 0; r < p->n_rates; ++r) Gv[r] = n_partials_for((int)((npix + p->rates[r] - 1) / p->rates[r]));
     for (int i = 1; i <= p->n_iters; ++i) {
@@ -284,7 +311,8 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
         const Points& S = views[r];
         const int K_i = p->alt_K ? p->Ks[r] : p->K;
         if (timed) (void)hipEventRecord(g_timing.ev[2 * (i - 1)], s);
-        if ((rc = launch_score(vv, S, poses, K_i + 1, fit, nv, s, st))) return rc;
+        const int expect = forecast ? g_forecast.regime[i - 1] : -1;
+        if ((rc = launch_score(vv, S, poses, K_i + 1, fit, nv, s, st, expect))) return rc;
         if (timed) (void)hipEventRecord(g_timing.ev[2 * (i - 1) + 1], s);
         if ((rc = launch_adv(true, vv, S, Gv[r], fit, st, p->K, s))) return rc;
         // the last iteration only completes (E*, s); its particles stay in `poses` / `fit`
@@ -320,6 +348,18 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
     if (hs.flags) return set_error(PF_EINVAL, "track_frame: inconsistent optimizer state (flags %d)", hs.flags);
     // iterations that ran (all n_iters unless the stop rule ended the optimization)
     const int n_run = hs.iter_done;
+    g_forecast.valid = true;
+    g_forecast.K = p->K;
+    g_forecast.n_iters = p->n_iters;
+    g_forecast.n_rates = p->n_rates;
+    g_forecast.alt_K = p->alt_K;
+    for (int r = 0; r < 3; ++r) {
+        g_forecast.rates[r] = p->rates[r];
+        g_forecast.Ks[r] = p->Ks[r];
+    }
+    g_forecast.inv_vs = vv.inv_vs;
+    for (int i = 0; i < PF_MAX_ITERS; ++i)
+        g_forecast.regime[i] = i < n_run && i < p->n_iters ? spread_regime_of(hr[i].s_rad, hr[i].s_m, vv.inv_vs) : -1;
     if (timed) {
         for (int i = 0; i < n_run; ++i) {
             float ms = 0.0f;

@@ -463,6 +463,31 @@ def test_fullsize_track_frame(pf, orc, dev, cfg2_full):
     del v32
 
 
+def test_fullsize_regime_forecast_changes_nothing(pf, dev, cfg2_full):
+    """track_frame launches, per iteration, only the scoring shape of the spread regime the same
+    iteration had in the previous call with the same parameters. Whether that forecast is right
+    (same frame again), wrong (forecast from a run started far away) or absent (other parameters
+    in between) changes nothing in the result."""
+    say("[fullsize] regime forecast: right, wrong and absent give the same frame")
+    f, ov = cfg2_full
+    gv = upload(pf, f["vol"], ov.T.astype(np.float32), ov.W, dev)
+    depth = torch.as_tensor(f["depth"](1)).to(dev)
+    R0, t0 = f["rel"][1]
+    prm = pf.TrackParams(seed=14, frame_index=1, n_iters=20, K=3072, rates=(8, 16, 32), pixel_stride=1)
+    other = pf.TrackParams(seed=14, frame_index=1, n_iters=19, K=3072, rates=(8, 16, 32), pixel_stride=1)
+    trk = pf.Tracker(f["intr"], prm, device=dev)
+    pf.Tracker(f["intr"], other, device=dev).track(gv, depth, R0, t0)             # no forecast for prm
+    ref = trk.track(gv, depth, R0, t0)
+    same = trk.track(gv, depth, R0, t0)                                            # right forecast
+    far = synth.rot(np.array([0.02, -0.03, 0.01])) @ R0
+    trk.track(gv, depth, far, t0 + 0.04)                                           # forecast from elsewhere
+    wrong = trk.track(gv, depth, R0, t0)
+    for R, t, st in (same, wrong):
+        assert np.array_equal(R, ref[0]) and np.array_equal(t, ref[1])
+        assert list(st.Estar) == list(ref[2].Estar) and list(st.n_adv) == list(ref[2].n_adv)
+        assert st.E_final == ref[2].E_final
+
+
 def test_fullsize_track_frame_paper_schedule(pf, orc, dev, cfg2_full):
     say("[fullsize] track frame 1 with K 1024/3072/10240 at rates 8/16/32 and the stop rule")
     f, ov = cfg2_full

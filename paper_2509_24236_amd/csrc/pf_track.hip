@@ -358,8 +358,13 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
         g_forecast.Ks[r] = p->Ks[r];
     }
     g_forecast.inv_vs = vv.inv_vs;
-    for (int i = 0; i < PF_MAX_ITERS; ++i)
-        g_forecast.regime[i] = i < n_run && i < p->n_iters ? spread_regime_of(hr[i].s_rad, hr[i].s_m, vv.inv_vs) : -1;
+    // iterations after an early exit take the last regime that ran (their launches return at once
+    // while the optimization stays stopped)
+    int last = -1;
+    for (int i = 0; i < PF_MAX_ITERS; ++i) {
+        if (i < n_run && i < p->n_iters) last = spread_regime_of(hr[i].s_rad, hr[i].s_m, vv.inv_vs);
+        g_forecast.regime[i] = last;
+    }
     if (timed) {
         for (int i = 0; i < n_run; ++i) {
             float ms = 0.0f;

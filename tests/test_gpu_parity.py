@@ -486,6 +486,15 @@ def test_fullsize_regime_forecast_changes_nothing(pf, dev, cfg2_full):
         assert np.array_equal(R, ref[0]) and np.array_equal(t, ref[1])
         assert list(st.Estar) == list(ref[2].Estar) and list(st.n_adv) == list(ref[2].n_adv)
         assert st.E_final == ref[2].E_final
+    # the paper's schedule with the early exit: iterations after the stop take the last regime
+    paper = pf.TrackParams(seed=14, frame_index=1, n_iters=20, K=10240, Ks=(1024, 3072, 10240), rates=(8, 16, 32),
+                           pixel_stride=1, stop_deg=0.05, stop_m=0.0005)
+    tp = pf.Tracker(f["intr"], paper, device=dev)
+    pf.Tracker(f["intr"], other, device=dev).track(gv, depth, R0, t0)
+    ref = tp.track(gv, depth, R0, t0)
+    again = tp.track(gv, depth, R0, t0)
+    assert ref[2].n_iters < 20 and again[2].n_iters == ref[2].n_iters
+    assert np.array_equal(again[0], ref[0]) and np.array_equal(again[1], ref[1])
 
 
 def test_fullsize_track_frame_paper_schedule(pf, orc, dev, cfg2_full):

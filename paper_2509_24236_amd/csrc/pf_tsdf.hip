@@ -118,6 +118,7 @@ struct FuseArgs {
     // FP32 copies for the conservative pre-test: camera-frame depth and pixel coordinates of
     // voxel (i, j, k) are q = Q0 + i Qi + j Qj + k Qk with Q0 = R^T (origin - t), Qi = R^T e_x vs, ...
     float q0[3], qi[3], qj[3], qk[3];
+    double zfar;   // largest camera depth of a grid corner: no voxel lies deeper
 };
 
 // The projection is evaluated in FP64 with the same operation order as the plain definition,
@@ -368,6 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_bricks_candidates(FuseArgs a, BrickA
     const double D = (double)a.depth[pix];
     if (!(isfinite(D) && D > 0.0)) return;
     const double z0 = fmax(D - a.tau, 0.0), z1 = D + a.tau;
+    if (z0 > a.zfar) return;   // the segment lies beyond every voxel (and its footprint stays bounded)
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     const double org[3] = {a.ox, a.oy, a.oz};
     for (int c = 0; c < 8; ++c) {
@@ -603,6 +605,13 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
         a.qj[r] = (float)(a.R[3 + r] * v->voxel_size);
         a.qk[r] = (float)(a.R[6 + r] * v->voxel_size);
     }
+    a.zfar = -1e300;
+    for (int c = 0; c < 8; ++c) {
+        const double p[3] = {a.ox + a.vs * ((c & 1) ? v->nx - 1 : 0), a.oy + a.vs * ((c & 2) ? v->ny - 1 : 0),
+                             a.oz + a.vs * ((c & 4) ? v->nz - 1 : 0)};
+        a.zfar = fmax(a.zfar, a.R[2] * (p[0] - a.t[0]) + a.R[5] * (p[1] - a.t[1]) + a.R[8] * (p[2] - a.t[2]));
+    }
+    a.zfar += 1e-6 * (fabs(a.zfar) + 1.0);
     a.fx = K->fx;
     a.fy = K->fy;
     a.cx = K->cx;

@@ -123,6 +123,31 @@ def test_bricks_fusion_parity_cfg1(pf, orc, dev, cfg1, fmt):
     assert 0 < int(ov.bricks.sum()) < ov.bricks.size
 
 
+def test_bricks_fusion_extreme_depths(pf, orc, dev, cfg1):
+    """Depth pixels far beyond the grid (up to 1e30 m), invalid values and a camera inside the grid:
+    the candidate search stays bounded and the bricks match the oracle's."""
+    say("[bricks] extreme depth values")
+    spec, intr = cfg1["vol"], cfg1["intr"]
+    rng = np.random.default_rng(17)
+    depth = cfg1["depth1"].copy()
+    m = rng.random(depth.shape)
+    depth[m < 0.02] = 1e30
+    depth[(m >= 0.02) & (m < 0.04)] = 1e6
+    depth[(m >= 0.04) & (m < 0.05)] = np.nan
+    depth[(m >= 0.05) & (m < 0.06)] = -1.0
+    depth[(m >= 0.06) & (m < 0.07)] = np.inf
+    R, t = cfg1["gt1"]
+    ov = orc.Volume(spec)
+    ov.integrate_bricks(depth, intr, R, t, edge=E)
+    gv = pf.Tsdf(spec, device=dev, layout=pf.LAYOUT_BRICKS, max_bricks=4096)
+    gv.integrate(torch.as_tensor(depth).to(dev), intr, R, t)
+    n, overflow = gv.bricks_used()
+    assert overflow == 0 and n == int(ov.bricks.sum()) > 0
+    T, W = gv.export_linear()
+    assert np.array_equal(W.cpu().numpy(), ov.W.astype(np.float32))
+    assert np.abs(T.cpu().numpy().astype(np.float64) - ov.T)[ov.W > 0].max() <= T_TOL[0]
+
+
 def test_bricks_overflow(pf, orc, dev, cfg1):
     say("[bricks] pool smaller than the band")
     spec, intr = cfg1["vol"], cfg1["intr"]

@@ -283,6 +283,34 @@ def test_bricks_batch_equals_cells(pf, dev, cfg1):
         assert np.array_equal(R1, R2) and np.array_equal(t1, t2) and s1.E_final == s2.E_final
 
 
+def test_bricks_sequence_room_2cm(pf, orc, dev):
+    """Sixteen frames of the paper-scale sequence (every 12th, so the camera sweeps the room, with
+    fast rotations between them) fused at the true poses into the whole room at 2 cm: after every
+    fourth frame the bricks, weights and values match the oracle's bricked fusion, and at the end
+    every cell block of every slot equals its stored corners."""
+    f = synth.cfg2_frames(181)
+    spec = synth.room_spec(f["scene"], 0.02, 0.08)
+    say(f"[bricks] sequence into the room at 2 cm: {spec.nx}x{spec.ny}x{spec.nz}")
+    intr = f["intr"]
+    ov = orc.Volume(spec)
+    gv = pf.Tsdf(spec, device=dev, layout=pf.LAYOUT_BRICKS, max_bricks=40000)
+    for q, t in enumerate(range(0, 181, 12)):
+        depth = f["depth"](t)
+        ov.integrate_bricks(depth, intr, *f["gt"][t], edge=E)
+        gv.integrate(torch.as_tensor(depth).to(dev), intr, *f["gt"][t])
+        if q % 4 == 3 or t == 180:
+            n, overflow = gv.bricks_used()
+            assert overflow == 0 and n == int(ov.bricks.sum())
+            T, W = gv.export_linear()
+            assert np.array_equal(W.cpu().numpy(), ov.W.astype(np.float32)), t
+            upd = ov.W > 0
+            # the FP32 running average rounds once per update
+            assert np.abs(T.cpu().numpy().astype(np.float64) - ov.T)[upd].max() <= 2e-6 * (1 + q), t
+            say(f"    frame {t}: {n} bricks")
+    index, _ = check_pool_consistent(pf, gv)
+    assert np.array_equal(index >= 0, ov.bricks.astype(bool))
+
+
 # ----------------------------------------------------------------------------- full size
 def test_fullsize_bricks_whole_room(pf, orc, dev):
     """The paper-scale sequence's room as one bricked grid at 1 cm (608 x 312 x 512 voxels, the

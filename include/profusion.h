@@ -54,7 +54,10 @@ extern "C" {
  *         (0,0,0) (1,0,0) (0,1,0) (1,1,0) (0,0,1) (1,0,1) (0,1,1) (1,1,1). A sample then reads
  *         one contiguous 32-byte (FP32) or 16-byte block instead of four rows; the replica is 8x
  *         the size of T and is kept equal to T by tsdf_init, tsdf_import_linear and
- *         tsdf_integrate (which rewrites only the cells of voxels whose stored value changed). */
+ *         tsdf_integrate (which rewrites only the cells of voxels whose stored value changed),
+ *         except that in the FP32 and FP16 formats a corner outside the band (|T| >= 1, the +1
+ *         sentinel included) is stored as NaN: the interpolated value of a sample is then NaN
+ *         exactly when the sample is not valid, which replaces eight corner tests by one. */
 /* BRICKS: a sparse volume for scenes larger than a dense grid affords (nx, ny, nz multiples of 8).
  *         Bricks of 8x8x8 voxels live in a pool of max_bricks slots behind a dense brick-index
  *         grid (one int32 per brick: its slot, or -1); there is no hash table. The T buffer holds,
@@ -63,9 +66,10 @@ extern "C" {
  *         +1 corners), the index grid (entry (bz * ny/8 + by) * nx/8 + bx for the brick of voxels
  *         8bx..8bx+7, ...), a candidate list of the same size (scratch of tsdf_integrate), the
  *         brick coordinates of every slot (int32 x4), the slots' T (512 values each, x-fastest
- *         inside the brick) and their cells (512 per brick,
- *         cell (x, y, z) local to the brick at x + 8y + 64z, its 8 corners in the CELLS order;
- *         corners in the next brick along +x/+y/+z read that brick, or +1 where it has no slot).
+ *         inside the brick) and their cells (512 per brick, cell (x, y, z) local to the brick at
+ *         x + 8y + 64z, its 8 corners in the CELLS order and with the CELLS marking of corners
+ *         outside the band; corners in the next brick along +x/+y/+z read that brick, or +1
+ *         where it has no slot).
  *         The W buffer holds the slots' W. A voxel outside every allocated brick reads T = +1,
  *         W = 0. tsdf_integrate first gives a slot to every brick that holds a voxel the frame
  *         puts in the band (-tau <= eta < tau, the same FP64 test as the update), then updates

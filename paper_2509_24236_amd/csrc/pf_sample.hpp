@@ -24,9 +24,12 @@ struct Fmt;
 
 // `fix` maps a valid |value| (in stored units, always below the band limit) into [0, 2^32);
 // `unfix` maps the fixed-point sum back to normalised TSDF units.
+// `nan_cells`: the cell replica marks corners outside the band as NaN, so a sample is valid exactly
+// when its interpolated value is a number (the x-fastest storage keeps the +1 sentinel).
 template <>
 struct Fmt<PF_F32_W_F32> {
     using T = float;
+    static constexpr bool nan_cells = true;
     __device__ static inline float val(float a) { return a; }
     __device__ static inline bool in_band(float a) { return fabsf(a) < 1.0f; }
     static constexpr float scale = 1.0f;
@@ -37,6 +40,7 @@ struct Fmt<PF_F32_W_F32> {
 template <>
 struct Fmt<PF_F16_W_U8> {
     using T = __half;
+    static constexpr bool nan_cells = true;
     __device__ static inline float val(__half a) { return __half2float(a); }
     __device__ static inline bool in_band(float a) { return fabsf(a) < 1.0f; }
     static constexpr float scale = 1.0f;
@@ -47,6 +51,7 @@ struct Fmt<PF_F16_W_U8> {
 template <>
 struct Fmt<PF_I16_W_U8> {
     using T = int16_t;
+    static constexpr bool nan_cells = false;
     __device__ static inline float val(int16_t a) { return (float)a; }
     __device__ static inline bool in_band(float a) { return fabsf(a) < 32767.0f; }
     static constexpr float scale = 1.0f / 32767.0f;
@@ -161,6 +166,14 @@ __device__ inline GridPose fold_pose(const float* P, float inv_vs, float gx0, fl
     return g;
 }
 
+// floor(x) as an int (v_cvt_flr_i32_f32; the compiler emits floor and convert separately). Values
+// outside the int range only ever produce out-of-grid cells, which are clamped and rejected.
+__device__ inline int floor_to_int(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 // Evaluates one point (already divided by the voxel size) against NP poses in three phases:
 // the cell of every pose, then all gathers, then validity and interpolation, so that the gathers
 // of all poses are in flight together. The cell is clamped into the grid so every gather is in
@@ -180,15 +193,19 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
         const float gx = fmaf(g[j].r[0], x, fmaf(g[j].r[1], y, fmaf(g[j].r[2], z, g[j].t[0])));
         const float gy = fmaf(g[j].r[3], x, fmaf(g[j].r[4], y, fmaf(g[j].r[5], z, g[j].t[1])));
         const float gz = fmaf(g[j].r[6], x, fmaf(g[j].r[7], y, fmaf(g[j].r[8], z, g[j].t[2])));
-        const float fx0 = floorf(gx), fy0 = floorf(gy), fz0 = floorf(gz);
-        const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
-        inb[j] = ((unsigned)ix < lx) & ((unsigned)iy < ly) & ((unsigned)iz < lz);
-        const int cx = min(max(ix, 0), (int)lx - 1);
-        const int cy = min(max(iy, 0), (int)ly - 1);
-        const int cz = min(max(iz, 0), (int)lz - 1);
-        f[j][0] = gx - fx0;
-        f[j][1] = gy - fy0;
-        f[j][2] = gz - fz0;
+        // lower corner and fraction: floor as an integer in one instruction, and x - floor(x), which
+        // is exact in FP32, from the fract instruction
+        const int ix = floor_to_int(gx), iy = floor_to_int(gy), iz = floor_to_int(gz);
+        const unsigned ux = (unsigned)ix, uy = (unsigned)iy, uz = (unsigned)iz;
+        inb[j] = (ux < lx) & (uy < ly) & (uz < lz);
+        // any corner outside the grid (negative ones wrap to large values) is clamped to the last
+        // cell: the gather stays in bounds and the sample is rejected by inb
+        const int cx = (int)min(ux, lx - 1u);
+        const int cy = (int)min(uy, ly - 1u);
+        const int cz = (int)min(uz, lz - 1u);
+        f[j][0] = __builtin_amdgcn_fractf(gx);
+        f[j][1] = __builtin_amdgcn_fractf(gy);
+        f[j][2] = __builtin_amdgcn_fractf(gz);
         cl[j][0] = cx;
         cl[j][1] = cy;
         cl[j][2] = cz;
@@ -246,11 +263,16 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
 #pragma unroll
         for (int q = 0; q < 8; ++q) c[j][q] = d ? c[j - 1][q] : c[j][q];
     }
+    // validity: with NaN-marked cells a NaN corner makes every step below NaN, so the value itself
+    // says whether all 8 corners are in the band; otherwise each corner is tested
+    constexpr bool kNanTest = LAYOUT != PF_LAYOUT_LINEAR && Fmt<FMT>::nan_cells;
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         bool ok = inb[j];
+        if constexpr (!kNanTest) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) ok &= Fmt<FMT>::in_band(c[j][q]);
+            for (int q = 0; q < 8; ++q) ok &= Fmt<FMT>::in_band(c[j][q]);
+        }
         const float a00 = fmaf(f[j][0], c[j][1] - c[j][0], c[j][0]);
         const float a10 = fmaf(f[j][0], c[j][3] - c[j][2], c[j][2]);
         const float a01 = fmaf(f[j][0], c[j][5] - c[j][4], c[j][4]);
@@ -258,6 +280,7 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
         const float b0 = fmaf(f[j][1], a10 - a00, a00);
         const float b1 = fmaf(f[j][1], a11 - a01, a01);
         const float v = fmaf(f[j][2], b1 - b0, b0);
+        if constexpr (kNanTest) ok &= !__builtin_isnan(v);
         const float a = ok ? fminf(fabsf(v) * Fmt<FMT>::fix, kFixMax) : 0.0f;
         sum[j] += (FixSum)(unsigned)a;
         cnt[j] += ok ? 1 : 0;

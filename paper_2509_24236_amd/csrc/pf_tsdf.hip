@@ -30,6 +30,8 @@ struct Store<PF_F32_W_F32> {
     __device__ static inline W encw(float w) { return w; }
     __device__ static inline float decw(W w) { return w; }
     __device__ static inline bool same(T a, T b) { return __float_as_uint(a) == __float_as_uint(b); }
+    // replica value of a stored T: itself inside the band, NaN outside it
+    __device__ static inline T cell(T v) { return fabsf(v) < 1.0f ? v : __uint_as_float(0x7fc00000u); }
 };
 
 template <>
@@ -41,6 +43,7 @@ struct Store<PF_F16_W_U8> {
     __device__ static inline W encw(float w) { return (uint8_t)fminf(255.0f, fmaxf(0.0f, rintf(w))); }
     __device__ static inline float decw(W w) { return (float)w; }
     __device__ static inline bool same(T a, T b) { return __half_as_ushort(a) == __half_as_ushort(b); }
+    __device__ static inline T cell(T v) { return fabsf(__half2float(v)) < 1.0f ? v : __ushort_as_half(0x7e00u); }
 };
 
 template <>
@@ -53,6 +56,7 @@ struct Store<PF_I16_W_U8> {
     __device__ static inline W encw(float w) { return (uint8_t)fminf(255.0f, fmaxf(0.0f, rintf(w))); }
     __device__ static inline float decw(W w) { return (float)w; }
     __device__ static inline bool same(T a, T b) { return a == b; }
+    __device__ static inline T cell(T v) { return v; }   // no NaN: the scoring tests the corners
 };
 
 struct Dims {
@@ -71,7 +75,8 @@ Dims dims_of(const pf_tsdf* v) {
     return d;
 }
 
-// Writes voxel (i, j, k)'s stored value into every cell that has it as a corner.
+// Writes voxel (i, j, k)'s replica value (Store::cell of its stored value) into every cell that has
+// it as a corner.
 template <typename T>
 __device__ inline void write_corners(T* cells, const Dims& d, int i, int j, int k, T val) {
     const int cnx = d.nx - 1, cny = d.ny - 1, cnz = d.nz - 1;
@@ -100,8 +105,9 @@ __global__ __launch_bounds__(kBlock) void k_init(void* Tv, void* Wv, void* Cv, D
         T[i] = one;
         W[i] = S::encw(0.0f);
     }
+    const typename S::T one_cell = S::cell(one);
     if (C)
-        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (d.ncells << 3); i += stride) C[i] = one;
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (d.ncells << 3); i += stride) C[i] = one_cell;
 }
 
 struct FuseArgs {
@@ -198,7 +204,7 @@ __device__ inline void fuse_voxel(const FuseArgs& a, int i, int j, int k) {
     typename Store<FMT>::T tnew;
     const int64_t idx = ((int64_t)k * a.d.ny + j) * a.d.nx + i;
     if (fuse_apply<FMT>(a, idx, phi, tnew) && a.C)
-        write_corners(static_cast<typename Store<FMT>::T*>(a.C), a.d, i, j, k, tnew);
+        write_corners(static_cast<typename Store<FMT>::T*>(a.C), a.d, i, j, k, Store<FMT>::cell(tnew));
 }
 
 // Grid: a workgroup owns a brick of kFuseX x kFuseY x kFuseZ voxels (a wave per x row, each thread
@@ -279,14 +285,14 @@ __global__ __launch_bounds__(kBlock) void k_build_cells(const void* Tv, void* Cv
         const int64_t b = ((int64_t)ck * d.ny + cj) * d.nx + ci;
         const int64_t nxy = (int64_t)d.nx * d.ny;
         typename S::T* o = C + (c << 3);
-        o[0] = T[b];
-        o[1] = T[b + 1];
-        o[2] = T[b + d.nx];
-        o[3] = T[b + d.nx + 1];
-        o[4] = T[b + nxy];
-        o[5] = T[b + nxy + 1];
-        o[6] = T[b + nxy + d.nx];
-        o[7] = T[b + nxy + d.nx + 1];
+        o[0] = S::cell(T[b]);
+        o[1] = S::cell(T[b + 1]);
+        o[2] = S::cell(T[b + d.nx]);
+        o[3] = S::cell(T[b + d.nx + 1]);
+        o[4] = S::cell(T[b + nxy]);
+        o[5] = S::cell(T[b + nxy + 1]);
+        o[6] = S::cell(T[b + nxy + d.nx]);
+        o[7] = S::cell(T[b + nxy + d.nx + 1]);
     }
 }
 
@@ -336,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_bricks_reset(BrickArgs b, int64_t n_
     if (blockIdx.x == 0 && threadIdx.x < 8) {
         if (threadIdx.x == 0) *b.hdr = BrickHeader{0, 0, 0, 0};
         reinterpret_cast<typename Store<FMT>::T*>(reinterpret_cast<char*>(b.hdr) + kBrickOnes)[threadIdx.x] =
-            Store<FMT>::enc(1.0f);
+            Store<FMT>::cell(Store<FMT>::enc(1.0f));
     }
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n_index; i += stride) b.index[i] = -1;
@@ -431,15 +437,15 @@ __global__ __launch_bounds__(kBlock) void k_bricks_mark(FuseArgs a, BrickArgs b)
     }
 }
 
-// Value of voxel (i, j, k) for a cell corner: from slot s < src_limit, +1 elsewhere.
+// Replica value of voxel (i, j, k) as a cell corner: from slot s < src_limit, +1 elsewhere.
 template <int FMT>
 __device__ inline typename Store<FMT>::T brick_voxel(const BrickArgs& b, const Dims& d, int i, int j, int k,
                                                      int src_limit) {
     using S = Store<FMT>;
-    if (i >= d.nx || j >= d.ny || k >= d.nz) return S::enc(1.0f);
+    if (i >= d.nx || j >= d.ny || k >= d.nz) return S::cell(S::enc(1.0f));
     const int s2 = brick_slot(b, i >> 3, j >> 3, k >> 3);
-    if (s2 < 0 || s2 >= src_limit) return S::enc(1.0f);
-    return static_cast<const typename S::T*>(b.T)[((int64_t)s2 << 9) + brick_local(i, j, k)];
+    if (s2 < 0 || s2 >= src_limit) return S::cell(S::enc(1.0f));
+    return S::cell(static_cast<const typename S::T*>(b.T)[((int64_t)s2 << 9) + brick_local(i, j, k)]);
 }
 
 // Cells of slots [begin, end), corners read from slots below src_limit (+1 elsewhere). With
@@ -468,7 +474,7 @@ __global__ __launch_bounds__(kBlock) void k_bricks_cells(BrickArgs b, Dims d, in
     }
 }
 
-// Writes voxel (i, j, k)'s value into every allocated cell that has it as a corner.
+// Writes voxel (i, j, k)'s replica value into every allocated cell that has it as a corner.
 template <typename T>
 __device__ inline void write_corners_bricks(const BrickArgs& b, const Dims& d, int i, int j, int k, T val) {
     T* C = static_cast<T*>(b.C);
@@ -499,7 +505,8 @@ __global__ __launch_bounds__(kBlock) void k_bricks_integrate(FuseArgs a, BrickAr
             double phi;
             if (!fuse_decide(a, i, j, k, phi)) continue;
             typename Store<FMT>::T tnew;
-            if (fuse_apply<FMT>(a, ((int64_t)slot << 9) + e, phi, tnew)) write_corners_bricks(b, a.d, i, j, k, tnew);
+            if (fuse_apply<FMT>(a, ((int64_t)slot << 9) + e, phi, tnew))
+                write_corners_bricks(b, a.d, i, j, k, Store<FMT>::cell(tnew));
         }
     }
 }

@@ -32,6 +32,8 @@ struct BatchProb {
     float* pz;
     int* counts;
     int* ncount;            // [0] = |M|, [1 + r] = |S_r|
+    int* pix;               // pixel index of every point of M
+    ViewTiles tiles[3];
     float* vx[3];
     float* vy[3];
     float* vz[3];
@@ -82,11 +84,25 @@ __global__ __launch_bounds__(kBpThreads) void kb_bp_scatter(const BatchProb* tab
     bp_scatter_step(P.bp, P.counts, P.bp_blocks, P.px, P.py, P.pz, P.ncount, w.y);
 }
 
-__global__ __launch_bounds__(256) void kb_view(const BatchProb* tab, const int4* items) {
+__global__ __launch_bounds__(256) void kb_view_mark(const BatchProb* tab, const int4* items) {
+    const int4 w = items[blockIdx.x];
+    const BatchProb& P = tab[w.x];
+    view_mark_step(P.pix, P.ncount, P.rates[w.y], P.bp.width, P.tiles[w.y], w.z);
+}
+
+// one workgroup per (problem, view); views with rate 1 have no tiles
+__global__ __launch_bounds__(256) void kb_view_scan(const BatchProb* tab) {
+    const BatchProb& P = tab[blockIdx.x / 3];
+    const int r = blockIdx.x % 3;
+    if (P.tiles[r].n_tiles > 0) view_scan_step(P.tiles[r]);
+}
+
+__global__ __launch_bounds__(256) void kb_view_scatter(const BatchProb* tab, const int4* items) {
     const int4 w = items[blockIdx.x];
     const BatchProb& P = tab[w.x];
     const int r = w.y;
-    view_step(P.px, P.py, P.pz, P.ncount, P.rates[r], P.caps[r], P.vx[r], P.vy[r], P.vz[r], P.ncount + 1 + r, w.z);
+    view_scatter_step(P.px, P.py, P.pz, P.pix, P.ncount, P.rates[r], P.bp.width, P.tiles[r], P.vx[r], P.vy[r],
+                      P.vz[r], P.ncount + 1 + r, w.z);
 }
 
 __global__ void kb_state_set(const BatchProb* tab, const pf_track_state* init, int n) {
@@ -187,8 +203,11 @@ __global__ void kb_polish_commit(const BatchProb* tab) {
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
+int rate_or_1(const pf_track_params& p, int r) { return r < p.n_rates ? p.rates[r] : 1; }
+
 struct ProbLayout {
-    size_t pts, counts, ncount, views[3], poses, fit, nv, state, recs, fin, polish, end;
+    size_t pts, pix, counts, ncount, views[3], tiles_mask[3], tiles_start[3], n_tiles[3], poses, fit, nv, state, recs,
+        fin, polish, end;
 };
 
 ProbLayout prob_layout(const pf_batch_problem& q, size_t off) {
@@ -197,14 +216,31 @@ ProbLayout prob_layout(const pf_batch_problem& q, size_t off) {
     const pf_track_params& p = q.params;
     L.pts = off;
     off += al(3 * npix * sizeof(float));
+    L.pix = off;
+    off += al(npix * sizeof(int));
     L.counts = off;
     off += al(((npix + kBpChunk - 1) / kBpChunk + 1) * sizeof(int));
     L.ncount = off;
     off += al(8 * sizeof(int));
     for (int r = 0; r < 3; ++r) {
         L.views[r] = off;
-        if (r < p.n_rates && p.rates[r] > 1) off += al(3 * ((npix + p.rates[r] - 1) / p.rates[r]) * sizeof(float));
+        L.n_tiles[r] = 0;
+        if (r < p.n_rates && p.rates[r] > 1) {
+            off += al(3 * ((npix + p.rates[r] - 1) / p.rates[r]) * sizeof(float));
+            L.n_tiles[r] = (size_t)view_n_tiles(q.K.width, q.K.height, p.rates[r]);
+        }
     }
+    // the tile masks back to back, cleared as one range by the count step
+    for (int r = 0; r < 3; ++r) {
+        L.tiles_mask[r] = off;
+        off += L.n_tiles[r] * sizeof(unsigned long long);
+    }
+    off = al(off);
+    for (int r = 0; r < 3; ++r) {
+        L.tiles_start[r] = off;
+        off += L.n_tiles[r] * sizeof(int);
+    }
+    off = al(off);
     L.poses = off;
     off += al((size_t)(p.K + 1) * 12 * sizeof(float));
     L.fit = off;
@@ -261,7 +297,11 @@ template <int FMT, int LAYOUT>
 int32_t run_t(pf_batch* b, hipStream_t s) {
     hipLaunchKernelGGL(kb_bp_count, dim3(b->n_bp), dim3(kBpThreads), 0, s, b->tab, b->items + b->off_bp);
     hipLaunchKernelGGL(kb_bp_scatter, dim3(b->n_bp), dim3(kBpThreads), 0, s, b->tab, b->items + b->off_bp);
-    if (b->n_view) hipLaunchKernelGGL(kb_view, dim3(b->n_view), dim3(256), 0, s, b->tab, b->items + b->off_view);
+    if (b->n_view) {
+        hipLaunchKernelGGL(kb_view_mark, dim3(b->n_view), dim3(256), 0, s, b->tab, b->items + b->off_view);
+        hipLaunchKernelGGL(kb_view_scan, dim3(3 * b->n), dim3(256), 0, s, b->tab);
+        hipLaunchKernelGGL(kb_view_scatter, dim3(b->n_view), dim3(256), 0, s, b->tab, b->items + b->off_view);
+    }
     hipLaunchKernelGGL(kb_state_set, dim3((b->n + 63) / 64), dim3(64), 0, s, b->tab, b->init, b->n);
     hipLaunchKernelGGL((kb_next<FMT, true>), dim3(b->n_next), dim3(256), 0, s, b->tab, b->items + b->off_next, 0, 1);
     for (int i = 1; i <= b->n_iters; ++i) {
@@ -386,6 +426,15 @@ pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const 
         P.bp.cx = (float)q.K.cx;
         P.bp.cy = (float)q.K.cy;
         P.bp_blocks = (int)((npix + kBpChunk - 1) / kBpChunk);
+        P.bp.nblocks = P.bp_blocks;
+        P.pix = reinterpret_cast<int*>(b->ws + L.pix);
+        P.bp.pix = P.pix;
+        P.bp.masks = reinterpret_cast<unsigned long long*>(b->ws + L.tiles_mask[0]);
+        P.bp.n_masks = (int)(L.n_tiles[0] + L.n_tiles[1] + L.n_tiles[2]);
+        for (int r = 0; r < 3; ++r)
+            P.tiles[r] = ViewTiles{reinterpret_cast<unsigned long long*>(b->ws + L.tiles_mask[r]),
+                                   reinterpret_cast<int*>(b->ws + L.tiles_start[r]),
+                                   view_tiles_x(q.K.width, rate_or_1(q.params, r)), (int)L.n_tiles[r]};
         P.K = q.params.K;
         P.px = reinterpret_cast<float*>(b->ws + L.pts);
         P.py = P.px + npix;

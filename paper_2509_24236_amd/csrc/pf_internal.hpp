@@ -184,7 +184,8 @@ int32_t launch_state_fitness(const VolView& vv, const Points& p, int S, const pf
                              float* E_out, int* n_out, hipStream_t s);
 
 int32_t launch_backproject(const float* depth, const pf_intrinsics* K, int stride, float* px, float* py, float* pz,
-                           int* n_out, int* block_counts, hipStream_t s);
+                           int* n_out, int* block_counts, hipStream_t s, int* pix = nullptr,
+                           unsigned long long* masks = nullptr, int n_masks = 0);
 size_t backproject_scratch_ints(const pf_intrinsics* K);
 
 }  // namespace pf

@@ -17,6 +17,9 @@ struct BpArgs {
     const float* depth;
     int width, height, stride;
     float fx, fy, cx, cy;
+    int* pix;                    // optional: pixel index of every compacted point
+    unsigned long long* masks;   // optional: view-tile masks cleared by the count step
+    int n_masks, nblocks;        // masks to clear; workgroups of the count step
 };
 
 __device__ inline bool bp_valid(const BpArgs& a, int pix, float& z) {
@@ -29,6 +32,7 @@ __device__ inline bool bp_valid(const BpArgs& a, int pix, float& z) {
 }
 
 __device__ inline void bp_count_step(const BpArgs& a, int* counts, int blk) {
+    for (int i = blk * kBpThreads + threadIdx.x; i < a.n_masks; i += a.nblocks * kBpThreads) a.masks[i] = 0ull;
     const int base = blk * kBpChunk + threadIdx.x * kBpPerThread;
     int c = 0;
 #pragma unroll
@@ -115,24 +119,92 @@ __device__ inline void bp_scatter_step(const BpArgs& a, const int* counts, int n
             px[pos] = ((float)u - a.cx) * z / a.fx;
             py[pos] = ((float)v - a.cy) * z / a.fy;
             pz[pos] = z;
+            if (a.pix) a.pix[pos] = pix;
             ++pos;
         }
     }
     __syncthreads();
 }
 
-// S_r[j] = M[j r] for j < ceil(n / r), copied contiguously; the count goes to *n_view.
-__device__ inline void view_step(const float* px, const float* py, const float* pz, const int* n_all, int r, int cap,
-                                 float* vx, float* vy, float* vz, int* n_view, int blk) {
-    const int n = *n_all;
-    const int m = (n + r - 1) / r;
+// ------------------------------------------------------------------ sub-sampled views
+// S_r holds M[j r] for j < ceil(n / r) (the set the method defines), copied contiguously in an order
+// chosen for the gathers: tiles of 32 image rows by 2 r columns, row by row inside a tile. A
+// wavefront's 64 lanes then take a 32 x 2 patch of neighbouring points instead of 64 points
+// spread along a row, r pixels apart, and its stencils share cache lines. Sums over a view are
+// exact integers or are taken in this fixed order, so the order changes speed only. Two points
+// of S_r in one row are at least r pixels apart, so a row puts at most one point in each half of
+// a tile: (row mod 32, half) is a distinct bit of the tile's 64-bit mask, and a point's place in
+// the view is its tile's start plus the number of lower bits set.
+constexpr int kTileRows = 32;
+
+struct ViewTiles {
+    unsigned long long* mask;   // per tile
+    int* start;                 // per tile: position of its first point in the view
+    int tiles_x, n_tiles;
+};
+
+__host__ __device__ inline int view_tiles_x(int width, int r) { return (width + 2 * r - 1) / (2 * r); }
+__host__ __device__ inline int view_n_tiles(int width, int height, int r) {
+    return view_tiles_x(width, r) * ((height + kTileRows - 1) / kTileRows);
+}
+
+__device__ inline int view_tile(int pix, int width, int r, int tiles_x, int& bit) {
+    const int v = pix / width, u = pix - v * width;
+    const int cx = u / (2 * r);
+    bit = (v % kTileRows) * 2 + (u - cx * 2 * r >= r ? 1 : 0);
+    return (v / kTileRows) * tiles_x + cx;
+}
+
+// Sets the bit of every point of S_r (the masks were cleared by the count step).
+__device__ inline void view_mark_step(const int* pix, const int* n_all, int r, int width, const ViewTiles& t, int blk) {
+    const int m = (*n_all + r - 1) / r;
+    const int j = blk * 256 + threadIdx.x;
+    if (j >= m) return;
+    int bit;
+    const int tile = view_tile(pix[j * r], width, r, t.tiles_x, bit);
+    atomicOr(&t.mask[tile], 1ull << bit);
+}
+
+// Exclusive scan of the tiles' point counts; one workgroup of 256 threads.
+__device__ inline void view_scan_step(const ViewTiles& t) {
+    __shared__ int part[256];
+    const int per = (t.n_tiles + 255) / 256;
+    const int q0 = threadIdx.x * per, q1 = min(t.n_tiles, q0 + per);
+    int c = 0;
+    for (int q = q0; q < q1; ++q) c += __popcll(t.mask[q]);
+    part[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < 256; ++w) {
+            const int x = part[w];
+            part[w] = acc;
+            acc += x;
+        }
+    }
+    __syncthreads();
+    int acc = part[threadIdx.x];
+    for (int q = q0; q < q1; ++q) {
+        t.start[q] = acc;
+        acc += __popcll(t.mask[q]);
+    }
+}
+
+// Writes every point of S_r at its place; the count goes to *n_view.
+__device__ inline void view_scatter_step(const float* px, const float* py, const float* pz, const int* pix,
+                                         const int* n_all, int r, int width, const ViewTiles& t, float* vx, float* vy,
+                                         float* vz, int* n_view, int blk) {
+    const int m = (*n_all + r - 1) / r;
     const int j = blk * 256 + threadIdx.x;
     if (j == 0) *n_view = m;
-    if (j < m && j < cap) {
-        vx[j] = px[j * r];
-        vy[j] = py[j * r];
-        vz[j] = pz[j * r];
-    }
+    if (j >= m) return;
+    const int q = j * r;
+    int bit;
+    const int tile = view_tile(pix[q], width, r, t.tiles_x, bit);
+    const int pos = t.start[tile] + __popcll(t.mask[tile] & ((1ull << bit) - 1ull));
+    vx[pos] = px[q];
+    vy[pos] = py[q];
+    vz[pos] = pz[q];
 }
 
 // ------------------------------------------------------------------ optimizer state

@@ -51,9 +51,27 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_scatter(BpArgs a, const int* 
     bp_scatter_step(a, counts, nblocks, px, py, pz, n_out, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_view(const float* px, const float* py, const float* pz, const int* n_all,
-                                              int r, int cap, float* vx, float* vy, float* vz, int* n_view) {
-    view_step(px, py, pz, n_all, r, cap, vx, vy, vz, n_view, blockIdx.x);
+// The sub-sampled views of a frame, built together: blockIdx.y is the view.
+struct ViewSet {
+    int rate[3];
+    ViewTiles t[3];
+    float* vx[3];
+    float* vy[3];
+    float* vz[3];
+    int* n_view[3];
+};
+
+__global__ __launch_bounds__(256) void k_view_mark(const int* pix, const int* n_all, int width, ViewSet v) {
+    view_mark_step(pix, n_all, v.rate[blockIdx.y], width, v.t[blockIdx.y], blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_view_scan(ViewSet v) { view_scan_step(v.t[blockIdx.x]); }
+
+__global__ __launch_bounds__(256) void k_view_scatter(const float* px, const float* py, const float* pz, const int* pix,
+                                                      const int* n_all, int width, ViewSet v) {
+    const int y = blockIdx.y;
+    view_scatter_step(px, py, pz, pix, n_all, v.rate[y], width, v.t[y], v.vx[y], v.vy[y], v.vz[y], v.n_view[y],
+                      blockIdx.x);
 }
 
 __global__ void k_state_set(pf_track_state* st, pf_track_state init) { *st = init; }
@@ -147,7 +165,8 @@ pf_track_state make_state(const pf_pose* init, const pf_track_params* p) {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t pts, counts, views[3], vcount, poses, fit, nv, state, recs, polish, fin, total;
+    size_t pts, pix, counts, views[3], tiles_mask[3], tiles_start[3], vcount, poses, fit, nv, state, recs, polish, fin,
+        total;
 };
 
 WsLayout ws_layout(const pf_intrinsics* K, const pf_track_params* p) {
@@ -156,15 +175,30 @@ WsLayout ws_layout(const pf_intrinsics* K, const pf_track_params* p) {
     size_t off = 0;
     L.pts = off;
     off += align_up(3 * npix * sizeof(float));
+    L.pix = off;
+    off += align_up(npix * sizeof(int));
     L.counts = off;
     off += align_up(((npix + kBpChunk - 1) / kBpChunk + 1) * sizeof(int));
+    // views, then the views' tile masks back to back (cleared as one range), then the tile starts
+    size_t nt[3] = {0, 0, 0};
     for (int r = 0; r < 3; ++r) {
         L.views[r] = off;
         if (r < p->n_rates && p->rates[r] > 1) {
             const size_t m = (npix + p->rates[r] - 1) / p->rates[r];
             off += align_up(3 * m * sizeof(float));
+            nt[r] = (size_t)view_n_tiles(K->width, K->height, p->rates[r]);
         }
     }
+    for (int r = 0; r < 3; ++r) {
+        L.tiles_mask[r] = off;
+        off += nt[r] * sizeof(unsigned long long);
+    }
+    off = align_up(off);
+    for (int r = 0; r < 3; ++r) {
+        L.tiles_start[r] = off;
+        off += nt[r] * sizeof(int);
+    }
+    off = align_up(off);
     L.vcount = off;
     off += align_up(8 * sizeof(int));
     L.poses = off;
@@ -192,7 +226,8 @@ size_t state_bytes(int K) { return partials_offset(K) + kMaxPartials * sizeof(Pa
 pf_track_state initial_state(const pf_pose* init, const pf_track_params* p) { return make_state(init, p); }
 
 int32_t launch_backproject(const float* depth, const pf_intrinsics* K, int stride, float* px, float* py, float* pz,
-                           int* n_out, int* block_counts, hipStream_t s) {
+                           int* n_out, int* block_counts, hipStream_t s, int* pix, unsigned long long* masks,
+                           int n_masks) {
     BpArgs a;
     a.depth = depth;
     a.width = K->width;
@@ -204,6 +239,10 @@ int32_t launch_backproject(const float* depth, const pf_intrinsics* K, int strid
     a.cy = (float)K->cy;
     const int npix = K->width * K->height;
     const int nb = (npix + kBpChunk - 1) / kBpChunk;
+    a.pix = pix;
+    a.masks = masks;
+    a.n_masks = n_masks;
+    a.nblocks = nb;
     hipLaunchKernelGGL(k_bp_count, dim3(nb), dim3(kBpThreads), 0, s, a, block_counts);
     int32_t rc = check_launch("backproject");
     if (rc) return rc;
@@ -283,9 +322,11 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
     IterRec* recs = reinterpret_cast<IterRec*>(ws + L.recs);
     const VolView vv = make_view(v);
 
-    int32_t rc = launch_backproject(depth, K, p->pixel_stride, px, py, pz, vcount, counts, s);
-    if (rc) return rc;
+    // the views' tile masks sit one after another, so the count step clears them as one range
+    int* pixv = reinterpret_cast<int*>(ws + L.pix);
+    ViewSet vs{};
     Points views[3];
+    int nviews = 0, max_blocks = 0, n_masks = 0;
     for (int r = 0; r < p->n_rates; ++r) {
         const int rate = p->rates[r];
         if (rate == 1) {
@@ -294,12 +335,28 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
         }
         const int cap = (int)((npix + rate - 1) / rate);
         float* vx = reinterpret_cast<float*>(ws + L.views[r]);
-        float* vy = vx + cap;
-        float* vz = vy + cap;
-        hipLaunchKernelGGL(k_view, dim3((cap + 255) / 256), dim3(256), 0, s, px, py, pz, vcount, rate, cap, vx, vy,
-                           vz, vcount + 1 + r);
+        const int y = nviews++;
+        vs.rate[y] = rate;
+        vs.t[y] = ViewTiles{reinterpret_cast<unsigned long long*>(ws + L.tiles_mask[r]),
+                            reinterpret_cast<int*>(ws + L.tiles_start[r]), view_tiles_x(K->width, rate),
+                            view_n_tiles(K->width, K->height, rate)};
+        vs.vx[y] = vx;
+        vs.vy[y] = vx + cap;
+        vs.vz[y] = vx + 2 * cap;
+        vs.n_view[y] = vcount + 1 + r;
+        max_blocks = max_blocks > (cap + 255) / 256 ? max_blocks : (cap + 255) / 256;
+        n_masks += vs.t[y].n_tiles;
+        views[r] = Points{vs.vx[y], vs.vy[y], vs.vz[y], 0, vs.n_view[y]};
+    }
+    int32_t rc = launch_backproject(depth, K, p->pixel_stride, px, py, pz, vcount, counts, s, pixv,
+                                    reinterpret_cast<unsigned long long*>(ws + L.tiles_mask[0]), n_masks);
+    if (rc) return rc;
+    if (nviews) {
+        hipLaunchKernelGGL(k_view_mark, dim3(max_blocks, nviews), dim3(256), 0, s, pixv, vcount, K->width, vs);
+        hipLaunchKernelGGL(k_view_scan, dim3(nviews), dim3(256), 0, s, vs);
+        hipLaunchKernelGGL(k_view_scatter, dim3(max_blocks, nviews), dim3(256), 0, s, px, py, pz, pixv, vcount,
+                           K->width, vs);
         if ((rc = check_launch("track_frame views"))) return rc;
-        views[r] = Points{vx, vy, vz, 0, vcount + 1 + r};
     }
     if ((rc = state_init(st, init, p, vv.format, poses, s))) return rc;
     const bool timed = g_timing.on;

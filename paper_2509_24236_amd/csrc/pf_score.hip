@@ -27,7 +27,7 @@ namespace {
 // bound by the vector memory pipeline. Each regime has its own launch shape; the choice changes
 // speed only, since the sums are exact.
 constexpr double kSpreadLever = 2.0;                       // metres
-constexpr double kSpreadWide = 2.0, kSpreadTight = 0.05;   // voxels
+constexpr double kSpreadWide = 2.0, kSpreadTight = 0.25;   // voxels
 
 __device__ inline int spread_regime(const pf_track_state* st, double inv_vs) {
     const double d = (st->s_rad * kSpreadLever + st->s_m) * inv_vs;

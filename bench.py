@@ -224,8 +224,8 @@ def bench_batch(args):
 def bench_regimes(args):
     """Scoring kernel alone across the spread regimes of one frame's optimization: 3073 poses drawn
     in a box of +-s around the true pose of frame 1 (s = 10, 1, 0.1, 0.001 deg with s/100 m), scored
-    on the rate-1/8 view against the 512^3 FP32 volume holding frame 0, with the launch shape the
-    automatic mode uses for that spread. Prints one JSON line; for counter runs (rocprofv3 --pmc),
+    on the rate-1/8 view (in track_frame's tiled order) against the 512^3 FP32 volume holding frame
+    0, with the launch shape the automatic mode uses for that spread. Prints one JSON line; for counter runs (rocprofv3 --pmc),
     every regime is launched 1 + args.steps times in order."""
     import numpy as np
     import torch
@@ -238,7 +238,14 @@ def bench_regimes(args):
     vol.integrate(torch.as_tensor(f["depth"](0)).to(dev), intr, np.eye(3), np.zeros(3))
     px, py, pz, n = pf.backproject(torch.as_tensor(f["depth"](1)).to(dev), intr, 1)
     N = int(n[0].item())
-    x, y, z = px[:N:8].contiguous(), py[:N:8].contiguous(), pz[:N:8].contiguous()
+    # the rate-1/8 view in the order track_frame builds it: tiles of 32 image rows by 16 columns,
+    # row by row inside a tile (the pixel of each point recovered from its coordinates)
+    S = torch.stack([px[:N:8], py[:N:8], pz[:N:8]], 1).cpu().numpy().astype(np.float64)
+    u = np.rint(intr.fx * S[:, 0] / S[:, 2] + intr.cx).astype(np.int64)
+    v = np.rint(intr.fy * S[:, 1] / S[:, 2] + intr.cy).astype(np.int64)
+    tile = (v // 32) * ((intr.width + 15) // 16) + u // 16
+    order = torch.as_tensor(np.lexsort((u, v % 32, tile))).to(dev)
+    x, y, z = px[:N:8][order].contiguous(), py[:N:8][order].contiguous(), pz[:N:8][order].contiguous()
     Rg, tg = f["gt"][1]
     rng = np.random.default_rng(0)
     out = {"workload": "particles_score, 3073 poses x rate-1/8 view of frame 1 (%d points), 512^3 f32 cells"

@@ -354,13 +354,17 @@ typedef struct pf_batch_problem {
     const float* depth;      /* device, float32 [height][width] */
     pf_intrinsics K;
     pf_pose init;            /* P^(0) */
-    pf_track_params params;  /* n_iters, n_rates equal across the batch; polish_steps must be 0 */
+    pf_track_params params;  /* n_iters, rates and polish_steps equal across the batch; the fixed
+                                schedule only (alt_K = 0, no stop rule) */
 } pf_batch_problem;
 
 /* Launch plan of a batch (the project autotuner chooses it per shape class). */
 typedef struct pf_batch_plan {
-    int32_t score_tk;        /* poses per scoring workgroup: 1, 2, 4 or 8 */
-    int32_t score_grid;      /* workgroups of the persistent scoring launch, >= 1 */
+    int32_t score_tk;        /* poses per scoring workgroup: 1, 2, 4 or 8; or 0, the shapes of
+                                track_frame by spread regime (2x64, 4x128, 4x256 poses x threads), one
+                                persistent launch each over the problems in that regime */
+    int32_t score_grid;      /* workgroups of the persistent scoring launch (x4 for the 64-thread
+                                shape), >= 1 */
     int32_t order;           /* 0: items in problem order; 1: problems with most points first */
     int32_t reserved;        /* must be 0 */
 } pf_batch_plan;

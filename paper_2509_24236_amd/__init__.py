@@ -468,8 +468,8 @@ def timing_read(reset: bool = False):
 # ----------------------------------------------------------------------------- batches
 @dataclasses.dataclass
 class BatchPlan:
-    score_tk: int = 4
-    score_grid: int = 1024
+    score_tk: int = 4        # poses per workgroup (1, 2, 4, 8), or 0: the spread-regime shapes of track_frame
+    score_grid: int = 512
     order: int = 1
 
     def c(self) -> pf_batch_plan:

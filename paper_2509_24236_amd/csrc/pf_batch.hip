@@ -117,15 +117,20 @@ __global__ __launch_bounds__(256) void kb_next(const BatchProb* tab, const int4*
     next_step<FMT, FIRST>(P.st, P.K, P.G[phase], draw, P.poses, P.recs, w.y);
 }
 
-template <int FMT, int LAYOUT, int TK>
-__global__ __launch_bounds__(256) void kb_score(const BatchProb* tab, const int4* items, int n_items, int phase) {
+// Persistent over the (problem, pose group) items. With regime >= 0 only the items of problems
+// whose particles are in that spread regime are scored (the automatic plan launches one shape per
+// regime, as track_frame does); the others are skipped at the cost of one state read.
+template <int FMT, int LAYOUT, int TK, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void kb_score(const BatchProb* tab, const int4* items, int n_items, int phase,
+                                                  int regime) {
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int4 w = items[it];
         const BatchProb& P = tab[w.x];
+        if (regime >= 0 && spread_regime(P.st, P.vv.inv_vs) != regime) continue;
         const float *x, *y, *z;
         const int* nd;
         view_of(P, phase, x, y, z, nd);
-        score_step<FMT, LAYOUT, TK, 256>(P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv);
+        score_step<FMT, LAYOUT, TK, BLOCK>(P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv);
     }
 }
 
@@ -275,9 +280,10 @@ struct pf_batch {
     BatchProb* tab = nullptr;
     pf_track_state* init = nullptr;
     int4* items = nullptr;                  // all lists, back to back
-    size_t off_bp = 0, off_view = 0, off_next = 0, off_score = 0, off_fin = 0, off_adv[3] = {0, 0, 0};
+    size_t off_bp = 0, off_view = 0, off_next = 0, off_score = 0, off_score2 = 0, off_fin = 0, off_adv[3] = {0, 0, 0};
     size_t off_grad = 0, off_pp = 0;
-    int n_bp = 0, n_view = 0, n_next = 0, n_score = 0, n_fin = 0, n_adv[3] = {0, 0, 0}, n_grad = 0, n_pp = 0;
+    int n_bp = 0, n_view = 0, n_next = 0, n_score = 0, n_score2 = 0, n_fin = 0, n_adv[3] = {0, 0, 0}, n_grad = 0,
+        n_pp = 0;
     std::vector<BatchProb> host;
     std::vector<int> min_valid;
 };
@@ -289,8 +295,21 @@ size_t table_bytes(int n) { return al(sizeof(BatchProb) * n) + al(sizeof(pf_trac
 template <int FMT, int LAYOUT, int TK>
 void launch_score_batch(pf_batch* b, int phase, hipStream_t s) {
     const int grid = std::min(b->plan.score_grid, b->n_score);
-    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, TK>), dim3(grid), dim3(256), 0, s, b->tab, b->items + b->off_score,
-                       b->n_score, phase);
+    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, TK, 256>), dim3(grid), dim3(256), 0, s, b->tab,
+                       b->items + b->off_score, b->n_score, phase, -1);
+}
+
+// The automatic plan: the three regime shapes of track_frame (2x64, 4x128, 4x256), each persistent
+// over its own item list and scoring only the problems in its regime.
+template <int FMT, int LAYOUT>
+void launch_score_batch_auto(pf_batch* b, int phase, hipStream_t s) {
+    const int g2 = std::min(b->plan.score_grid * 4, b->n_score2), g4 = std::min(b->plan.score_grid, b->n_score);
+    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 2, 64>), dim3(g2), dim3(64), 0, s, b->tab, b->items + b->off_score2,
+                       b->n_score2, phase, 0);
+    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 4, 128>), dim3(g4), dim3(128), 0, s, b->tab, b->items + b->off_score,
+                       b->n_score, phase, 1);
+    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 4, 256>), dim3(g4), dim3(256), 0, s, b->tab, b->items + b->off_score,
+                       b->n_score, phase, 2);
 }
 
 template <int FMT, int LAYOUT>
@@ -307,6 +326,7 @@ int32_t run_t(pf_batch* b, hipStream_t s) {
     for (int i = 1; i <= b->n_iters; ++i) {
         const int ph = (i - 1) % b->n_rates;
         switch (b->plan.score_tk) {
+            case 0: launch_score_batch_auto<FMT, LAYOUT>(b, ph, s); break;
             case 1: launch_score_batch<FMT, LAYOUT, 1>(b, ph, s); break;
             case 2: launch_score_batch<FMT, LAYOUT, 2>(b, ph, s); break;
             case 8: launch_score_batch<FMT, LAYOUT, 8>(b, ph, s); break;
@@ -365,8 +385,9 @@ pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const 
         set_error(PF_EINVAL, "track_batch_create: null argument or n < 1");
         return nullptr;
     }
-    if (plan->score_tk != 1 && plan->score_tk != 2 && plan->score_tk != 4 && plan->score_tk != 8) {
-        set_error(PF_EINVAL, "track_batch_create: score_tk %d not in {1, 2, 4, 8}", plan->score_tk);
+    if (plan->score_tk != 0 && plan->score_tk != 1 && plan->score_tk != 2 && plan->score_tk != 4 &&
+        plan->score_tk != 8) {
+        set_error(PF_EINVAL, "track_batch_create: score_tk %d not in {0, 1, 2, 4, 8}", plan->score_tk);
         return nullptr;
     }
     if (plan->score_grid < 1 || plan->reserved != 0 || (plan->order != 0 && plan->order != 1)) {
@@ -497,10 +518,15 @@ pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const 
         for (int k = 0; k < (b->host[p].K + 1 + 255) / 256; ++k) items.push_back(make_int4(p, k, 0, 0));
     b->n_next = (int)(items.size() - b->off_next);
     mark(b->off_score);
-    const int tk = plan->score_tk;
+    const int tk = plan->score_tk == 0 ? 4 : plan->score_tk;
     for (int p : order)
         for (int g = 0; g < (b->host[p].K + 1 + tk - 1) / tk; ++g) items.push_back(make_int4(p, g, 0, 0));
     b->n_score = (int)(items.size() - b->off_score);
+    mark(b->off_score2);   // the automatic plan's 2-pose groups
+    if (plan->score_tk == 0)
+        for (int p : order)
+            for (int g = 0; g < (b->host[p].K + 1 + 1) / 2; ++g) items.push_back(make_int4(p, g, 0, 0));
+    b->n_score2 = (int)(items.size() - b->off_score2);
     for (int ph = 0; ph < b->n_rates; ++ph) {
         mark(b->off_adv[ph]);
         for (int p = 0; p < n; ++p)

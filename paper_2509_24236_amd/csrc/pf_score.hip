@@ -21,19 +21,6 @@
 namespace pf {
 namespace {
 
-// Spread regime of the particles being scored, from the search size that drew them: the largest
-// displacement of a point 2 m from the rotation centre, in voxels. Wide spreads gather from cells
-// scattered over the band and are bound by L2 misses; tight spreads revisit the same cells and are
-// bound by the vector memory pipeline. Each regime has its own launch shape; the choice changes
-// speed only, since the sums are exact.
-constexpr double kSpreadLever = 2.0;                       // metres
-constexpr double kSpreadWide = 2.0, kSpreadTight = 0.25;   // voxels
-
-__device__ inline int spread_regime(const pf_track_state* st, double inv_vs) {
-    const double d = (st->s_rad * kSpreadLever + st->s_m) * inv_vs;
-    return d > kSpreadWide ? 0 : (d > kSpreadTight ? 1 : 2);
-}
-
 // With an optimizer state, the launch returns at once when the stop rule has ended the
 // optimization, or when `regime` >= 0 and the particles' spread is in another regime.
 template <int FMT, int LAYOUT, int TK, int BLOCK>
@@ -41,7 +28,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(VolView vv, const float* __rest
                                                  const float* __restrict__ pz, int n_host, const int* __restrict__ n_dev,
                                                  const float* __restrict__ poses, int K, float* __restrict__ fitness,
                                                  int* __restrict__ n_valid, const pf_track_state* st, int regime) {
-    if (st && (st->done || (regime >= 0 && spread_regime(st, (double)vv.inv_vs) != regime))) return;
+    if (st && (st->done || (regime >= 0 && spread_regime(st, vv.inv_vs) != regime))) return;
     score_step<FMT, LAYOUT, TK, BLOCK>(vv, px, py, pz, n_dev ? *n_dev : n_host, poses, K, blockIdx.x * TK, fitness,
                                        n_valid);
 }
@@ -136,9 +123,6 @@ int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int
     });
 }
 
-int spread_regime_of(double s_rad, double s_m, float inv_vs) {
-    const double d = (s_rad * kSpreadLever + s_m) * (double)inv_vs;
-    return d > kSpreadWide ? 0 : (d > kSpreadTight ? 1 : 2);
-}
+int spread_regime_of(double s_rad, double s_m, float inv_vs) { return spread_regime_sm(s_rad, s_m, inv_vs); }
 
 }  // namespace pf

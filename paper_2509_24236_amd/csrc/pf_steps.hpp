@@ -478,6 +478,24 @@ __device__ inline void next_step(pf_track_state* st, int K, int n_partials, int 
 
 int n_partials_for(int cap);
 
+// ------------------------------------------------------------------ spread regimes
+// Spread regime of the particles being scored, from the search size that drew them: the largest
+// displacement of a point 2 m from the rotation centre, in voxels. Wide spreads gather from cells
+// scattered over the band and are bound by L2 misses; tight spreads revisit the same cells and are
+// bound by the vector ALUs. Each regime has its own launch shape; the choice changes speed only,
+// since the sums are exact.
+constexpr double kSpreadLever = 2.0;                       // metres
+constexpr double kSpreadWide = 2.0, kSpreadTight = 0.25;   // voxels
+
+__host__ __device__ inline int spread_regime_sm(double s_rad, double s_m, float inv_vs) {
+    const double d = (s_rad * kSpreadLever + s_m) * (double)inv_vs;
+    return d > kSpreadWide ? 0 : (d > kSpreadTight ? 1 : 2);
+}
+
+__device__ inline int spread_regime(const pf_track_state* st, float inv_vs) {
+    return spread_regime_sm(st->s_rad, st->s_m, inv_vs);
+}
+
 // ------------------------------------------------------------------ particle scoring
 // Workgroup of BLOCK threads scoring poses k0 .. k0+TK-1 over all n points: every lane keeps a
 // point in registers and evaluates it against the TK poses (uniform, in scalar registers). The

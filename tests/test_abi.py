@@ -215,11 +215,12 @@ def test_batch_validation(pf):
                              C.c_size_t(1 << 30), None)
     assert not h and "differs" in pf.last_error()
     q[1].params.polish_steps = 0
-    bad = pf.pf_batch_plan(3, 1024, 0, 0)
-    h = L.track_batch_create(q, 2, C.byref(bad), C.c_void_p(0x6000), C.c_size_t(1 << 30), None)
-    assert not h and "score_tk" in pf.last_error()
+    for tk in (3, -1, 16):                     # 0 (automatic) and 1, 2, 4, 8 are the plans
+        bad = pf.pf_batch_plan(tk, 1024, 0, 0)
+        h = L.track_batch_create(q, 2, C.byref(bad), C.c_void_p(0x6000), C.c_size_t(1 << 30), None)
+        assert not h and "score_tk" in pf.last_error()
     q[1].params.n_iters = 5                    # all problems must share n_iters
-    ok = pf.pf_batch_plan(4, 1024, 1, 0)
+    ok = pf.pf_batch_plan(0, 1024, 1, 0)
     h = L.track_batch_create(q, 2, C.byref(ok), C.c_void_p(0x6000), C.c_size_t(1 << 30), None)
     assert not h and "differs" in pf.last_error()
     assert L.track_batch_run(None, None) == pf.PF_EINVAL

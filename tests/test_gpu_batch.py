@@ -55,7 +55,7 @@ def same(a, b):
         assert s1.E_final == s2.E_final and s1.n_valid_final == s2.n_valid_final and s1.n_points == s2.n_points
 
 
-@pytest.mark.parametrize("tk,grid,order", [(4, 1024, 1), (1, 512, 0), (8, 4096, 1), (2, 2048, 0)])
+@pytest.mark.parametrize("tk,grid,order", [(0, 1024, 1), (4, 1024, 1), (1, 512, 0), (8, 4096, 1), (2, 2048, 0)])
 def test_batch_equals_plain(pf, problems, tk, grid, order):
     say(f"[batch] plan tk={tk} grid={grid} order={order}")
     ref = plain(pf, problems)
@@ -84,7 +84,7 @@ def test_batch_polish_equals_plain(pf, problems):
 
 def test_batch_graph_replay(pf, problems):
     say("[batch] HIP graph capture and replay")
-    b = pf.Batch(problems, pf.BatchPlan(4, 1024, 1))
+    b = pf.Batch(problems, pf.BatchPlan(0, 1024, 1))
     b.run()
     eager = b.results()
     s = torch.cuda.Stream()

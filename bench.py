@@ -225,8 +225,10 @@ def bench_regimes(args):
     """Scoring kernel alone across the spread regimes of one frame's optimization: 3073 poses drawn
     in a box of +-s around the true pose of frame 1 (s = 10, 1, 0.1, 0.001 deg with s/100 m), scored
     on the rate-1/8 view (in track_frame's tiled order) against the 512^3 FP32 volume holding frame
-    0, with the launch shape the automatic mode uses for that spread. Prints one JSON line; for counter runs (rocprofv3 --pmc),
-    every regime is launched 1 + args.steps times in order."""
+    0, with the launch track_frame's automatic mode uses for that spread (4 poses x 256 threads,
+    through the cell-validity mask with compaction at the three spreads above a quarter voxel).
+    Prints one JSON line; for counter runs
+    (rocprofv3 --pmc), every regime is launched 1 + args.steps times in order."""
     import numpy as np
     import torch
     import paper_2509_24236_amd as pf
@@ -250,13 +252,15 @@ def bench_regimes(args):
     rng = np.random.default_rng(0)
     out = {"workload": "particles_score, 3073 poses x rate-1/8 view of frame 1 (%d points), 512^3 f32 cells"
                        % x.numel(), "regimes": []}
-    for s_deg, shape in [(10.0, (2, 64)), (1.0, (2, 64)), (0.1, (4, 128)), (0.001, (4, 256))]:
+    for s_deg, shape, mask in [(10.0, (4, 256), True), (1.0, (4, 256), True), (0.1, (4, 256), True),
+                               (0.001, (4, 256), False)]:
         poses = [(Rg, tg)]
         for _ in range(3072):
             r = rng.uniform(-1, 1, 3) * math.radians(s_deg)
             poses.append((synth.rot(r) @ Rg, tg + rng.uniform(-1, 1, 3) * s_deg / 100.0))
         P = torch.as_tensor(pf.poses_to_f32(poses)).to(dev)
         pf.score_config(*shape)
+        pf.score_mask(pf.MASK_ALWAYS if mask else pf.MASK_NEVER)
         E, nv = pf.particles_score(vol, x, y, z, P)
         torch.cuda.synchronize()
         ts = []
@@ -269,10 +273,12 @@ def bench_regimes(args):
             ts.append(e0.elapsed_time(e1))
         ms = sorted(ts)[len(ts) // 2]
         ev = 3073 * x.numel()
-        out["regimes"].append({"spread_deg": s_deg, "shape": list(shape), "ms": ms, "evals_per_s": ev / ms * 1e3,
-                               "algorithmic_GBps": BYTES_PER_EVAL * ev / ms / 1e6})
-        log(f"[regimes] spread {s_deg} deg, shape {shape}: {ms:.4f} ms, {ev / ms / 1e6:.1f} Gevals/s")
+        out["regimes"].append({"spread_deg": s_deg, "shape": list(shape), "mask": mask, "ms": ms,
+                               "evals_per_s": ev / ms * 1e3, "algorithmic_GBps": BYTES_PER_EVAL * ev / ms / 1e6,
+                               "valid_fraction": float(nv.sum().item()) / ev})
+        log(f"[regimes] spread {s_deg} deg, shape {shape}, mask {mask}: {ms:.4f} ms, {ev / ms / 1e6:.1f} Gevals/s")
     pf.score_config(0, 0)
+    pf.score_mask(pf.MASK_BY_SPREAD)
     print(json.dumps(out), flush=True)
 
 
@@ -779,14 +785,15 @@ def main():
             "particles": K if args.schedule == "fixed" else [1024, 3072, 10240],
             "iterations": I,
             "mean_iterations_run": sum(iters_run) / max(1, len(iters_run)),
-            "tsdf": "512^3 f32 T + f32 W, cell-major f32 replica for scoring",
+            "tsdf": "512^3 f32 T + f32 W, cell-major f32 replica and cell-validity mask for scoring",
             "fusion_ms_per_frame": fuse_ms,
             "volume_bytes": vol_bytes,
         },
         "roofline": {
             "bound": "hbm",
             "kernel": "particles_score per iteration: k_score<f32, cells> in the shape of the particles' spread "
-                      "regime (2x64, 4x128 or 4x256 poses x threads), forecast from the previous frame",
+                      "regime (4 poses x 256 threads; through the cell-validity mask with compaction while the "
+                      "particles are spread over more than a quarter voxel), forecast from the previous frame",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -809,7 +816,7 @@ def main():
                      f"per-brick cell blocks; {spec.nx}x{spec.ny}x{spec.nz} grid ({spec.nx * spec.ny * spec.nz / 1e6:.1f}M "
                      f"voxels), {used * 512 / (spec.nx * spec.ny * spec.nz):.1%} of them stored")
         c["bricks_used"] = used
-        out["roofline"]["kernel"] = out["roofline"]["kernel"].replace("<f32, cells>", "<f32, bricks>")
+        out["roofline"]["kernel"] = ("particles_score per iteration: k_score<f32, bricks>, 4 poses x 256 threads")
         out["roofline"]["traffic"] = out["roofline"]["traffic_bytes_per_launch"] = None
         log(f"[bench] bricks {used}, fusion {fuse_ms:.3f} ms/frame, volume {vol_bytes / 2**30:.2f} GiB")
     if not args.no_cpu_baseline:

@@ -57,7 +57,15 @@ extern "C" {
  *         tsdf_integrate (which rewrites only the cells of voxels whose stored value changed),
  *         except that in the FP32 and FP16 formats a corner outside the band (|T| >= 1, the +1
  *         sentinel included) is stored as NaN: the interpolated value of a sample is then NaN
- *         exactly when the sample is not valid, which replaces eight corner tests by one. */
+ *         exactly when the sample is not valid, which replaces eight corner tests by one.
+ *         After the replica (at tsdf_mask_offset()) a cell-validity mask: one uint64 word per
+ *         block of 4x4x4 cells, word ((k/4)*mwy + j/4)*mwx + i/4 with mwx = ceil((nx-1)/4),
+ *         mwy = ceil((ny-1)/4), mwz = ceil((nz-1)/4), whose bit (i%4) + 4(j%4) + 16(k%4) is set
+ *         iff all 8 corners of cell (i, j, k) are in the band; then one byte per word (at
+ *         tsdf_mask_offset() + 8*mwx*mwy*mwz rounded up to 256) that is 0 between calls.
+ *         Scoring reads the mask before the replica while the particles are widely spread, where
+ *         most samples miss the band. The same three calls keep it equal to the replica: fusion
+ *         flags the words of voxels that enter or leave the band and rebuilds exactly those. */
 /* BRICKS: a sparse volume for scenes larger than a dense grid affords (nx, ny, nz multiples of 8).
  *         Bricks of 8x8x8 voxels live in a pool of max_bricks slots behind a dense brick-index
  *         grid (one int32 per brick: its slot, or -1); there is no hash table. The T buffer holds,
@@ -205,6 +213,9 @@ size_t tsdf_bytes(const pf_tsdf* v, size_t* weight_bytes);
 /* Byte offset of the cell-major replica inside v->tsdf (PF_LAYOUT_CELLS), 0 otherwise. */
 size_t tsdf_cells_offset(const pf_tsdf* v);
 
+/* Byte offset of the cell-validity mask inside v->tsdf (PF_LAYOUT_CELLS), 0 otherwise. */
+size_t tsdf_mask_offset(const pf_tsdf* v);
+
 /* BRICKS: byte offsets inside v->tsdf of the index grid, the slot coordinates, the slots' T and
  * their cells (each may be NULL); returns PF_EINVAL for another layout or a bad description. */
 int32_t tsdf_brick_offsets(const pf_tsdf* v, size_t* index, size_t* coords, size_t* pool_t, size_t* pool_cells);
@@ -285,12 +296,27 @@ int32_t particles_score_grad(const pf_tsdf* v, const float* px, const float* py,
 
 /* Launch shape of the scoring launches with more than 64 poses (particles_score and
  * track_frame): poses per workgroup (1, 2, 4, 8) and workgroup size (64, 128, 256, 512; 1 pose
- * needs >= 256), or 0 and 0 (the default) for the automatic shape: track_frame then picks the shape
- * of every iteration on the device from the spread of the search size that drew its particles,
- * and particles_score uses 4 poses x 256 threads. Process-wide. Fitness sums are exact (64-bit
- * fixed point), so every shape, and the batched path, gives bitwise identical results; the shape
- * changes speed only. Returns PF_EINVAL for an unsupported shape. */
+ * needs >= 256), or 0 and 0 (the default) for the automatic shape, 4 poses x 256 threads (fewer
+ * poses per workgroup when K is too small to fill the GPU); track_frame then also picks, per
+ * iteration, the launch of the spread regime of the search size that drew its particles (see
+ * pf_score_mask). Process-wide. Fitness sums are exact (64-bit fixed point), so every shape, and
+ * the batched path, gives bitwise identical results; the shape changes speed only. Returns
+ * PF_EINVAL for an unsupported shape. */
 int32_t pf_score_config(int32_t poses_per_group, int32_t group_size);
+
+/* When the scoring launches of particles_score and track_frame read a CELLS volume's replica
+ * through its cell-validity mask: PF_MASK_BY_SPREAD (the default: the automatic launches of
+ * track_frame while the particles are spread over more than a quarter voxel, where many samples
+ * miss the band; never in particles_score, which has no spread, nor with a configured shape),
+ * PF_MASK_ALWAYS (every launch, configured shapes included) or PF_MASK_NEVER. A launch that reads
+ * the mask gathers and interpolates only the valid samples, compacted into full waves. Other
+ * layouts have no mask; the batched path reads it by spread whatever the mode. Process-wide. The
+ * mask bit of a cell equals the replica's validity, so results are bitwise identical in every mode;
+ * the mode changes speed only. Returns PF_EINVAL for another value. */
+#define PF_MASK_BY_SPREAD 0
+#define PF_MASK_ALWAYS 1
+#define PF_MASK_NEVER 2
+int32_t pf_score_mask(int32_t mode);
 
 /* Bytes of the device state buffer for K particles (pf_track_state + (K+1)*6 doubles). */
 size_t particles_state_bytes(int32_t K);
@@ -360,11 +386,9 @@ typedef struct pf_batch_problem {
 
 /* Launch plan of a batch (the project autotuner chooses it per shape class). */
 typedef struct pf_batch_plan {
-    int32_t score_tk;        /* poses per scoring workgroup: 1, 2, 4 or 8; or 0, the shapes of
-                                track_frame by spread regime (2x64, 4x128, 4x256 poses x threads), one
-                                persistent launch each over the problems in that regime */
-    int32_t score_grid;      /* workgroups of the persistent scoring launch (x4 for the 64-thread
-                                shape), >= 1 */
+    int32_t score_tk;        /* poses per scoring workgroup of 256 threads: 1, 2, 4 or 8; or 0,
+                                track_frame's automatic shape (4) */
+    int32_t score_grid;      /* workgroups of the persistent scoring launch, >= 1 */
     int32_t order;           /* 0: items in problem order; 1: problems with most points first */
     int32_t reserved;        /* must be 0 */
 } pf_batch_plan;

@@ -88,8 +88,8 @@ class pf_batch_plan(C.Structure):
 
 
 # every symbol include/profusion.h declares
-EXPORTS = ("pf_last_error", "tsdf_bytes", "tsdf_cells_offset", "tsdf_brick_offsets", "tsdf_bricks_used", "tsdf_init", "tsdf_integrate", "tsdf_export_linear", "tsdf_import_linear",
-           "backproject", "particles_score", "particles_score_grad", "pf_score_config", "particles_state_bytes", "particles_state_init", "particles_update",
+EXPORTS = ("pf_last_error", "tsdf_bytes", "tsdf_cells_offset", "tsdf_mask_offset", "tsdf_brick_offsets", "tsdf_bricks_used", "tsdf_init", "tsdf_integrate", "tsdf_export_linear", "tsdf_import_linear",
+           "backproject", "particles_score", "particles_score_grad", "pf_score_config", "pf_score_mask", "particles_state_bytes", "particles_state_init", "particles_update",
            "track_workspace_bytes", "track_frame", "track_batch_workspace_bytes", "track_batch_create",
            "track_batch_run", "track_batch_results", "track_batch_destroy", "pf_timing_enable", "pf_timing_read")
 
@@ -111,6 +111,8 @@ def lib() -> C.CDLL:
     L.tsdf_bytes.argtypes = [P(pf_tsdf), P(C.c_size_t)]
     L.tsdf_cells_offset.restype = C.c_size_t
     L.tsdf_cells_offset.argtypes = [P(pf_tsdf)]
+    L.tsdf_mask_offset.restype = C.c_size_t
+    L.tsdf_mask_offset.argtypes = [P(pf_tsdf)]
     L.tsdf_brick_offsets.argtypes = [P(pf_tsdf), P(C.c_size_t), P(C.c_size_t), P(C.c_size_t), P(C.c_size_t)]
     L.tsdf_bricks_used.argtypes = [P(pf_tsdf), P(C.c_int32), P(C.c_int32), vp]
     for name in ("tsdf_init",):
@@ -122,6 +124,7 @@ def lib() -> C.CDLL:
     L.particles_score.argtypes = [P(pf_tsdf), vp, vp, vp, i32, vp, i32, vp, vp, vp]
     L.particles_score_grad.argtypes = [P(pf_tsdf), vp, vp, vp, i32, vp, vp, i32, i32, vp, vp, vp, vp]
     L.pf_score_config.argtypes = [i32, i32]
+    L.pf_score_mask.argtypes = [i32]
     L.particles_state_bytes.restype = C.c_size_t
     L.particles_state_bytes.argtypes = [i32]
     L.particles_state_init.argtypes = [vp, P(pf_pose), P(pf_track_params), vp, vp]
@@ -281,6 +284,19 @@ class Tsdf:
         _check(lib().tsdf_brick_offsets(C.byref(self.desc), *[C.byref(x) for x in o]))
         return tuple(int(x.value) for x in o)
 
+    def cell_mask(self):
+        """CELLS: the cell-validity mask words, (mwz, mwy, mwx) int64 (a view of the T buffer), and the
+        per-word flag bytes (all 0 between calls)."""
+        torch = _torch()
+        off = lib().tsdf_mask_offset(C.byref(self.desc))
+        if self.layout != LAYOUT_CELLS or off == 0:
+            raise PFError(PF_EINVAL, "cell_mask: not a CELLS volume")
+        m = [(n - 1 + 3) // 4 for n in (self.spec.nz, self.spec.ny, self.spec.nx)]
+        words = m[0] * m[1] * m[2]
+        raw = self.T.view(torch.uint8)
+        foff = (off + 8 * words + 255) // 256 * 256
+        return raw[off:off + 8 * words].view(torch.int64).view(*m), raw[foff:foff + words].view(*m)
+
     def export_linear(self, with_weight=True, stream=None):
         torch = _torch()
         n = self.spec.nx * self.spec.ny * self.spec.nz
@@ -385,6 +401,14 @@ def score_config(poses_per_group: int = 0, group_size: int = 0):
     _check(lib().pf_score_config(poses_per_group, group_size))
 
 
+MASK_BY_SPREAD, MASK_ALWAYS, MASK_NEVER = 0, 1, 2
+
+
+def score_mask(mode: int = MASK_BY_SPREAD):
+    """When automatic scoring launches read the cell-validity mask (process-wide); speed only."""
+    _check(lib().pf_score_mask(mode))
+
+
 def state_bytes(K: int) -> int:
     return int(lib().particles_state_bytes(K))
 
@@ -468,7 +492,7 @@ def timing_read(reset: bool = False):
 # ----------------------------------------------------------------------------- batches
 @dataclasses.dataclass
 class BatchPlan:
-    score_tk: int = 4        # poses per workgroup (1, 2, 4, 8), or 0: the spread-regime shapes of track_frame
+    score_tk: int = 4        # poses per 256-thread workgroup (1, 2, 4, 8), or 0: track_frame's automatic shape (4)
     score_grid: int = 512
     order: int = 1
 

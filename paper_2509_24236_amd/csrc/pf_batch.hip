@@ -117,20 +117,23 @@ __global__ __launch_bounds__(256) void kb_next(const BatchProb* tab, const int4*
     next_step<FMT, FIRST>(P.st, P.K, P.G[phase], draw, P.poses, P.recs, w.y);
 }
 
-// Persistent over the (problem, pose group) items. With regime >= 0 only the items of problems
-// whose particles are in that spread regime are scored (the automatic plan launches one shape per
-// regime, as track_frame does); the others are skipped at the cost of one state read.
+// Persistent over the (problem, pose group) items. Only the items of problems whose particles are
+// in one of the spread regimes `regimes` (bit r for regime r) are scored (the automatic plan
+// launches one shape per group of regimes, as track_frame does); the others are skipped at the cost
+// of one state read. A problem in a regime of kMaskRegimes reads its replica through the mask.
 template <int FMT, int LAYOUT, int TK, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void kb_score(const BatchProb* tab, const int4* items, int n_items, int phase,
-                                                  int regime) {
+                                                  int regimes) {
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int4 w = items[it];
         const BatchProb& P = tab[w.x];
-        if (regime >= 0 && spread_regime(P.st, P.vv.inv_vs) != regime) continue;
+        const int regime = spread_regime(P.st, P.vv.inv_vs);
+        if (!((regimes >> regime) & 1)) continue;
         const float *x, *y, *z;
         const int* nd;
         view_of(P, phase, x, y, z, nd);
-        score_step<FMT, LAYOUT, TK, BLOCK>(P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv);
+        score_step_regime<FMT, LAYOUT, TK, BLOCK>(P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv,
+                                                  regime);
     }
 }
 
@@ -280,9 +283,9 @@ struct pf_batch {
     BatchProb* tab = nullptr;
     pf_track_state* init = nullptr;
     int4* items = nullptr;                  // all lists, back to back
-    size_t off_bp = 0, off_view = 0, off_next = 0, off_score = 0, off_score2 = 0, off_fin = 0, off_adv[3] = {0, 0, 0};
+    size_t off_bp = 0, off_view = 0, off_next = 0, off_score = 0, off_fin = 0, off_adv[3] = {0, 0, 0};
     size_t off_grad = 0, off_pp = 0;
-    int n_bp = 0, n_view = 0, n_next = 0, n_score = 0, n_score2 = 0, n_fin = 0, n_adv[3] = {0, 0, 0}, n_grad = 0,
+    int n_bp = 0, n_view = 0, n_next = 0, n_score = 0, n_fin = 0, n_adv[3] = {0, 0, 0}, n_grad = 0,
         n_pp = 0;
     std::vector<BatchProb> host;
     std::vector<int> min_valid;
@@ -296,20 +299,16 @@ template <int FMT, int LAYOUT, int TK>
 void launch_score_batch(pf_batch* b, int phase, hipStream_t s) {
     const int grid = std::min(b->plan.score_grid, b->n_score);
     hipLaunchKernelGGL((kb_score<FMT, LAYOUT, TK, 256>), dim3(grid), dim3(256), 0, s, b->tab,
-                       b->items + b->off_score, b->n_score, phase, -1);
+                       b->items + b->off_score, b->n_score, phase, (1 << kRegimes) - 1);
 }
 
-// The automatic plan: the three regime shapes of track_frame (2x64, 4x128, 4x256), each persistent
-// over its own item list and scoring only the problems in its regime.
+// The automatic plan: track_frame's shape (4 poses x 256 threads in both spread regimes), persistent
+// over the item list.
 template <int FMT, int LAYOUT>
 void launch_score_batch_auto(pf_batch* b, int phase, hipStream_t s) {
-    const int g2 = std::min(b->plan.score_grid * 4, b->n_score2), g4 = std::min(b->plan.score_grid, b->n_score);
-    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 2, 64>), dim3(g2), dim3(64), 0, s, b->tab, b->items + b->off_score2,
-                       b->n_score2, phase, 0);
-    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 4, 128>), dim3(g4), dim3(128), 0, s, b->tab, b->items + b->off_score,
-                       b->n_score, phase, 1);
-    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 4, 256>), dim3(g4), dim3(256), 0, s, b->tab, b->items + b->off_score,
-                       b->n_score, phase, 2);
+    const int g = std::min(b->plan.score_grid, b->n_score);
+    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 4, 256>), dim3(g), dim3(256), 0, s, b->tab, b->items + b->off_score,
+                       b->n_score, phase, (1 << kRegimes) - 1);
 }
 
 template <int FMT, int LAYOUT>
@@ -522,11 +521,6 @@ pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const 
     for (int p : order)
         for (int g = 0; g < (b->host[p].K + 1 + tk - 1) / tk; ++g) items.push_back(make_int4(p, g, 0, 0));
     b->n_score = (int)(items.size() - b->off_score);
-    mark(b->off_score2);   // the automatic plan's 2-pose groups
-    if (plan->score_tk == 0)
-        for (int p : order)
-            for (int g = 0; g < (b->host[p].K + 1 + 1) / 2; ++g) items.push_back(make_int4(p, g, 0, 0));
-    b->n_score2 = (int)(items.size() - b->off_score2);
     for (int ph = 0; ph < b->n_rates; ++ph) {
         mark(b->off_adv[ph]);
         for (int p = 0; p < n; ++p)

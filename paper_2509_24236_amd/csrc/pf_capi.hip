@@ -21,6 +21,7 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
               hipStream_t s);
 int32_t timing_enable(int on);
 int32_t score_config(int tk, int block);
+int32_t score_mask(int mode);
 int32_t timing_read(double* ms, int64_t* launches, int64_t* evals, int reset);
 
 namespace {
@@ -51,6 +52,19 @@ size_t cells_offset_bytes(const pf_tsdf* v) {
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+CellMask cell_mask_layout(const pf_tsdf* v) {
+    CellMask M;
+    M.mwx = (v->nx - 1 + 3) / 4;
+    M.mwy = (v->ny - 1 + 3) / 4;
+    M.mwz = (v->nz - 1 + 3) / 4;
+    M.words = (size_t)M.mwx * M.mwy * M.mwz;
+    const size_t cells = (size_t)(v->nx - 1) * (v->ny - 1) * (v->nz - 1);
+    M.mask = al256(cells_offset_bytes(v) + cells * 8 * t_elem_bytes(v->format));
+    M.flags = al256(M.mask + M.words * sizeof(unsigned long long));
+    M.t_total = al256(M.flags + M.words);
+    return M;
+}
+
 BrickLayout brick_layout(const pf_tsdf* v) {
     BrickLayout L;
     L.nbx = v->nx / kBrickEdge;
@@ -74,6 +88,14 @@ VolView make_view(const pf_tsdf* v) {
     vv.ones = nullptr;
     vv.nbx = vv.nby = 0;
     vv.cells = v->layout == PF_LAYOUT_CELLS ? static_cast<const char*>(v->tsdf) + cells_offset_bytes(v) : nullptr;
+    vv.mask = nullptr;
+    vv.mwx = vv.mwy = 0;
+    if (v->layout == PF_LAYOUT_CELLS) {
+        const CellMask M = cell_mask_layout(v);
+        vv.mask = reinterpret_cast<const unsigned long long*>(static_cast<const char*>(v->tsdf) + M.mask);
+        vv.mwx = M.mwx;
+        vv.mwy = M.mwy;
+    }
     if (v->layout == PF_LAYOUT_BRICKS) {
         const BrickLayout L = brick_layout(v);
         const char* base = static_cast<const char*>(v->tsdf);
@@ -235,13 +257,17 @@ size_t tsdf_bytes(const pf_tsdf* v, size_t* weight_bytes) {
     const size_t tb = t_elem_bytes(v->format), wb = v->format == PF_F32_W_F32 ? 4 : 1;
     if (weight_bytes) *weight_bytes = (size_t)n * wb;
     if (v->layout == PF_LAYOUT_LINEAR) return (size_t)n * tb;
-    const size_t cells = (size_t)(v->nx - 1) * (v->ny - 1) * (v->nz - 1);
-    return cells_offset_bytes(v) + cells * 8 * tb;
+    return cell_mask_layout(v).t_total;
 }
 
 size_t tsdf_cells_offset(const pf_tsdf* v) {
     if (!v || tsdf_bytes(v, nullptr) == 0) return 0;
     return cells_offset_bytes(v);
+}
+
+size_t tsdf_mask_offset(const pf_tsdf* v) {
+    if (!v || v->layout != PF_LAYOUT_CELLS || tsdf_bytes(v, nullptr) == 0) return 0;
+    return cell_mask_layout(v).mask;
 }
 
 int32_t tsdf_brick_offsets(const pf_tsdf* v, size_t* index, size_t* coords, size_t* pool_t, size_t* pool_cells) {
@@ -345,6 +371,8 @@ int32_t particles_score_grad(const pf_tsdf* v, const float* px, const float* py,
 int32_t pf_score_config(int32_t poses_per_group, int32_t group_size) {
     return score_config(poses_per_group, group_size);
 }
+
+int32_t pf_score_mask(int32_t mode) { return score_mask(mode); }
 
 size_t particles_state_bytes(int32_t K) {
     if (K < 1 || K > PF_MAX_K) return 0;

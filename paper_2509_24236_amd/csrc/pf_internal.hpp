@@ -90,6 +90,8 @@ struct VolView {
     const void* T;       // x-fastest storage (dense layouts) or the slots' T (BRICKS)
     const void* cells;   // cell-major replica (PF_LAYOUT_CELLS) or the slots' cells (BRICKS), else nullptr
     const int* bindex;   // BRICKS: brick-index grid, else nullptr
+    const unsigned long long* mask;   // CELLS: cell-validity words (4x4x4 cells each), else nullptr
+    int mwx, mwy;        // CELLS: mask words along x and y
     const void* ones;    // BRICKS: one cell block of +1 (read for cells of bricks without a slot)
     int nbx, nby;        // BRICKS: bricks along x and y
     int nx, ny, nz, format, layout;
@@ -98,6 +100,18 @@ struct VolView {
 };
 
 VolView make_view(const pf_tsdf* v);
+
+// Cell-validity mask of a CELLS T buffer: after the replica, one 64-bit word per block of 4x4x4
+// cells (bit (x&3) + 4 (y&3) + 16 (z&3) of word ((z/4) mwy + y/4) mwx + x/4 is set iff all 8
+// corners of cell (x, y, z) are in the band), then one byte per word that fusion sets when a
+// voxel of the word's cells enters or leaves the band (the word is rebuilt and the byte cleared
+// right after).
+struct CellMask {
+    int mwx, mwy, mwz;
+    size_t words;
+    size_t mask, flags, t_total;   // byte offsets from v->tsdf, and the whole T buffer (a multiple of 256)
+};
+CellMask cell_mask_layout(const pf_tsdf* v);
 
 // Byte layout of a BRICKS T buffer (offsets from v->tsdf) and of its W buffer.
 constexpr int kBrickEdge = 8, kBrickVox = 512;

@@ -123,10 +123,18 @@ struct Gather<FMT, PF_LAYOUT_CELLS> {
     using ST = typename Fmt<FMT>::T;
     const ST* __restrict__ C;   // cells
     int cnx, cnxy;              // (nx-1), (nx-1)*(ny-1)
+    const unsigned long long* __restrict__ M;   // cell-validity mask: one word per 4x4x4 cells
+    int mwx, mwxy;
     __device__ inline const ST* addr(int cx, int cy, int cz) const {
         return C + ((size_t)((cz * cnxy) + cy * cnx + cx) << 3);
     }
     __device__ inline void load(const ST* p, float (&c)[8]) const { load_cell8<FMT>(p, c); }
+    __device__ inline const unsigned long long* mask_word(int cx, int cy, int cz) const {
+        return M + ((cz >> 2) * mwxy + (cy >> 2) * mwx + (cx >> 2));
+    }
+    __device__ static inline unsigned mask_bit(int cx, int cy, int cz) {
+        return (unsigned)((cx & 3) | ((cy & 3) << 2) | ((cz & 3) << 4));
+    }
 };
 
 // Sparse bricks: the brick-index grid names the slot of the cell's 8x8x8 brick, whose cell
@@ -174,15 +182,33 @@ __device__ inline int floor_to_int(float x) {
     return r;
 }
 
+// Trilinear interpolation of the 8 corners (order as in Gather) at fractions (f0, f1, f2): lerps
+// along x, then y, then z, each as one fused multiply-add.
+__device__ inline float trilerp(float f0, float f1, float f2, const float (&c)[8]) {
+    const float a00 = fmaf(f0, c[1] - c[0], c[0]);
+    const float a10 = fmaf(f0, c[3] - c[2], c[2]);
+    const float a01 = fmaf(f0, c[5] - c[4], c[4]);
+    const float a11 = fmaf(f0, c[7] - c[6], c[6]);
+    const float b0 = fmaf(f1, a10 - a00, a00);
+    const float b1 = fmaf(f1, a11 - a01, a01);
+    return fmaf(f2, b1 - b0, b0);
+}
+
 // Evaluates one point (already divided by the voxel size) against NP poses in three phases:
 // the cell of every pose, then all gathers, then validity and interpolation, so that the gathers
 // of all poses are in flight together. The cell is clamped into the grid so every gather is in
 // bounds, and an out-of-grid sample is rejected afterwards. Adds |value| (fixed point) and 1 to
 // (sum[j], cnt[j]) for every valid sample.
-template <int FMT, int LAYOUT, int NP>
+//
+// MASK (replica only): the cell-validity mask is read first, in one round of loads for all poses,
+// and a cell block is gathered only for a sample whose cell the mask marks valid; the mask bit
+// then stands in for the value test. Where most samples miss the band (a wide particle spread),
+// this replaces most 32-byte gathers by reads of a mask that is 1/256 of the replica's size.
+template <int FMT, int LAYOUT, int NP, bool MASK = false>
 __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, unsigned ly, unsigned lz,
                                   const GridPose (&g)[NP], float x, float y, float z, FixSum (&sum)[NP],
                                   int (&cnt)[NP]) {
+    static_assert(!MASK || LAYOUT == PF_LAYOUT_CELLS, "the mask exists for the replica only");
     using ST = typename Fmt<FMT>::T;
     const ST* p[NP];
     float f[NP][3];
@@ -239,6 +265,28 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     // keep the phases apart: the scheduler would otherwise interleave them pose by pose and
     // leave only one pose's gathers in flight
     __builtin_amdgcn_sched_barrier(0);
+    // with the mask: whether each sample's cell is valid (a cell outside the grid was clamped onto
+    // the last cell, whose bit may be set; such a sample is still rejected by inb)
+    bool need[NP];
+    if constexpr (MASK) {
+        unsigned long long mw[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) mw[j] = *G.mask_word(cl[j][0], cl[j][1], cl[j][2]);
+        __builtin_amdgcn_sched_barrier(0);
+        // every bit is taken before the first gather is issued (an empty asm statement keeps the
+        // tests out of the gathers' branches): a wait inside them would also wait for the gathers
+        // already in flight
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            unsigned b = (unsigned)(mw[j] >> G.mask_bit(cl[j][0], cl[j][1], cl[j][2])) & 1u;
+            asm volatile("" : "+v"(b));
+            need[j] = b != 0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    } else {
+#pragma unroll
+        for (int j = 0; j < NP; ++j) need[j] = true;
+    }
     // A pose that lands in the same cell as the previous pose reuses its corners instead of
     // gathering them again. Late in an optimization the search size has contracted so far that
     // neighbouring particles sample the same cells almost everywhere, and the loads of a whole
@@ -246,14 +294,16 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     // The copy is made after all gathers were issued: the flag that selects it is passed through
     // an empty asm statement so the compiler cannot fold the copy into the branch, where it would
     // wait for the previous pose's gather before issuing the next one.
+    // (With the mask, a pose in the same cell as the previous one has the same bit, so the block it
+    // copies was gathered whenever it needs one.)
     float c[NP][8];
     int dup[NP];
     dup[0] = 0;
-    G.load(p[0], c[0]);
+    if (need[0]) G.load(p[0], c[0]);
 #pragma unroll
     for (int j = 1; j < NP; ++j) {
         dup[j] = p[j] == p[j - 1] ? 1 : 0;
-        if (!dup[j]) G.load(p[j], c[j]);
+        if (!dup[j] && need[j]) G.load(p[j], c[j]);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -265,21 +315,15 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     }
     // validity: with NaN-marked cells a NaN corner makes every step below NaN, so the value itself
     // says whether all 8 corners are in the band; otherwise each corner is tested
-    constexpr bool kNanTest = LAYOUT != PF_LAYOUT_LINEAR && Fmt<FMT>::nan_cells;
+    constexpr bool kNanTest = !MASK && LAYOUT != PF_LAYOUT_LINEAR && Fmt<FMT>::nan_cells;
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
-        bool ok = inb[j];
-        if constexpr (!kNanTest) {
+        bool ok = inb[j] & need[j];
+        if constexpr (!kNanTest && !MASK) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) ok &= Fmt<FMT>::in_band(c[j][q]);
         }
-        const float a00 = fmaf(f[j][0], c[j][1] - c[j][0], c[j][0]);
-        const float a10 = fmaf(f[j][0], c[j][3] - c[j][2], c[j][2]);
-        const float a01 = fmaf(f[j][0], c[j][5] - c[j][4], c[j][4]);
-        const float a11 = fmaf(f[j][0], c[j][7] - c[j][6], c[j][6]);
-        const float b0 = fmaf(f[j][1], a10 - a00, a00);
-        const float b1 = fmaf(f[j][1], a11 - a01, a01);
-        const float v = fmaf(f[j][2], b1 - b0, b0);
+        const float v = trilerp(f[j][0], f[j][1], f[j][2], c[j]);
         if constexpr (kNanTest) ok &= !__builtin_isnan(v);
         const float a = ok ? fminf(fabsf(v) * Fmt<FMT>::fix, kFixMax) : 0.0f;
         sum[j] += (FixSum)(unsigned)a;
@@ -332,6 +376,9 @@ __host__ __device__ inline Gather<FMT, LAYOUT> make_gather(const VolView& vv) {
         G.C = static_cast<const typename Fmt<FMT>::T*>(vv.cells);
         G.cnx = vv.nx - 1;
         G.cnxy = (vv.nx - 1) * (vv.ny - 1);
+        G.M = vv.mask;
+        G.mwx = vv.mwx;
+        G.mwxy = vv.mwx * vv.mwy;
     } else {
         G.C = static_cast<const typename Fmt<FMT>::T*>(vv.cells);
         G.ones = static_cast<const typename Fmt<FMT>::T*>(vv.ones);

@@ -23,44 +23,65 @@ namespace {
 
 // With an optimizer state, the launch returns at once when the stop rule has ended the
 // optimization, or when `regime` >= 0 and the particles' spread is in another regime.
-template <int FMT, int LAYOUT, int TK, int BLOCK>
+template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK>
 __global__ __launch_bounds__(BLOCK) void k_score(VolView vv, const float* __restrict__ px, const float* __restrict__ py,
                                                  const float* __restrict__ pz, int n_host, const int* __restrict__ n_dev,
                                                  const float* __restrict__ poses, int K, float* __restrict__ fitness,
                                                  int* __restrict__ n_valid, const pf_track_state* st, int regime) {
     if (st && (st->done || (regime >= 0 && spread_regime(st, vv.inv_vs) != regime))) return;
-    score_step<FMT, LAYOUT, TK, BLOCK>(vv, px, py, pz, n_dev ? *n_dev : n_host, poses, K, blockIdx.x * TK, fitness,
-                                       n_valid);
+    score_step<FMT, LAYOUT, TK, BLOCK, MASK>(vv, px, py, pz, n_dev ? *n_dev : n_host, poses, K, blockIdx.x * TK,
+                                             fitness, n_valid);
 }
 
-template <int FMT, int LAYOUT, int TK, int BLOCK>
+template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK = false>
 int32_t launch_t(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
                  const pf_track_state* st, int regime, hipStream_t s) {
     const int blocks = (K + TK - 1) / TK;
-    hipLaunchKernelGGL((k_score<FMT, LAYOUT, TK, BLOCK>), dim3(blocks), dim3(BLOCK), 0, s, vv, p.x, p.y, p.z, p.n,
-                       p.n_dev, poses, K, fitness, n_valid, st, regime);
+    hipLaunchKernelGGL((k_score<FMT, LAYOUT, TK, BLOCK, MASK>), dim3(blocks), dim3(BLOCK), 0, s, vv, p.x, p.y, p.z,
+                       p.n, p.n_dev, poses, K, fitness, n_valid, st, regime);
     return check_launch("particles_score");
 }
+
 
 // Launch shape of the many-pose scoring launches (pf_score_config): poses per workgroup and
 // workgroup size, or 0 and 0 for the shape by spread regime (the default).
 int g_tk = 0, g_block = 0;
 
-// Automatic shape of a regime for K poses: the regime's preferred shape (2x64 wide, 4x128 mid,
-// 4x256 tight, as measured at K = 3073), or, when that launch would hold fewer than one wave per
-// SIMD (1024 on MI355X), the first of 2x256, 1x256, 1x1024 that does: a few hundred poses must
-// spread their points over more waves to fill the chip. Shape codes: 0 = 2x64, 1 = 4x128,
-// 2 = 4x256, 3 = 2x256, 4 = 1x256, 5 = 1x1024.
+// Spread regimes whose automatic launches read the cell-validity mask (pf_score_mask), bit r for
+// regime r; kMaskAlways also masks the launches without a spread (particles_score).
+constexpr int kMaskAlways = 8;
+int g_mask_regimes = kMaskRegimes;
+
+// Automatic shape for K poses: 4x256 (measured at K = 3073: the masked, compacting launch of the
+// spread regime ran the headline sequence at 4.01 ms per frame at 4x256, 4.09 at 2x256, 4.16 at
+// 1x256, 4.33 at 4x128; the tight launch is fastest at 4x256; the unmasked spread launch of the
+// sparse layout ran its sequence at 4.92 ms at 4x256, 5.06 at 4x128, 5.35 at 2x64), or, when that
+// launch would hold fewer than one wave per SIMD (1024 on MI355X), the first of 2x256, 1x256,
+// 1x1024 that does: a few hundred poses must spread their points over more waves to fill the chip.
+// Shape codes: 0 = 4x256, 1 = 2x256, 2 = 1x256, 3 = 1x1024.
 constexpr int kMinWaves = 1024;
 
-int auto_shape(int regime, int K) {
-    static const int tk[6] = {2, 4, 4, 2, 1, 1}, wpg[6] = {1, 2, 4, 4, 4, 16};
-    auto waves = [&](int c) { return (K + tk[c] - 1) / tk[c] * wpg[c]; };
-    const int pref = regime == 0 ? 0 : (regime == 1 ? 1 : 2);
-    if (waves(pref) >= kMinWaves) return pref;
-    for (int c : {3, 4, 5})
-        if (waves(c) >= kMinWaves) return c;
-    return 5;
+int auto_shape(int K) {
+    static const int tk[4] = {4, 2, 1, 1}, wpg[4] = {4, 4, 4, 16};
+    for (int c = 0; c < 3; ++c)
+        if ((K + tk[c] - 1) / tk[c] * wpg[c] >= kMinWaves) return c;
+    return 3;
+}
+
+// One launch of automatic shape code `shape`.
+template <int FMT, int LAYOUT, bool MASK>
+int32_t launch_shape(int shape, const VolView& vv, const Points& p, const float* poses, int K, float* fitness,
+                     int* n_valid, const pf_track_state* st, int gate, hipStream_t s) {
+    if constexpr (MASK && LAYOUT != PF_LAYOUT_CELLS) {
+        return set_error(PF_EUNSUPPORTED, "particles_score: the mask exists for the replica only");
+    } else {
+        switch (shape) {
+            case 0: return launch_t<FMT, LAYOUT, 4, 256, MASK>(vv, p, poses, K, fitness, n_valid, st, gate, s);
+            case 1: return launch_t<FMT, LAYOUT, 2, 256, MASK>(vv, p, poses, K, fitness, n_valid, st, gate, s);
+            case 2: return launch_t<FMT, LAYOUT, 1, 256, MASK>(vv, p, poses, K, fitness, n_valid, st, gate, s);
+            default: return launch_t<FMT, LAYOUT, 1, 1024, MASK>(vv, p, poses, K, fitness, n_valid, st, gate, s);
+        }
+    }
 }
 
 // The configured shape (pf_score_config); in automatic mode with an optimizer state, either the
@@ -70,11 +91,16 @@ int auto_shape(int regime, int K) {
 template <int FMT, int LAYOUT>
 int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
                   const pf_track_state* st, hipStream_t s, int expect) {
+    constexpr bool kCells = LAYOUT == PF_LAYOUT_CELLS;
+    const bool mask_all = kCells && (g_mask_regimes & kMaskAlways);
     // few poses: spread the points over a wide workgroup
-    if (K <= 64) return launch_t<FMT, LAYOUT, 1, 1024>(vv, p, poses, K, fitness, n_valid, st, -1, s);
-#define PF_SHAPE(TK, B)                 \
-    if (g_tk == TK && g_block == B)     \
-        return launch_t<FMT, LAYOUT, TK, B>(vv, p, poses, K, fitness, n_valid, st, -1, s);
+    if (K <= 64)
+        return mask_all ? launch_t<FMT, LAYOUT, 1, 1024, kCells>(vv, p, poses, K, fitness, n_valid, st, -1, s)
+                        : launch_t<FMT, LAYOUT, 1, 1024>(vv, p, poses, K, fitness, n_valid, st, -1, s);
+#define PF_SHAPE(TK, B)                                                                                       \
+    if (g_tk == TK && g_block == B)                                                                           \
+        return mask_all ? launch_t<FMT, LAYOUT, TK, B, kCells>(vv, p, poses, K, fitness, n_valid, st, -1, s) \
+                        : launch_t<FMT, LAYOUT, TK, B>(vv, p, poses, K, fitness, n_valid, st, -1, s);
     PF_SHAPE(1, 256) PF_SHAPE(2, 256) PF_SHAPE(8, 256)
     PF_SHAPE(1, 512) PF_SHAPE(2, 512) PF_SHAPE(4, 512) PF_SHAPE(8, 512)
     PF_SHAPE(2, 128) PF_SHAPE(4, 128) PF_SHAPE(8, 128)
@@ -82,21 +108,18 @@ int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K,
 #undef PF_SHAPE
     if (g_tk == 0 && st) {
         int32_t rc = PF_OK;
-        for (int regime = 0; regime < 3 && !rc; ++regime) {
+        for (int regime = 0; regime < kRegimes && !rc; ++regime) {
             if (expect >= 0 && regime != expect) continue;
             const int gate = expect >= 0 ? -1 : regime;
-            switch (auto_shape(regime, K)) {
-                case 0: rc = launch_t<FMT, LAYOUT, 2, 64>(vv, p, poses, K, fitness, n_valid, st, gate, s); break;
-                case 1: rc = launch_t<FMT, LAYOUT, 4, 128>(vv, p, poses, K, fitness, n_valid, st, gate, s); break;
-                case 2: rc = launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, gate, s); break;
-                case 3: rc = launch_t<FMT, LAYOUT, 2, 256>(vv, p, poses, K, fitness, n_valid, st, gate, s); break;
-                case 4: rc = launch_t<FMT, LAYOUT, 1, 256>(vv, p, poses, K, fitness, n_valid, st, gate, s); break;
-                default: rc = launch_t<FMT, LAYOUT, 1, 1024>(vv, p, poses, K, fitness, n_valid, st, gate, s); break;
-            }
+            const bool mask = kCells && ((g_mask_regimes >> regime) & 1);
+            const int shape = auto_shape(K);
+            rc = mask ? launch_shape<FMT, LAYOUT, true>(shape, vv, p, poses, K, fitness, n_valid, st, gate, s)
+                      : launch_shape<FMT, LAYOUT, false>(shape, vv, p, poses, K, fitness, n_valid, st, gate, s);
         }
         return rc;
     }
-    return launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, -1, s);
+    return mask_all ? launch_t<FMT, LAYOUT, 4, 256, kCells>(vv, p, poses, K, fitness, n_valid, st, -1, s)
+                    : launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, -1, s);
 }
 
 }  // namespace
@@ -113,6 +136,15 @@ int32_t score_config(int tk, int block) {
     g_tk = tk;
     g_block = block;
     return PF_OK;
+}
+
+int32_t score_mask(int mode) {
+    switch (mode) {
+        case PF_MASK_BY_SPREAD: g_mask_regimes = kMaskRegimes; return PF_OK;
+        case PF_MASK_ALWAYS: g_mask_regimes = ((1 << kRegimes) - 1) | kMaskAlways; return PF_OK;
+        case PF_MASK_NEVER: g_mask_regimes = 0; return PF_OK;
+        default: return set_error(PF_EINVAL, "pf_score_mask: unknown mode %d", mode);
+    }
 }
 
 int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,

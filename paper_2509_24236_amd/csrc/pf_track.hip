@@ -280,9 +280,9 @@ namespace {
 
 // The spread regime of every iteration of the last call on this thread, and the parameters it ran
 // with. The search size contracts along much the same path frame after frame, so a call with the
-// same parameters launches, per iteration, only the scoring shape of the regime that iteration had
-// last time, instead of the three regime-gated launches (two of which return at once). A wrong
-// forecast costs speed only: the sums are exact whatever the shape.
+// same parameters launches, per iteration, only the scoring launch of the regime that iteration had
+// last time, instead of one regime-gated launch per regime (all but one of which return at once).
+// A wrong forecast costs speed only: the sums are exact whatever the launch.
 struct RegimeForecast {
     bool valid = false;
     int K = 0, n_iters = 0, n_rates = 0, alt_K = 0, rates[3] = {}, Ks[3] = {};

@@ -93,8 +93,44 @@ __device__ inline void write_corners(T* cells, const Dims& d, int i, int j, int 
             }
 }
 
+// The cell-validity mask of a CELLS volume (64-bit words of 4x4x4 cells) and the per-word bytes
+// that fusion sets when a voxel of the word's cells enters or leaves the band.
+struct MaskArgs {
+    unsigned long long* mask;
+    uint8_t* flags;
+    int mwx, mwy, mwz;
+};
+
+MaskArgs mask_args(const pf_tsdf* v) {
+    MaskArgs m{nullptr, nullptr, 0, 0, 0};
+    if (v->layout != PF_LAYOUT_CELLS) return m;
+    const CellMask M = cell_mask_layout(v);
+    m.mask = reinterpret_cast<unsigned long long*>(static_cast<char*>(v->tsdf) + M.mask);
+    m.flags = reinterpret_cast<uint8_t*>(static_cast<char*>(v->tsdf) + M.flags);
+    m.mwx = M.mwx;
+    m.mwy = M.mwy;
+    m.mwz = M.mwz;
+    return m;
+}
+
+// The band test of the scoring kernels on a stored value.
 template <int FMT>
-__global__ __launch_bounds__(kBlock) void k_init(void* Tv, void* Wv, void* Cv, Dims d) {
+__device__ inline bool stored_in_band(typename Store<FMT>::T v) {
+    return Fmt<FMT>::in_band(Fmt<FMT>::val(v));
+}
+
+// Flags the mask words of the (up to 8) cells that have voxel (i, j, k) as a corner.
+__device__ inline void flag_cells_of(const MaskArgs& m, const Dims& d, int i, int j, int k) {
+    const int x0 = max(i - 1, 0) >> 2, x1 = min(i, d.nx - 2) >> 2;
+    const int y0 = max(j - 1, 0) >> 2, y1 = min(j, d.ny - 2) >> 2;
+    const int z0 = max(k - 1, 0) >> 2, z1 = min(k, d.nz - 2) >> 2;
+    for (int z = z0; z <= z1; ++z)
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) m.flags[((int64_t)z * m.mwy + y) * m.mwx + x] = 1;
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_init(void* Tv, void* Wv, void* Cv, Dims d, MaskArgs m) {
     using S = Store<FMT>;
     auto* T = static_cast<typename S::T*>(Tv);
     auto* W = static_cast<typename S::W*>(Wv);
@@ -108,12 +144,66 @@ __global__ __launch_bounds__(kBlock) void k_init(void* Tv, void* Wv, void* Cv, D
     const typename S::T one_cell = S::cell(one);
     if (C)
         for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (d.ncells << 3); i += stride) C[i] = one_cell;
+    // no voxel is in the band: every mask word is 0 and none is flagged
+    const int64_t words = (int64_t)m.mwx * m.mwy * m.mwz;
+    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < words; w += stride) {
+        m.mask[w] = 0;
+        m.flags[w] = 0;
+    }
+}
+
+// Rebuilds mask word w from the x-fastest storage: the in-band bits of its 5x5x5 voxels, then a
+// cell's bit as the AND of its 8 corners'. Corners outside the grid count as out of band, so the
+// words' bits past the last cell are 0.
+template <int FMT>
+__device__ inline unsigned long long mask_word(const typename Store<FMT>::T* T, const Dims& d, const MaskArgs& m,
+                                               int64_t w) {
+    const int wx = (int)(w % m.mwx), wy = (int)((w / m.mwx) % m.mwy), wz = (int)(w / ((int64_t)m.mwx * m.mwy));
+    const int x0 = wx * 4, y0 = wy * 4, z0 = wz * 4;
+    unsigned rows[5][5];
+#pragma unroll
+    for (int dz = 0; dz < 5; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 5; ++dy) {
+            unsigned r = 0;
+            const int y = y0 + dy, z = z0 + dz;
+            if (y < d.ny && z < d.nz) {
+                const typename Store<FMT>::T* row = T + ((int64_t)z * d.ny + y) * d.nx;
+#pragma unroll
+                for (int dx = 0; dx < 5; ++dx)
+                    if (x0 + dx < d.nx && stored_in_band<FMT>(row[x0 + dx])) r |= 1u << dx;
+            }
+            rows[dz][dy] = r;
+        }
+    unsigned long long word = 0;
+#pragma unroll
+    for (int cz = 0; cz < 4; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 4; ++cy) {
+            const unsigned c = rows[cz][cy] & rows[cz][cy + 1] & rows[cz + 1][cy] & rows[cz + 1][cy + 1];
+            word |= (unsigned long long)(c & (c >> 1) & 0xfu) << (cz * 16 + cy * 4);
+        }
+    return word;
+}
+
+// Rebuilds the flagged mask words (every word when `all`) and clears their flags.
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_mask_update(const void* Tv, Dims d, MaskArgs m, int all) {
+    const auto* T = static_cast<const typename Store<FMT>::T*>(Tv);
+    const int64_t words = (int64_t)m.mwx * m.mwy * m.mwz;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < words; w += stride) {
+        if (!all && !m.flags[w]) continue;
+        m.mask[w] = mask_word<FMT>(T, d, m, w);
+        m.flags[w] = 0;
+    }
 }
 
 struct FuseArgs {
     void* T;
     void* W;
     void* C;
+    MaskArgs m;   // CELLS: the validity mask, else null
     Dims d;
     double vs, tau, ox, oy, oz;
     double R[9], t[3];
@@ -183,11 +273,12 @@ __device__ inline bool fuse_decide(const FuseArgs& a, int i, int j, int k, doubl
 
 // The running-average update of one stored voxel (T[e], W[e]); returns whether T changed.
 template <int FMT>
-__device__ inline bool fuse_apply(const FuseArgs& a, int64_t e, double phi, typename Store<FMT>::T& tnew) {
+__device__ inline bool fuse_apply(const FuseArgs& a, int64_t e, double phi, typename Store<FMT>::T& told,
+                                  typename Store<FMT>::T& tnew) {
     using S = Store<FMT>;
     auto* T = static_cast<typename S::T*>(a.T);
     auto* W = static_cast<typename S::W*>(a.W);
-    const typename S::T told = T[e];
+    told = T[e];
     const float w = S::decw(W[e]);
     const float tn = (S::dec(told) * w + (float)phi) / (w + 1.0f);
     tnew = S::enc(tn);
@@ -201,10 +292,12 @@ template <int FMT>
 __device__ inline void fuse_voxel(const FuseArgs& a, int i, int j, int k) {
     double phi;
     if (!fuse_decide(a, i, j, k, phi)) return;
-    typename Store<FMT>::T tnew;
+    typename Store<FMT>::T told, tnew;
     const int64_t idx = ((int64_t)k * a.d.ny + j) * a.d.nx + i;
-    if (fuse_apply<FMT>(a, idx, phi, tnew) && a.C)
+    if (fuse_apply<FMT>(a, idx, phi, told, tnew) && a.C) {
         write_corners(static_cast<typename Store<FMT>::T*>(a.C), a.d, i, j, k, Store<FMT>::cell(tnew));
+        if (stored_in_band<FMT>(told) != stored_in_band<FMT>(tnew)) flag_cells_of(a.m, a.d, i, j, k);
+    }
 }
 
 // Grid: a workgroup owns a brick of kFuseX x kFuseY x kFuseZ voxels (a wave per x row, each thread
@@ -504,8 +597,8 @@ __global__ __launch_bounds__(kBlock) void k_bricks_integrate(FuseArgs a, BrickAr
             const int i = i0 + (e & 7), j = j0 + ((e >> 3) & 7), k = k0 + (e >> 6);
             double phi;
             if (!fuse_decide(a, i, j, k, phi)) continue;
-            typename Store<FMT>::T tnew;
-            if (fuse_apply<FMT>(a, ((int64_t)slot << 9) + e, phi, tnew))
+            typename Store<FMT>::T told, tnew;
+            if (fuse_apply<FMT>(a, ((int64_t)slot << 9) + e, phi, told, tnew))
                 write_corners_bricks(b, a.d, i, j, k, Store<FMT>::cell(tnew));
         }
     }
@@ -588,7 +681,8 @@ template <int FMT>
 int32_t init_t(const pf_tsdf* v, hipStream_t s) {
     if (v->layout == PF_LAYOUT_BRICKS) return bricks_reset<FMT>(v, s);
     const Dims d = dims_of(v);
-    hipLaunchKernelGGL(k_init<FMT>, dim3(grid_for(d.n * 8)), dim3(kBlock), 0, s, v->tsdf, v->weight, cells_ptr(v), d);
+    hipLaunchKernelGGL(k_init<FMT>, dim3(grid_for(d.n * 8)), dim3(kBlock), 0, s, v->tsdf, v->weight, cells_ptr(v), d,
+                       mask_args(v));
     return check_launch("tsdf_init");
 }
 
@@ -598,6 +692,7 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
     a.T = v->tsdf;
     a.W = v->weight;
     a.C = cells_ptr(v);
+    a.m = mask_args(v);
     a.d = dims_of(v);
     a.vs = v->voxel_size;
     a.tau = v->trunc;
@@ -643,6 +738,10 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
     const dim3 grid((unsigned)((a.d.nx + kFuseX - 1) / kFuseX), (unsigned)((a.d.ny + kFuseY - 1) / kFuseY),
                     (unsigned)((a.d.nz + kFuseZ - 1) / kFuseZ));
     hipLaunchKernelGGL(k_integrate<FMT>, grid, dim3(kBlock), 0, s, a);
+    if (v->layout == PF_LAYOUT_CELLS) {
+        const int64_t words = (int64_t)a.m.mwx * a.m.mwy * a.m.mwz;
+        hipLaunchKernelGGL(k_mask_update<FMT>, dim3(grid_for(words)), dim3(kBlock), 0, s, v->tsdf, a.d, a.m, 0);
+    }
     return check_launch("tsdf_integrate");
 }
 
@@ -674,6 +773,9 @@ int32_t import_t(const pf_tsdf* v, const float* T, const float* W, hipStream_t s
     int32_t rc = check_launch("tsdf_import_linear");
     if (rc || v->layout != PF_LAYOUT_CELLS) return rc;
     hipLaunchKernelGGL(k_build_cells<FMT>, dim3(grid_for(d.ncells)), dim3(kBlock), 0, s, v->tsdf, cells_ptr(v), d);
+    const MaskArgs m = mask_args(v);
+    const int64_t words = (int64_t)m.mwx * m.mwy * m.mwz;
+    hipLaunchKernelGGL(k_mask_update<FMT>, dim3(grid_for(words)), dim3(kBlock), 0, s, v->tsdf, d, m, 1);
     return check_launch("tsdf_import_linear (cells)");
 }
 

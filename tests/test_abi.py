@@ -88,11 +88,19 @@ def test_tsdf_bytes(pf):
         assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == 16 * 8 * 4 * tb
         assert wb.value == 16 * 8 * 4 * wbb
     for fmt, tb in {0: 4, 1: 2, 2: 2}.items():
+        # CELLS: T, the replica, the cell-validity mask (one word per 4x4x4 cells: 4 x 2 x 1 words for
+        # 15 x 7 x 3 cells) and one flag byte per word, each part starting on a 256-byte boundary
         d = _desc(pf, 16, 8, 4, fmt, layout=1)
         off = L.tsdf_cells_offset(C.byref(d))
         assert off >= 16 * 8 * 4 * tb and off % 256 == 0
-        assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == off + 15 * 7 * 3 * 8 * tb
+        moff = L.tsdf_mask_offset(C.byref(d))
+        assert moff >= off + 15 * 7 * 3 * 8 * tb and moff % 256 == 0 and moff - (off + 15 * 7 * 3 * 8 * tb) < 256
+        words = 4 * 2 * 1
+        foff = (moff + 8 * words + 255) // 256 * 256
+        assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == (foff + words + 255) // 256 * 256
     assert L.tsdf_cells_offset(C.byref(_desc(pf, 16, 8, 4, 0, layout=0))) == 0
+    assert L.tsdf_mask_offset(C.byref(_desc(pf, 16, 8, 4, 0, layout=0))) == 0
+    assert L.tsdf_mask_offset(None) == 0
     assert L.tsdf_bytes(C.byref(_desc(pf, layout=5)), C.byref(wb)) == 0
     assert L.tsdf_bytes(C.byref(_desc(pf, layout=2)), C.byref(wb)) == 0    # BRICKS without a pool
     d = _desc(pf)

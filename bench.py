@@ -296,6 +296,7 @@ def bench_combined(args):
     import numpy as np
     import torch
     import paper_2509_24236_amd as pf
+    from paper_2509_24236_amd import autotune
     import synth
     dev = torch.device("cuda:0")
     n = args.problems
@@ -336,7 +337,7 @@ def bench_combined(args):
     rows, chosen = [], None
     for iters in range(3, 10):
         cp = [(v, d, k, R, t, dataclasses.replace(prm, n_iters=iters, polish_steps=5)) for v, d, k, R, t, prm in probs]
-        b = pf.Batch(cp, pf.BatchPlan(), device=dev)
+        b = pf.Batch(cp, autotune.plan_for(cp), device=dev)
         b.run()
         res = b.results()
         torch.cuda.synchronize()

@@ -493,7 +493,7 @@ def timing_read(reset: bool = False):
 @dataclasses.dataclass
 class BatchPlan:
     score_tk: int = 4        # poses per 256-thread workgroup (1, 2, 4, 8), or 0: track_frame's automatic shape (4)
-    score_grid: int = 512
+    score_grid: int = 4096
     order: int = 1
 
     def c(self) -> pf_batch_plan:

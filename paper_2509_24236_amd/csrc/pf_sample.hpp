@@ -61,8 +61,14 @@ struct Fmt<PF_I16_W_U8> {
 
 using FixSum = unsigned long long;
 
-// Largest float below 2^32: a clamp that keeps the conversion defined whatever the input.
-constexpr float kFixMax = 4294967040.0f;
+// Fixed-point value of a valid sample. Each lerp of the interpolation is one fused multiply-add
+// with a fraction below 1, whose exact value lies between its two endpoints, so rounding keeps it
+// there: |value| is at most the largest |corner|, below 1 (32767 stored units for int16), and the
+// product with `fix` is at most (1 - 2^-24) 2^32 (32766 * 2^17), inside the unsigned range.
+template <int FMT>
+__device__ inline unsigned fixed_point(float v) {
+    return (unsigned)(fabsf(v) * Fmt<FMT>::fix);
+}
 
 // E from an exact (sum, count) pair; E = 1 for an empty valid set.
 template <int FMT>
@@ -125,12 +131,19 @@ struct Gather<FMT, PF_LAYOUT_CELLS> {
     int cnx, cnxy;              // (nx-1), (nx-1)*(ny-1)
     const unsigned long long* __restrict__ M;   // cell-validity mask: one word per 4x4x4 cells
     int mwx, mwxy;
-    __device__ inline const ST* addr(int cx, int cy, int cz) const {
-        return C + ((size_t)((cz * cnxy) + cy * cnx + cx) << 3);
+    // cell index (below 2^31 for the dense layouts), unsigned so that its widening is a zero
+    // extension and the address one shift-and-add
+    __device__ inline unsigned index(unsigned cx, unsigned cy, unsigned cz) const {
+        return cz * (unsigned)cnxy + cy * (unsigned)cnx + cx;
     }
+    __device__ inline const ST* at(unsigned idx) const { return C + ((size_t)idx << 3); }
+    __device__ inline const ST* addr(int cx, int cy, int cz) const { return at(index(cx, cy, cz)); }
     __device__ inline void load(const ST* p, float (&c)[8]) const { load_cell8<FMT>(p, c); }
+    // the mask is below 2^28 bytes, so a 32-bit offset from the uniform base addresses a word
     __device__ inline const unsigned long long* mask_word(int cx, int cy, int cz) const {
-        return M + ((cz >> 2) * mwxy + (cy >> 2) * mwx + (cx >> 2));
+        const unsigned w = (unsigned)(cz >> 2) * (unsigned)mwxy + (unsigned)(cy >> 2) * (unsigned)mwx +
+                           (unsigned)(cx >> 2);
+        return reinterpret_cast<const unsigned long long*>(reinterpret_cast<const char*>(M) + (w << 3));
     }
     __device__ static inline unsigned mask_bit(int cx, int cy, int cz) {
         return (unsigned)((cx & 3) | ((cy & 3) << 2) | ((cz & 3) << 4));
@@ -174,6 +187,14 @@ __device__ inline GridPose fold_pose(const float* P, float inv_vs, float gx0, fl
     return g;
 }
 
+// For the active lanes whose bit in `lanes` is set, `if_set`, else `if_clear` (one v_cndmask_b32 on
+// the lane mask; opaque to the compiler, so it stays where it is written).
+__device__ inline float select_lanes(unsigned long long lanes, float if_set, float if_clear) {
+    float r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(lanes));
+    return r;
+}
+
 // floor(x) as an int (v_cvt_flr_i32_f32; the compiler emits floor and convert separately). Values
 // outside the int range only ever produce out-of-grid cells, which are clamped and rejected.
 __device__ inline int floor_to_int(float x) {
@@ -211,6 +232,7 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     static_assert(!MASK || LAYOUT == PF_LAYOUT_CELLS, "the mask exists for the replica only");
     using ST = typename Fmt<FMT>::T;
     const ST* p[NP];
+    unsigned ci[NP];   // replica: cell index, compared instead of the 64-bit address
     float f[NP][3];
     bool inb[NP];
     int cl[NP][3];
@@ -224,18 +246,30 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
         const int ix = floor_to_int(gx), iy = floor_to_int(gy), iz = floor_to_int(gz);
         const unsigned ux = (unsigned)ix, uy = (unsigned)iy, uz = (unsigned)iz;
         inb[j] = (ux < lx) & (uy < ly) & (uz < lz);
-        // any corner outside the grid (negative ones wrap to large values) is clamped to the last
-        // cell: the gather stays in bounds and the sample is rejected by inb
-        const int cx = (int)min(ux, lx - 1u);
-        const int cy = (int)min(uy, ly - 1u);
-        const int cz = (int)min(uz, lz - 1u);
         f[j][0] = __builtin_amdgcn_fractf(gx);
         f[j][1] = __builtin_amdgcn_fractf(gy);
         f[j][2] = __builtin_amdgcn_fractf(gz);
-        cl[j][0] = cx;
-        cl[j][1] = cy;
-        cl[j][2] = cz;
-        if constexpr (LAYOUT != PF_LAYOUT_BRICKS) p[j] = G.addr(cx, cy, cz);
+        if constexpr (LAYOUT == PF_LAYOUT_CELLS && !MASK) {
+            // a sample outside the grid (negative corners wrap to large values) reads cell 0
+            // instead: the gather stays in bounds and the sample is rejected by inb
+            ci[j] = inb[j] ? G.index(ux, uy, uz) : 0u;
+            p[j] = G.at(ci[j]);
+        } else {
+            // any corner outside the grid is clamped to the last cell: the gather (and the mask
+            // word) stay in bounds and the sample is rejected by inb
+            const int cx = (int)min(ux, lx - 1u);
+            const int cy = (int)min(uy, ly - 1u);
+            const int cz = (int)min(uz, lz - 1u);
+            cl[j][0] = cx;
+            cl[j][1] = cy;
+            cl[j][2] = cz;
+            if constexpr (LAYOUT == PF_LAYOUT_CELLS) {
+                ci[j] = G.index(cx, cy, cz);
+                p[j] = G.at(ci[j]);
+            } else if constexpr (LAYOUT == PF_LAYOUT_LINEAR) {
+                p[j] = G.addr(cx, cy, cz);
+            }
+        }
     }
     if constexpr (LAYOUT == PF_LAYOUT_BRICKS) {
         // The brick of a cell comes from the index grid: a pose whose cell lies in the same brick
@@ -291,28 +325,29 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     // gathering them again. Late in an optimization the search size has contracted so far that
     // neighbouring particles sample the same cells almost everywhere, and the loads of a whole
     // wavefront are then skipped; the values are identical either way.
-    // The copy is made after all gathers were issued: the flag that selects it is passed through
-    // an empty asm statement so the compiler cannot fold the copy into the branch, where it would
-    // wait for the previous pose's gather before issuing the next one.
+    // The copy is made after all gathers were issued, by a lane select the compiler cannot see
+    // through (select_lanes), so that it cannot fold the copy into the branch, where it would wait
+    // for the previous pose's gather before issuing the next one.
     // (With the mask, a pose in the same cell as the previous one has the same bit, so the block it
     // copies was gathered whenever it needs one.)
     float c[NP][8];
-    int dup[NP];
-    dup[0] = 0;
+    unsigned long long dup[NP];   // lanes whose pose j samples the same cell as pose j-1
     if (need[0]) G.load(p[0], c[0]);
 #pragma unroll
     for (int j = 1; j < NP; ++j) {
-        dup[j] = p[j] == p[j - 1] ? 1 : 0;
-        if (!dup[j] && need[j]) G.load(p[j], c[j]);
+        bool d;
+        if constexpr (LAYOUT == PF_LAYOUT_CELLS)
+            d = ci[j] == ci[j - 1];
+        else
+            d = p[j] == p[j - 1];
+        dup[j] = __ballot(d);
+        if (!d && need[j]) G.load(p[j], c[j]);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int j = 1; j < NP; ++j) {
-        int d = dup[j];
-        asm volatile("" : "+v"(d));
+    for (int j = 1; j < NP; ++j)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) c[j][q] = d ? c[j - 1][q] : c[j][q];
-    }
+        for (int q = 0; q < 8; ++q) c[j][q] = select_lanes(dup[j], c[j - 1][q], c[j][q]);
     // validity: with NaN-marked cells a NaN corner makes every step below NaN, so the value itself
     // says whether all 8 corners are in the band; otherwise each corner is tested
     constexpr bool kNanTest = !MASK && LAYOUT != PF_LAYOUT_LINEAR && Fmt<FMT>::nan_cells;
@@ -325,8 +360,7 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
         }
         const float v = trilerp(f[j][0], f[j][1], f[j][2], c[j]);
         if constexpr (kNanTest) ok &= !__builtin_isnan(v);
-        const float a = ok ? fminf(fabsf(v) * Fmt<FMT>::fix, kFixMax) : 0.0f;
-        sum[j] += (FixSum)(unsigned)a;
+        sum[j] += (FixSum)(ok ? fixed_point<FMT>(v) : 0u);
         cnt[j] += ok ? 1 : 0;
     }
 }

@@ -548,9 +548,9 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
         const uint4 e = Q[j][(head[j] + lane) & (kQueue - 1)];
         if (lane < m) {
             float c[8];
-            G.load(G.C + ((size_t)e.x << 3), c);
+            G.load(G.at(e.x), c);
             const float v = trilerp(__uint_as_float(e.y), __uint_as_float(e.z), __uint_as_float(e.w), c);
-            sum[j] += (FixSum)(unsigned)fminf(fabsf(v) * Fmt<FMT>::fix, kFixMax);
+            sum[j] += (FixSum)fixed_point<FMT>(v);
             cnt[j] += 1;
         }
         head[j] = (head[j] + m) & (kQueue - 1);
@@ -595,21 +595,26 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
         }
 #pragma unroll
         for (int j = 0; j < TK; ++j) mw[j] = *G.mask_word(cl[j][0], cl[j][1], cl[j][2]);
+        // (the loads are issued for every lane, in bounds thanks to the clamp, and kept together:
+        // a short-circuit test would move a load into a branch and wait for it there)
+        __builtin_amdgcn_sched_barrier(0);
         // append the valid samples of each pose to its queue, in lane order
 #pragma unroll
         for (int j = 0; j < TK; ++j) {
-            const bool valid = inb[j] && ((mw[j] >> G.mask_bit(cl[j][0], cl[j][1], cl[j][2])) & 1ull);
+            const bool valid = inb[j] & (((mw[j] >> G.mask_bit(cl[j][0], cl[j][1], cl[j][2])) & 1ull) != 0);
             const unsigned long long m = __ballot(valid);
             if (valid) {
                 const unsigned below =
                     __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                const unsigned cell = (unsigned)(cl[j][2] * G.cnxy + cl[j][1] * G.cnx + cl[j][0]);
+                const unsigned cell = G.index(cl[j][0], cl[j][1], cl[j][2]);
                 Q[j][(head[j] + fill[j] + (int)below) & (kQueue - 1)] =
                     make_uint4(cell, __float_as_uint(f[j][0]), __float_as_uint(f[j][1]), __float_as_uint(f[j][2]));
             }
             fill[j] += __popcll(m);
         }
         __builtin_amdgcn_wave_barrier();
+        // (draining the full queues one after the other measured faster than issuing all their
+        // gathers before the first wait)
 #pragma unroll
         for (int j = 0; j < TK; ++j)
             if (fill[j] >= kWave) drain(j, kWave);

@@ -152,50 +152,40 @@ __global__ __launch_bounds__(kBlock) void k_init(void* Tv, void* Wv, void* Cv, D
     }
 }
 
-// Rebuilds mask word w from the x-fastest storage: the in-band bits of its 5x5x5 voxels, then a
-// cell's bit as the AND of its 8 corners'. Corners outside the grid count as out of band, so the
-// words' bits past the last cell are 0.
-template <int FMT>
-__device__ inline unsigned long long mask_word(const typename Store<FMT>::T* T, const Dims& d, const MaskArgs& m,
-                                               int64_t w) {
-    const int wx = (int)(w % m.mwx), wy = (int)((w / m.mwx) % m.mwy), wz = (int)(w / ((int64_t)m.mwx * m.mwy));
-    const int x0 = wx * 4, y0 = wy * 4, z0 = wz * 4;
-    unsigned rows[5][5];
-#pragma unroll
-    for (int dz = 0; dz < 5; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 5; ++dy) {
-            unsigned r = 0;
-            const int y = y0 + dy, z = z0 + dz;
-            if (y < d.ny && z < d.nz) {
-                const typename Store<FMT>::T* row = T + ((int64_t)z * d.ny + y) * d.nx;
-#pragma unroll
-                for (int dx = 0; dx < 5; ++dx)
-                    if (x0 + dx < d.nx && stored_in_band<FMT>(row[x0 + dx])) r |= 1u << dx;
-            }
-            rows[dz][dy] = r;
-        }
-    unsigned long long word = 0;
-#pragma unroll
-    for (int cz = 0; cz < 4; ++cz)
-#pragma unroll
-        for (int cy = 0; cy < 4; ++cy) {
-            const unsigned c = rows[cz][cy] & rows[cz][cy + 1] & rows[cz + 1][cy] & rows[cz + 1][cy + 1];
-            word |= (unsigned long long)(c & (c >> 1) & 0xfu) << (cz * 16 + cy * 4);
-        }
-    return word;
-}
-
-// Rebuilds the flagged mask words (every word when `all`) and clears their flags.
+// Rebuilds the flagged mask words (every word when `all`) from the x-fastest storage and clears
+// their flags. A wave scans 64 consecutive words' flags, then rebuilds each flagged word together:
+// lane l takes cell l of the word's 4x4x4 block (bit l of the word), tests its 8 corners, and the
+// wave's ballot is the word. Cells past the last one of the grid have no corners there: bit 0.
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_mask_update(const void* Tv, Dims d, MaskArgs m, int all) {
     const auto* T = static_cast<const typename Store<FMT>::T*>(Tv);
     const int64_t words = (int64_t)m.mwx * m.mwy * m.mwz;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+    const int64_t nxy = (int64_t)d.nx * d.ny;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < words; w += stride) {
-        if (!all && !m.flags[w]) continue;
-        m.mask[w] = mask_word<FMT>(T, d, m, w);
-        m.flags[w] = 0;
+    for (int64_t base = ((int64_t)blockIdx.x * kBlock + threadIdx.x) - lane; base < words; base += stride) {
+        const int64_t own = base + lane;
+        unsigned long long todo = __ballot(own < words && (all || m.flags[own]));
+        while (todo) {   // uniform: the same words for every lane
+            const int64_t w = base + (__ffsll((long long)todo) - 1);
+            todo &= todo - 1;
+            const int wx = (int)(w % m.mwx), wy = (int)((w / m.mwx) % m.mwy), wz = (int)(w / ((int64_t)m.mwx * m.mwy));
+            const int cx = wx * 4 + lx, cy = wy * 4 + ly, cz = wz * 4 + lz;
+            bool valid = false;
+            if (cx < d.nx - 1 && cy < d.ny - 1 && cz < d.nz - 1) {
+                const int64_t b = ((int64_t)cz * d.ny + cy) * d.nx + cx;
+                valid = stored_in_band<FMT>(T[b]) & stored_in_band<FMT>(T[b + 1]) &
+                        stored_in_band<FMT>(T[b + d.nx]) & stored_in_band<FMT>(T[b + d.nx + 1]) &
+                        stored_in_band<FMT>(T[b + nxy]) & stored_in_band<FMT>(T[b + nxy + 1]) &
+                        stored_in_band<FMT>(T[b + nxy + d.nx]) & stored_in_band<FMT>(T[b + nxy + d.nx + 1]);
+            }
+            const unsigned long long word = __ballot(valid);
+            if (lane == 0) {
+                m.mask[w] = word;
+                m.flags[w] = 0;
+            }
+        }
     }
 }
 

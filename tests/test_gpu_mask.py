@@ -140,6 +140,35 @@ def test_masked_scoring_bitwise_and_parity(pf, orc, dev, cfg1, K, spread_deg):
     assert np.all(res[pf.MASK_ALWAYS][1] > 0)
 
 
+def test_masked_configured_shapes_bitwise(pf, orc, dev, cfg1):
+    """PF_MASK_ALWAYS with configured shapes: those whose queues fit in LDS compact the valid
+    samples, the larger ones (8x256, 4x512, 8x512) take the per-lane masked path; all equal the
+    unmasked result bit for bit, over a ragged point count."""
+    say("[mask] configured shapes through the mask")
+    gv = pf.Tsdf(cfg1["vol"], device=dev, layout=pf.LAYOUT_CELLS)
+    gv.integrate(torch.as_tensor(cfg1["depth1"]).to(dev), cfg1["intr"], np.eye(3), np.zeros(3))
+    X, _ = orc.backproject(cfg1["depth2"], cfg1["intr"], 2)
+    X = X[:4093]
+    xt = torch.as_tensor(X.astype(np.float32)).to(dev)
+    pts = (xt[:, 0].contiguous(), xt[:, 1].contiguous(), xt[:, 2].contiguous())
+    poses = _poses_around(orc, *cfg1["gt2"], 203, math.radians(3.0), 0.02, 17)
+    P = torch.as_tensor(pf.poses_to_f32(poses)).to(dev)
+    try:
+        pf.score_mask(pf.MASK_NEVER)
+        E0, n0 = pf.particles_score(gv, *pts, P)
+        ref = (E0.cpu().numpy().view(np.uint32), n0.cpu().numpy())
+        pf.score_mask(pf.MASK_ALWAYS)
+        for tk, blk in [(2, 64), (4, 128), (2, 512), (8, 256), (4, 512), (8, 512)]:
+            pf.score_config(tk, blk)
+            E, nv = pf.particles_score(gv, *pts, P)
+            assert np.array_equal(E.cpu().numpy().view(np.uint32), ref[0]), (tk, blk)
+            assert np.array_equal(nv.cpu().numpy(), ref[1]), (tk, blk)
+    finally:
+        pf.score_config(0, 0)
+        pf.score_mask(pf.MASK_BY_SPREAD)
+    assert int((ref[1] > 0).sum()) > 150
+
+
 def test_track_frame_mask_modes_bitwise(pf, orc, dev, cfg1):
     say("[mask] track_frame in the three mask modes")
     gv = pf.Tsdf(cfg1["vol"], device=dev, layout=pf.LAYOUT_CELLS)

@@ -77,7 +77,10 @@ extern "C" {
  *         inside the brick) and their cells (512 per brick, cell (x, y, z) local to the brick at
  *         x + 8y + 64z, its 8 corners in the CELLS order and with the CELLS marking of corners
  *         outside the band; corners in the next brick along +x/+y/+z read that brick, or +1
- *         where it has no slot).
+ *         where it has no slot), then (at tsdf_mask_offset()) 8 uint64 cell-validity words per
+ *         slot: bit (l % 64) of word l / 64 is set iff all 8 corners of the slot's cell at local
+ *         index l are in the band (rebuilt for every slot by tsdf_integrate and
+ *         tsdf_import_linear; read by scoring as the dense mask is).
  *         The W buffer holds the slots' W. A voxel outside every allocated brick reads T = +1,
  *         W = 0. tsdf_integrate first gives a slot to every brick that holds a voxel the frame
  *         puts in the band (-tau <= eta < tau, the same FP64 test as the update), then updates
@@ -115,7 +118,7 @@ typedef struct pf_tsdf {
     double origin[3];    /* centre of voxel (0,0,0), world metres */
     int32_t w_max;       /* weight cap, 1..255 */
     int32_t layout;      /* PF_LAYOUT_LINEAR, PF_LAYOUT_CELLS or PF_LAYOUT_BRICKS */
-    int32_t max_bricks;  /* BRICKS: pool slots (>= 1); 0 for the dense layouts */
+    int32_t max_bricks;  /* BRICKS: pool slots (1 .. 2^23); 0 for the dense layouts */
     int32_t reserved;    /* must be 0 */
     void* tsdf;          /* device, tsdf_bytes() bytes */
     void* weight;        /* device, *weight_bytes bytes */
@@ -213,7 +216,8 @@ size_t tsdf_bytes(const pf_tsdf* v, size_t* weight_bytes);
 /* Byte offset of the cell-major replica inside v->tsdf (PF_LAYOUT_CELLS), 0 otherwise. */
 size_t tsdf_cells_offset(const pf_tsdf* v);
 
-/* Byte offset of the cell-validity mask inside v->tsdf (PF_LAYOUT_CELLS), 0 otherwise. */
+/* Byte offset of the cell-validity mask inside v->tsdf (PF_LAYOUT_CELLS: the dense mask;
+ * PF_LAYOUT_BRICKS: the slots' words), 0 otherwise. */
 size_t tsdf_mask_offset(const pf_tsdf* v);
 
 /* BRICKS: byte offsets inside v->tsdf of the index grid, the slot coordinates, the slots' T and
@@ -304,15 +308,16 @@ int32_t particles_score_grad(const pf_tsdf* v, const float* px, const float* py,
  * PF_EINVAL for an unsupported shape. */
 int32_t pf_score_config(int32_t poses_per_group, int32_t group_size);
 
-/* When the scoring launches of particles_score and track_frame read a CELLS volume's replica
- * through its cell-validity mask: PF_MASK_BY_SPREAD (the default: the automatic launches of
+/* When the scoring launches of particles_score and track_frame read a CELLS or BRICKS volume's
+ * cells through its cell-validity mask: PF_MASK_BY_SPREAD (the default: the automatic launches of
  * track_frame while the particles are spread over more than a quarter voxel, where many samples
  * miss the band; never in particles_score, which has no spread, nor with a configured shape),
  * PF_MASK_ALWAYS (every launch, configured shapes included) or PF_MASK_NEVER. A launch that reads
- * the mask gathers and interpolates only the valid samples, compacted into full waves. Other
- * layouts have no mask; the batched path reads it by spread whatever the mode. Process-wide. The
- * mask bit of a cell equals the replica's validity, so results are bitwise identical in every mode;
- * the mode changes speed only. Returns PF_EINVAL for another value. */
+ * the mask gathers and interpolates only the valid samples, compacted into full waves (a BRICKS
+ * launch whose queues would not fit in LDS does not read it). LINEAR volumes have no mask; the
+ * batched path reads it by spread whatever the mode. Process-wide. The mask bit of a cell equals
+ * the cell's validity, so results are bitwise identical in every mode; the mode changes speed
+ * only. Returns PF_EINVAL for another value. */
 #define PF_MASK_BY_SPREAD 0
 #define PF_MASK_ALWAYS 1
 #define PF_MASK_NEVER 2

@@ -76,7 +76,8 @@ BrickLayout brick_layout(const pf_tsdf* v) {
     L.coords = L.cand + al256(nb * sizeof(int));
     L.pool_t = L.coords + al256(slots * 4 * sizeof(int));
     L.pool_cells = L.pool_t + al256(slots * kBrickVox * tb);
-    L.t_total = L.pool_cells + slots * kBrickVox * 8 * tb;
+    L.pool_mask = L.pool_cells + al256(slots * kBrickVox * 8 * tb);
+    L.t_total = L.pool_mask + slots * kBrickMaskWords * sizeof(unsigned long long);
     L.w_total = slots * kBrickVox * (v->format == PF_F32_W_F32 ? 4 : 1);
     return L;
 }
@@ -103,6 +104,7 @@ VolView make_view(const pf_tsdf* v) {
         vv.cells = base + L.pool_cells;
         vv.bindex = reinterpret_cast<const int*>(base + L.index);
         vv.ones = base + kBrickOnes;
+        vv.mask = reinterpret_cast<const unsigned long long*>(base + L.pool_mask);
         vv.nbx = L.nbx;
         vv.nby = L.nby;
     }
@@ -133,6 +135,9 @@ int32_t check_tsdf(const pf_tsdf* v, const char* fn, bool need_weight = true) {
         if ((int64_t)(v->nx / kBrickEdge) * (v->ny / kBrickEdge) * (v->nz / kBrickEdge) >= ((int64_t)1 << 31))
             return set_error(PF_EINVAL, "%s: brick-index grid exceeds 2^31 - 1 entries", fn);
         if (v->max_bricks < 1) return set_error(PF_EINVAL, "%s: BRICKS needs max_bricks >= 1", fn);
+        if (v->max_bricks > kMaxBricks)
+            return set_error(PF_EINVAL, "%s: BRICKS max_bricks %d > %d (a pool cell's index must fit 32 bits)", fn,
+                             v->max_bricks, kMaxBricks);
     } else {
         if (v->max_bricks != 0) return set_error(PF_EINVAL, "%s: max_bricks must be 0 for a dense layout", fn);
         if (v->ny > 65535 || v->nz > 65535)
@@ -244,7 +249,9 @@ size_t tsdf_bytes(const pf_tsdf* v, size_t* weight_bytes) {
     if (!v || v->nx < 2 || v->ny < 2 || v->nz < 2) return 0;
     if (v->format != PF_F32_W_F32 && v->format != PF_F16_W_U8 && v->format != PF_I16_W_U8) return 0;
     if (v->layout == PF_LAYOUT_BRICKS) {
-        if (v->nx % kBrickEdge || v->ny % kBrickEdge || v->nz % kBrickEdge || v->max_bricks < 1 || v->reserved) return 0;
+        if (v->nx % kBrickEdge || v->ny % kBrickEdge || v->nz % kBrickEdge || v->max_bricks < 1 ||
+            v->max_bricks > kMaxBricks || v->reserved)
+            return 0;
         if ((int64_t)(v->nx / kBrickEdge) * (v->ny / kBrickEdge) * (v->nz / kBrickEdge) >= ((int64_t)1 << 31)) return 0;
         const BrickLayout L = brick_layout(v);
         if (weight_bytes) *weight_bytes = L.w_total;
@@ -266,8 +273,10 @@ size_t tsdf_cells_offset(const pf_tsdf* v) {
 }
 
 size_t tsdf_mask_offset(const pf_tsdf* v) {
-    if (!v || v->layout != PF_LAYOUT_CELLS || tsdf_bytes(v, nullptr) == 0) return 0;
-    return cell_mask_layout(v).mask;
+    if (!v || tsdf_bytes(v, nullptr) == 0) return 0;
+    if (v->layout == PF_LAYOUT_CELLS) return cell_mask_layout(v).mask;
+    if (v->layout == PF_LAYOUT_BRICKS) return brick_layout(v).pool_mask;
+    return 0;
 }
 
 int32_t tsdf_brick_offsets(const pf_tsdf* v, size_t* index, size_t* coords, size_t* pool_t, size_t* pool_cells) {

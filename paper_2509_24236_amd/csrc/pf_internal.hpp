@@ -117,8 +117,10 @@ CellMask cell_mask_layout(const pf_tsdf* v);
 constexpr int kBrickEdge = 8, kBrickVox = 512;
 struct BrickLayout {
     int nbx, nby, nbz;
-    size_t index, cand, coords, pool_t, pool_cells, t_total, w_total;
+    size_t index, cand, coords, pool_t, pool_cells, pool_mask, t_total, w_total;
 };
+constexpr int kBrickMaskWords = 8;   // cell-validity words per slot: 64 cells (local 64w .. 64w+63) each
+constexpr int kMaxBricks = 1 << 23;  // slots: a pool cell's index (slot * 512 + local) fits 32 bits
 BrickLayout brick_layout(const pf_tsdf* v);
 
 // Header at the start of a BRICKS T buffer; a cell block of +1 follows at kBrickOnes.

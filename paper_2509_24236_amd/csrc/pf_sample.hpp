@@ -159,9 +159,15 @@ struct Gather<FMT, PF_LAYOUT_BRICKS> {
     const ST* __restrict__ C;     // the slots' cells
     const ST* ones;               // one block of +1
     const int* __restrict__ idx;  // brick-index grid
+    const unsigned long long* __restrict__ M;   // the slots' cell-validity words (8 per slot)
     int nbx, nbxy;
     __device__ inline int key(int cx, int cy, int cz) const { return (cz >> 3) * nbxy + (cy >> 3) * nbx + (cx >> 3); }
     __device__ inline int slot(int k) const { return idx[k]; }
+    __device__ static inline unsigned local(int cx, int cy, int cz) {
+        return (unsigned)((cx & 7) | ((cy & 7) << 3) | ((cz & 7) << 6));
+    }
+    // a cell by its index in the pool (slot * 512 + local)
+    __device__ inline const ST* at(unsigned cell) const { return C + ((size_t)cell << 3); }
     __device__ inline const ST* at(int s, int cx, int cy, int cz) const {
         const int local = (cx & 7) | ((cy & 7) << 3) | ((cz & 7) << 6);
         return s < 0 ? ones : C + ((((size_t)s << 9) | (size_t)local) << 3);
@@ -417,6 +423,7 @@ __host__ __device__ inline Gather<FMT, LAYOUT> make_gather(const VolView& vv) {
         G.C = static_cast<const typename Fmt<FMT>::T*>(vv.cells);
         G.ones = static_cast<const typename Fmt<FMT>::T*>(vv.ones);
         G.idx = vv.bindex;
+        G.M = vv.mask;
         G.nbx = vv.nbx;
         G.nbxy = vv.nbx * vv.nby;
     }

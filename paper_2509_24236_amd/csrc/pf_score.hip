@@ -72,8 +72,8 @@ int auto_shape(int K) {
 template <int FMT, int LAYOUT, bool MASK>
 int32_t launch_shape(int shape, const VolView& vv, const Points& p, const float* poses, int K, float* fitness,
                      int* n_valid, const pf_track_state* st, int gate, hipStream_t s) {
-    if constexpr (MASK && LAYOUT != PF_LAYOUT_CELLS) {
-        return set_error(PF_EUNSUPPORTED, "particles_score: the mask exists for the replica only");
+    if constexpr (MASK && LAYOUT == PF_LAYOUT_LINEAR) {
+        return set_error(PF_EUNSUPPORTED, "particles_score: the x-fastest layout has no mask");
     } else {
         switch (shape) {
             case 0: return launch_t<FMT, LAYOUT, 4, 256, MASK>(vv, p, poses, K, fitness, n_valid, st, gate, s);
@@ -91,15 +91,15 @@ int32_t launch_shape(int shape, const VolView& vv, const Points& p, const float*
 template <int FMT, int LAYOUT>
 int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
                   const pf_track_state* st, hipStream_t s, int expect) {
-    constexpr bool kCells = LAYOUT == PF_LAYOUT_CELLS;
-    const bool mask_all = kCells && (g_mask_regimes & kMaskAlways);
+    constexpr bool kMasked = LAYOUT != PF_LAYOUT_LINEAR;   // the layouts with a cell-validity mask
+    const bool mask_all = kMasked && (g_mask_regimes & kMaskAlways);
     // few poses: spread the points over a wide workgroup
     if (K <= 64)
-        return mask_all ? launch_t<FMT, LAYOUT, 1, 1024, kCells>(vv, p, poses, K, fitness, n_valid, st, -1, s)
+        return mask_all ? launch_t<FMT, LAYOUT, 1, 1024, kMasked>(vv, p, poses, K, fitness, n_valid, st, -1, s)
                         : launch_t<FMT, LAYOUT, 1, 1024>(vv, p, poses, K, fitness, n_valid, st, -1, s);
 #define PF_SHAPE(TK, B)                                                                                       \
     if (g_tk == TK && g_block == B)                                                                           \
-        return mask_all ? launch_t<FMT, LAYOUT, TK, B, kCells>(vv, p, poses, K, fitness, n_valid, st, -1, s) \
+        return mask_all ? launch_t<FMT, LAYOUT, TK, B, kMasked>(vv, p, poses, K, fitness, n_valid, st, -1, s) \
                         : launch_t<FMT, LAYOUT, TK, B>(vv, p, poses, K, fitness, n_valid, st, -1, s);
     PF_SHAPE(1, 256) PF_SHAPE(2, 256) PF_SHAPE(8, 256)
     PF_SHAPE(1, 512) PF_SHAPE(2, 512) PF_SHAPE(4, 512) PF_SHAPE(8, 512)
@@ -111,14 +111,14 @@ int32_t launch_fl(const VolView& vv, const Points& p, const float* poses, int K,
         for (int regime = 0; regime < kRegimes && !rc; ++regime) {
             if (expect >= 0 && regime != expect) continue;
             const int gate = expect >= 0 ? -1 : regime;
-            const bool mask = kCells && ((g_mask_regimes >> regime) & 1);
+            const bool mask = kMasked && ((g_mask_regimes >> regime) & 1);
             const int shape = auto_shape(K);
             rc = mask ? launch_shape<FMT, LAYOUT, true>(shape, vv, p, poses, K, fitness, n_valid, st, gate, s)
                       : launch_shape<FMT, LAYOUT, false>(shape, vv, p, poses, K, fitness, n_valid, st, gate, s);
         }
         return rc;
     }
-    return mask_all ? launch_t<FMT, LAYOUT, 4, 256, kCells>(vv, p, poses, K, fitness, n_valid, st, -1, s)
+    return mask_all ? launch_t<FMT, LAYOUT, 4, 256, kMasked>(vv, p, poses, K, fitness, n_valid, st, -1, s)
                     : launch_t<FMT, LAYOUT, 4, 256>(vv, p, poses, K, fitness, n_valid, st, -1, s);
 }
 

@@ -521,13 +521,14 @@ constexpr bool compact_fits() {
     return (BLOCK / kWave) * TK * kQueue * 16 <= 32768;
 }
 
-template <int FMT, int TK, int BLOCK>
+template <int FMT, int LAYOUT, int TK, int BLOCK>
 __device__ inline void score_points_compact(const VolView& vv, const float* __restrict__ px,
                                             const float* __restrict__ py, const float* __restrict__ pz, int n,
                                             const float* __restrict__ poses, int K, int k0, FixSum (&sum)[TK],
                                             int (&cnt)[TK]) {
+    static_assert(LAYOUT == PF_LAYOUT_CELLS || LAYOUT == PF_LAYOUT_BRICKS, "the mask exists for these layouts");
     __shared__ uint4 queue[BLOCK / kWave][TK][kQueue];
-    const Gather<FMT, PF_LAYOUT_CELLS> G = make_gather<FMT, PF_LAYOUT_CELLS>(vv);
+    const Gather<FMT, LAYOUT> G = make_gather<FMT, LAYOUT>(vv);
     GridPose g[TK];
 #pragma unroll
     for (int j = 0; j < TK; ++j)
@@ -578,6 +579,7 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
         float f[TK][3];
         bool inb[TK];
         unsigned long long mw[TK];
+        unsigned cell[TK], bit[TK];   // the cell's index in the replica or the pool, its mask bit
 #pragma unroll
         for (int j = 0; j < TK; ++j) {
             const float gx = fmaf(g[j].r[0], x, fmaf(g[j].r[1], y, fmaf(g[j].r[2], z, g[j].t[0])));
@@ -593,22 +595,44 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
             f[j][1] = __builtin_amdgcn_fractf(gy);
             f[j][2] = __builtin_amdgcn_fractf(gz);
         }
+        if constexpr (LAYOUT == PF_LAYOUT_CELLS) {
 #pragma unroll
-        for (int j = 0; j < TK; ++j) mw[j] = *G.mask_word(cl[j][0], cl[j][1], cl[j][2]);
+            for (int j = 0; j < TK; ++j) {
+                mw[j] = *G.mask_word(cl[j][0], cl[j][1], cl[j][2]);
+                cell[j] = G.index(cl[j][0], cl[j][1], cl[j][2]);
+                bit[j] = G.mask_bit(cl[j][0], cl[j][1], cl[j][2]);
+            }
+        } else {
+            // sparse: the brick's slot first (one round for all poses), then its mask word; a
+            // brick without a slot has no valid cell (its word is read from slot 0, in bounds,
+            // and ignored)
+            int slot[TK];
+#pragma unroll
+            for (int j = 0; j < TK; ++j) slot[j] = G.slot(G.key(cl[j][0], cl[j][1], cl[j][2]));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < TK; ++j) {
+                inb[j] &= slot[j] >= 0;
+                const unsigned sl = (unsigned)max(slot[j], 0);
+                const unsigned loc = G.local(cl[j][0], cl[j][1], cl[j][2]);
+                mw[j] = G.M[sl * kBrickMaskWords + (loc >> 6)];
+                cell[j] = (sl << 9) | loc;
+                bit[j] = loc & 63u;
+            }
+        }
         // (the loads are issued for every lane, in bounds thanks to the clamp, and kept together:
         // a short-circuit test would move a load into a branch and wait for it there)
         __builtin_amdgcn_sched_barrier(0);
         // append the valid samples of each pose to its queue, in lane order
 #pragma unroll
         for (int j = 0; j < TK; ++j) {
-            const bool valid = inb[j] & (((mw[j] >> G.mask_bit(cl[j][0], cl[j][1], cl[j][2])) & 1ull) != 0);
+            const bool valid = inb[j] & (((mw[j] >> bit[j]) & 1ull) != 0);
             const unsigned long long m = __ballot(valid);
             if (valid) {
                 const unsigned below =
                     __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                const unsigned cell = G.index(cl[j][0], cl[j][1], cl[j][2]);
-                Q[j][(head[j] + fill[j] + (int)below) & (kQueue - 1)] =
-                    make_uint4(cell, __float_as_uint(f[j][0]), __float_as_uint(f[j][1]), __float_as_uint(f[j][2]));
+                Q[j][(head[j] + fill[j] + (int)below) & (kQueue - 1)] = make_uint4(
+                    cell[j], __float_as_uint(f[j][0]), __float_as_uint(f[j][1]), __float_as_uint(f[j][2]));
             }
             fill[j] += __popcll(m);
         }
@@ -675,10 +699,11 @@ __device__ inline void score_step(const VolView& vv, const float* __restrict__ p
                                   float* __restrict__ fitness, int* __restrict__ n_valid) {
     FixSum sum[TK];
     int cnt[TK];
-    if constexpr (MASK && LAYOUT == PF_LAYOUT_CELLS && compact_fits<TK, BLOCK>())
-        score_points_compact<FMT, TK, BLOCK>(vv, px, py, pz, n, poses, K, k0, sum, cnt);
-    else
-        score_points_lanes<FMT, LAYOUT, TK, BLOCK, MASK>(vv, px, py, pz, n, poses, K, k0, sum, cnt);
+    if constexpr (MASK && LAYOUT != PF_LAYOUT_LINEAR && compact_fits<TK, BLOCK>())
+        score_points_compact<FMT, LAYOUT, TK, BLOCK>(vv, px, py, pz, n, poses, K, k0, sum, cnt);
+    else   // (the sparse layout reads its mask only when compacting: the mask changes speed only)
+        score_points_lanes<FMT, LAYOUT, TK, BLOCK, MASK && LAYOUT == PF_LAYOUT_CELLS>(vv, px, py, pz, n, poses, K,
+                                                                                   k0, sum, cnt);
     block_reduce<TK, BLOCK>(sum, cnt);
     if (threadIdx.x < TK) {
         const int k = k0 + threadIdx.x;
@@ -697,7 +722,7 @@ __device__ inline void score_step_regime(const VolView& vv, const float* __restr
                                          const float* __restrict__ py, const float* __restrict__ pz, int n,
                                          const float* __restrict__ poses, int K, int k0, float* __restrict__ fitness,
                                          int* __restrict__ n_valid, int regime) {
-    if constexpr (LAYOUT == PF_LAYOUT_CELLS) {
+    if constexpr (LAYOUT != PF_LAYOUT_LINEAR) {
         if ((kMaskRegimes >> regime) & 1) {
             score_step<FMT, LAYOUT, TK, BLOCK, true>(vv, px, py, pz, n, poses, K, k0, fitness, n_valid);
             return;

@@ -391,6 +391,7 @@ struct BrickArgs {
     int4* coords;   // slot -> brick coordinates
     void* T;        // slots' T, 512 each
     void* C;        // slots' cells, 512 x 8 each
+    unsigned long long* M;   // slots' cell-validity words, 8 each
     void* W;        // slots' W
     int nbx, nby, nbz, max_bricks;
 };
@@ -405,6 +406,7 @@ BrickArgs brick_args(const pf_tsdf* v) {
     b.coords = reinterpret_cast<int4*>(base + L.coords);
     b.T = base + L.pool_t;
     b.C = base + L.pool_cells;
+    b.M = reinterpret_cast<unsigned long long*>(base + L.pool_mask);
     b.W = v->weight;
     b.nbx = L.nbx;
     b.nby = L.nby;
@@ -594,6 +596,29 @@ __global__ __launch_bounds__(kBlock) void k_bricks_integrate(FuseArgs a, BrickAr
     }
 }
 
+// Rebuilds the cell-validity words of every slot in use from its cell blocks: bit (local & 63) of
+// word (local >> 6) is set iff all 8 corners of the cell are in the band (the test of the scoring;
+// a NaN-marked corner fails it). A wave covers 64 consecutive cells of a slot, so its ballot is a
+// word.
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_bricks_mask(BrickArgs b) {
+    using ST = typename Store<FMT>::T;
+    const ST* C = static_cast<const ST*>(b.C);
+    const int n_now = min(b.hdr->n, b.max_bricks);
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int slot = blockIdx.x; slot < n_now; slot += gridDim.x) {
+        for (int e = threadIdx.x; e < kBrickVox; e += kBlock) {
+            float c[8];
+            load_cell8<FMT>(C + ((((size_t)slot << 9) | (size_t)e) << 3), c);
+            bool valid = true;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) valid &= Fmt<FMT>::in_band(c[q]);
+            const unsigned long long word = __ballot(valid);
+            if (lane == 0) b.M[(size_t)slot * kBrickMaskWords + (e >> 6)] = word;
+        }
+    }
+}
+
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_bricks_export(BrickArgs b, Dims d, float* To, float* Wo) {
     using S = Store<FMT>;
@@ -723,6 +748,7 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
         hipLaunchKernelGGL(k_bricks_mark, dim3(kBrickGrid), dim3(kBlock), 0, s, a, b);
         hipLaunchKernelGGL((k_bricks_cells<FMT, true>), dim3(kBrickGrid), dim3(kBlock), 0, s, b, a.d, 1);
         hipLaunchKernelGGL(k_bricks_integrate<FMT>, dim3(kBrickGrid), dim3(kBlock), 0, s, a, b);
+        hipLaunchKernelGGL(k_bricks_mask<FMT>, dim3(kBrickGrid), dim3(kBlock), 0, s, b);
         return check_launch("tsdf_integrate (bricks)");
     }
     const dim3 grid((unsigned)((a.d.nx + kFuseX - 1) / kFuseX), (unsigned)((a.d.ny + kFuseY - 1) / kFuseY),
@@ -757,6 +783,7 @@ int32_t import_t(const pf_tsdf* v, const float* T, const float* W, hipStream_t s
                            0, s, b, d, T, W);
         hipLaunchKernelGGL(k_bricks_import_fill<FMT>, dim3(kBrickGrid), dim3(kBlock), 0, s, b, d, T, W);
         hipLaunchKernelGGL((k_bricks_cells<FMT, false>), dim3(kBrickGrid), dim3(kBlock), 0, s, b, d, 0);
+        hipLaunchKernelGGL(k_bricks_mask<FMT>, dim3(kBrickGrid), dim3(kBlock), 0, s, b);
         return check_launch("tsdf_import_linear (bricks)");
     }
     hipLaunchKernelGGL(k_import<FMT>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, v->tsdf, v->weight, d, T, W);

@@ -268,10 +268,13 @@ def test_brick_pool_bytes_and_offsets(pf):
         assert coords == index + 2 * _al(nb * 4)          # the index grid, then the candidate list
         assert pool_t == coords + _al(37 * 16)
         assert pool_cells == pool_t + _al(37 * 512 * tb)
-        assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == pool_cells + 37 * 512 * 8 * tb
+        pool_mask = L.tsdf_mask_offset(C.byref(d))        # 8 cell-validity words per slot
+        assert pool_mask == pool_cells + _al(37 * 512 * 8 * tb)
+        assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == pool_mask + 37 * 8 * 8
         assert wb.value == 37 * 512 * wbb
         assert all(x % 256 == 0 for x in (index, coords, pool_t, pool_cells))
-    for nx, ny, nz, mb in ((60, 40, 24, 4), (64, 40, 20, 4), (64, 40, 24, 0), (64, 40, 24, -1)):
+    for nx, ny, nz, mb in ((60, 40, 24, 4), (64, 40, 20, 4), (64, 40, 24, 0), (64, 40, 24, -1),
+                           (64, 40, 24, (1 << 23) + 1)):
         d = _desc(pf, nx, ny, nz, 0, layout=2)
         d.max_bricks = mb
         assert L.tsdf_bytes(C.byref(d), C.byref(wb)) == 0

@@ -5,6 +5,7 @@ Bars: the set of bricks with a slot and every weight bit-exact; T within the rou
 storage format of the FP64 value (the dense fusion's bars); every cell block of every slot equal
 to the 8 stored corners it stands for; scoring, gradients and whole tracked frames bitwise equal
 to the dense CELLS layout loaded with the exported values."""
+import ctypes
 import math
 import sys
 
@@ -248,6 +249,57 @@ def test_bricks_scoring_equals_cells(pf, orc, dev, cfg1, fmt):
     gcc = pf.particles_score_grad(gc, px, py, pz, base)
     for x, y in zip(ga, gcc):
         assert torch.equal(x, y)
+
+
+def check_brick_mask(pf, vol):
+    """Every slot's 8 cell-validity words against its cell blocks: bit l % 64 of word l / 64 is set
+    iff all 8 corners of the cell at local index l are in the band."""
+    _, _, _, Cp, n, _ = raw_pool(pf, vol)
+    off = pf.lib().tsdf_mask_offset(ctypes.byref(vol.desc))
+    words = vol.T.view(torch.uint8)[off:off + 64 * n].view(torch.int64).cpu().numpy().view(np.uint64).reshape(n, 8)
+    if Cp.dtype == np.int16:
+        ok = np.abs(Cp.astype(np.int32)) < 32767
+    else:
+        ok = np.abs(Cp.astype(np.float32)) < 1.0           # NaN-marked corners fail
+    valid = ok.all(axis=2).reshape(n, 8, 64)
+    want = np.packbits(valid, axis=-1, bitorder="little").view("<u8")[..., 0]
+    bad = np.argwhere(words != want)
+    assert bad.size == 0, f"{len(bad)} slot words differ, first (slot, word) {bad[:3].tolist()}"
+    return int(valid.sum())
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+def test_bricks_mask_and_masked_scoring(pf, orc, dev, cfg1, fmt):
+    """The slots' cell-validity words follow fusion and import, and scoring through them (with the
+    compaction, over spreads that reach unallocated bricks and outside the grid) equals scoring
+    without them bit for bit."""
+    say(f"[bricks] cell-validity words and masked scoring, format {fmt}")
+    gb, gc = fused_pair(pf, dev, cfg1, fmt)
+    assert check_brick_mask(pf, gb) > 1000
+    T, W = gb.export_linear()
+    gi = pf.Tsdf(cfg1["vol"], fmt=fmt, device=dev, layout=pf.LAYOUT_BRICKS, max_bricks=4096, init=False)
+    gi.import_linear(T, W)
+    check_brick_mask(pf, gi)
+    xyz, _ = orc.backproject(cfg1["depth2"], cfg1["intr"], 1)
+    far = np.array([[50.0, 0.0, 1.0], [-3.0, 2.0, 0.5]])
+    xt = torch.as_tensor(np.concatenate([xyz, far]).astype(np.float32)).to(dev)
+    pts = (xt[:, 0].contiguous(), xt[:, 1].contiguous(), xt[:, 2].contiguous())
+    try:
+        for K, rot, trans in ((3073, 10.0, 0.1), (257, 1.0, 0.01), (5, 30.0, 0.5)):
+            rng = np.random.default_rng(K + fmt)
+            R0, t0 = cfg1["init2"]
+            poses = [(R0, t0)] + [orc.compose(rng.uniform(-1, 1, 3) * math.radians(rot),
+                                              rng.uniform(-1, 1, 3) * trans, R0, t0) for _ in range(K - 1)]
+            P = torch.as_tensor(pf.poses_to_f32(poses)).to(dev)
+            pf.score_mask(pf.MASK_NEVER)
+            a = pf.particles_score(gb, *pts, P)
+            pf.score_mask(pf.MASK_ALWAYS)
+            b = pf.particles_score(gb, *pts, P)
+            c = pf.particles_score(gc, *pts, P)
+            assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), K
+            assert torch.equal(b[0], c[0]) and torch.equal(b[1], c[1]), K
+    finally:
+        pf.score_mask(pf.MASK_BY_SPREAD)
 
 
 @pytest.mark.parametrize("schedule", ["fixed", "paper_polish"])

@@ -86,6 +86,23 @@ def test_mask_follows_init_and_fusion(pf, dev, cfg1, fmt):
     assert check_mask(vol, fmt, "after re-init") == 0
 
 
+@pytest.mark.parametrize("fmt", [0, 2])
+def test_mask_follows_fusion_ragged_grid(pf, dev, cfg1, fmt):
+    """Fusion into a grid whose dimensions are not multiples of 4 (partial words at the far faces,
+    voxels on word boundaries flagging up to 8 words)."""
+    say(f"[mask] fusion into a 101 x 67 x 93 grid, format {fmt}")
+    s0 = cfg1["vol"]
+    centre = np.array(s0.origin) + 0.5 * (np.array([s0.nx, s0.ny, s0.nz]) - 1) * s0.voxel_size
+    n = np.array([101, 67, 93])
+    spec = synth.VolumeSpec(101, 67, 93, 0.025, 0.1, tuple(centre - 0.5 * (n - 1) * 0.025 + 0.0031))
+    vol = pf.Tsdf(spec, fmt=fmt, device=dev, layout=pf.LAYOUT_CELLS)
+    counts = []
+    for depth, (R, t) in [(cfg1["depth1"], cfg1["gt1"]), (cfg1["depth2"], cfg1["gt2"])]:
+        vol.integrate(torch.as_tensor(depth).to(dev), cfg1["intr"], R, t)
+        counts.append(check_mask(vol, fmt, "after fusion"))
+    assert counts[0] > 1000 and counts[1] != counts[0]
+
+
 @pytest.mark.parametrize("fmt", [0, 1, 2])
 def test_mask_after_import_ragged(pf, dev, fmt):
     """Dimensions that are not multiples of 4 (partial words at the far faces) and values on both

@@ -464,8 +464,9 @@ def test_fullsize_track_frame(pf, orc, dev, cfg2_full):
 
 
 def test_fullsize_regime_forecast_changes_nothing(pf, dev, cfg2_full):
-    """track_frame launches, per iteration, only the scoring shape of the spread regime the same
-    iteration had in the previous call with the same parameters. Whether that forecast is right
+    """track_frame launches, per iteration, only the scoring launch of the spread regime the same
+    iteration had in the previous call with the same parameters (the masked, compacting launch or
+    the per-lane one). Whether that forecast is right
     (same frame again), wrong (forecast from a run started far away) or absent (other parameters
     in between) changes nothing in the result."""
     say("[fullsize] regime forecast: right, wrong and absent give the same frame")

@@ -219,14 +219,16 @@ __device__ inline bool fuse_decide(const FuseArgs& a, int i, int j, int k, doubl
         // FP32 pre-test, conservative: it drops only voxels the FP64 test below drops too. The FP32
         // camera coordinates carry at most ~1e-5 m of error here (|q| < 10 m), so a voxel is
         // dropped as behind the camera only at qz < -1e-3 m, and as outside the image only at
-        // qz > 0.2 m (pixel error < 0.5) and more than two pixels beyond the border.
+        // qz > 0.2 m (pixel error < 0.5) and more than two pixels beyond the border. The
+        // reciprocal is the hardware's (1 ulp): for a pixel within reach of the border its error is
+        // below 1e-3 pixel.
         const float fi = (float)i, fj = (float)j, fk = (float)k;
         const float z32 = a.q0[2] + fi * a.qi[2] + fj * a.qj[2] + fk * a.qk[2];
         if (z32 < -1e-3f) return false;
         if (z32 > 0.2f) {
             const float x32 = a.q0[0] + fi * a.qi[0] + fj * a.qj[0] + fk * a.qk[0];
             const float y32 = a.q0[1] + fi * a.qi[1] + fj * a.qj[1] + fk * a.qk[1];
-            const float iz = 1.0f / z32;
+            const float iz = __builtin_amdgcn_rcpf(z32);
             const float u32 = (float)a.fx * x32 * iz + (float)a.cx;
             const float v32 = (float)a.fy * y32 * iz + (float)a.cy;
             if (!(u32 > -2.5f && u32 < (float)a.width + 1.5f && v32 > -2.5f && v32 < (float)a.height + 1.5f)) return false;
@@ -241,7 +243,7 @@ __device__ inline bool fuse_decide(const FuseArgs& a, int i, int j, int k, doubl
     const double qx = a.R[0] * dx + a.R[3] * dy + a.R[6] * dz;
     const double qy = a.R[1] * dx + a.R[4] * dy + a.R[7] * dz;
     if (qz > 1e-6) {   // (below, FP32 could overflow; the FP64 test decides alone)
-        const float iz = 1.0f / (float)qz;
+        const float iz = __builtin_amdgcn_rcpf((float)qz);
         const float uf32 = (float)a.fx * (float)qx * iz + (float)a.cx;
         const float vf32 = (float)a.fy * (float)qy * iz + (float)a.cy;
         if (!(uf32 > -2.5f && uf32 < (float)a.width + 1.5f && vf32 > -2.5f && vf32 < (float)a.height + 1.5f)) return false;

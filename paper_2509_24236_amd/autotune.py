@@ -18,7 +18,7 @@ from . import BatchPlan, Batch
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_table.json")
 
 CANDIDATES: List[BatchPlan] = [BatchPlan(tk, grid, order)
-                               for tk in (1, 2, 4, 8) for grid in (128, 256, 512, 1024, 2048, 4096)
+                               for tk in (0, 1, 2, 4, 8) for grid in (128, 256, 512, 1024, 2048, 4096)
                                for order in (0, 1)]
 
 

@@ -118,10 +118,12 @@ __global__ __launch_bounds__(256) void kb_next(const BatchProb* tab, const int4*
 }
 
 // Persistent over the (problem, pose group) items. Only the items of problems whose particles are
-// in one of the spread regimes `regimes` (bit r for regime r) are scored (the automatic plan
-// launches one shape per group of regimes, as track_frame does); the others are skipped at the cost
-// of one state read. A problem in a regime of kMaskRegimes reads its replica through the mask.
-template <int FMT, int LAYOUT, int TK, int BLOCK>
+// in one of the spread regimes `regimes` (bit r for regime r) are scored; the others are skipped at
+// the cost of one state read. PATH 0: a problem in a regime of kMaskRegimes reads its cells
+// through the mask, the others take the per-lane path, in one kernel; PATH 1 / 2: the masked
+// (compacting) path or the per-lane path only, each a kernel with its own register and LDS
+// footprint (the automatic plan launches the two, one per regime, as track_frame does).
+template <int FMT, int LAYOUT, int TK, int BLOCK, int PATH = 0>
 __global__ __launch_bounds__(BLOCK) void kb_score(const BatchProb* tab, const int4* items, int n_items, int phase,
                                                   int regimes) {
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -132,8 +134,12 @@ __global__ __launch_bounds__(BLOCK) void kb_score(const BatchProb* tab, const in
         const float *x, *y, *z;
         const int* nd;
         view_of(P, phase, x, y, z, nd);
-        score_step_regime<FMT, LAYOUT, TK, BLOCK>(P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv,
-                                                  regime);
+        if constexpr (PATH == 0)
+            score_step_regime<FMT, LAYOUT, TK, BLOCK>(P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv,
+                                                      regime);
+        else
+            score_step<FMT, LAYOUT, TK, BLOCK, PATH == 1 && LAYOUT != PF_LAYOUT_LINEAR>(
+                P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv);
     }
 }
 
@@ -302,13 +308,16 @@ void launch_score_batch(pf_batch* b, int phase, hipStream_t s) {
                        b->items + b->off_score, b->n_score, phase, (1 << kRegimes) - 1);
 }
 
-// The automatic plan: track_frame's shape (4 poses x 256 threads in both spread regimes), persistent
-// over the item list.
+// The automatic plan: track_frame's launches, 4 poses x 256 threads, one kernel per spread regime
+// (the masked, compacting one for the problems still spread, the per-lane one for the others), each
+// persistent over the item list.
 template <int FMT, int LAYOUT>
 void launch_score_batch_auto(pf_batch* b, int phase, hipStream_t s) {
     const int g = std::min(b->plan.score_grid, b->n_score);
-    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 4, 256>), dim3(g), dim3(256), 0, s, b->tab, b->items + b->off_score,
-                       b->n_score, phase, (1 << kRegimes) - 1);
+    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 4, 256, 1>), dim3(g), dim3(256), 0, s, b->tab,
+                       b->items + b->off_score, b->n_score, phase, kMaskRegimes);
+    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 4, 256, 2>), dim3(g), dim3(256), 0, s, b->tab,
+                       b->items + b->off_score, b->n_score, phase, ((1 << kRegimes) - 1) & ~kMaskRegimes);
 }
 
 template <int FMT, int LAYOUT>

@@ -232,6 +232,7 @@ __device__ inline float trilerp(float f0, float f1, float f2, const float (&c)[8
 // then stands in for the value test. Where most samples miss the band (a wide particle spread),
 // this replaces most 32-byte gathers by reads of a mask that is 1/256 of the replica's size.
 template <int FMT, int LAYOUT, int NP, bool MASK = false>
+__attribute__((always_inline))
 __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, unsigned ly, unsigned lz,
                                   const GridPose (&g)[NP], float x, float y, float z, FixSum (&sum)[NP],
                                   int (&cnt)[NP]) {

@@ -522,6 +522,7 @@ constexpr bool compact_fits() {
 }
 
 template <int FMT, int LAYOUT, int TK, int BLOCK>
+__attribute__((always_inline))
 __device__ inline void score_points_compact(const VolView& vv, const float* __restrict__ px,
                                             const float* __restrict__ py, const float* __restrict__ pz, int n,
                                             const float* __restrict__ poses, int K, int k0, FixSum (&sum)[TK],
@@ -653,6 +654,7 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
 // (uniform, in scalar registers; eval_poses), without the mask or through it when the compacting
 // queues do not fit.
 template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK>
+__attribute__((always_inline))
 __device__ inline void score_points_lanes(const VolView& vv, const float* __restrict__ px,
                                           const float* __restrict__ py, const float* __restrict__ pz, int n,
                                           const float* __restrict__ poses, int K, int k0, FixSum (&sum)[TK],
@@ -694,6 +696,7 @@ __device__ inline void score_points_lanes(const VolView& vv, const float* __rest
 // cell-validity mask when MASK (compacting the valid samples when the queues fit in 32 KB of LDS).
 // The sums are exact, so the result of a pose does not depend on TK, BLOCK, MASK or the workgroup.
 template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK = false>
+__attribute__((always_inline))
 __device__ inline void score_step(const VolView& vv, const float* __restrict__ px, const float* __restrict__ py,
                                   const float* __restrict__ pz, int n, const float* __restrict__ poses, int K, int k0,
                                   float* __restrict__ fitness, int* __restrict__ n_valid) {
@@ -718,6 +721,7 @@ __device__ inline void score_step(const VolView& vv, const float* __restrict__ p
 // score_step through the cell-validity mask when the replica has one and the particles' spread
 // regime `regime` is one of kMaskRegimes (uniform across the workgroup).
 template <int FMT, int LAYOUT, int TK, int BLOCK>
+__attribute__((always_inline))
 __device__ inline void score_step_regime(const VolView& vv, const float* __restrict__ px,
                                          const float* __restrict__ py, const float* __restrict__ pz, int n,
                                          const float* __restrict__ poses, int K, int k0, float* __restrict__ fitness,

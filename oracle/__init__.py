@@ -130,6 +130,8 @@ def lib():
         L.orc_fitness_frozen.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, dp]
         L.orc_polish.restype = C.c_int32
         L.orc_polish.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, C.c_int32, dp]
+        L.orc_best_candidate.restype = C.c_int32
+        L.orc_best_candidate.argtypes = [C.c_double, dp, C.c_int32]
         L.orc_track_frame.restype = C.c_int64
         L.orc_track_frame.argtypes = [P(Vol), P(C.c_float), P(Intr), P(Pose), P(Params), P(Pose), P(IterRec),
                                       P(C.c_int32)]
@@ -399,6 +401,13 @@ def advantage_update(E, deltas, R, t, mode=COMPOSE_DECOUPLED):
     na = lib().orc_advantage_update(_dp(E), _dp(d), K, mode, C.byref(Pose.of(R, t)), C.byref(out), _dp(mean))
     R2, t2 = out.rt()
     return int(na), R2, t2, mean
+
+
+def best_candidate(Estar, E) -> int:
+    """Start of the polish: 0 for the optimized pose (fitness Estar), else the index k >= 1 of the
+    last iteration's particle with the lowest fitness E[k]; ties to the pose, then the lowest k."""
+    E = _f64(E)
+    return int(lib().orc_best_candidate(float(Estar), _dp(E), E.shape[0] - 1))
 
 
 def make_params(seed=3, frame_index=1, n_iters=10, K=256, rates=(1,), pixel_stride=2, s1_deg=5.0, s1_m=0.03,

@@ -875,6 +875,23 @@ int32_t orc_polish(const orc_vol* V, const double* xyz, int64_t n, orc_pose* P, 
 }
 
 /* ----------------------------------------------------------------------------------------
+ * Candidate that the polish starts from (not in the paper; a rule stated here): the lowest
+ * fitness among the optimized pose P^(I) (fitness Estar) and the particles k = 1..K of the last
+ * iteration (fitness E[k], all on the same view). Ties go to P^(I), then to the lowest particle
+ * index. Returns 0 for P^(I), else the particle index k.
+ * ---------------------------------------------------------------------------------------- */
+int32_t orc_best_candidate(double Estar, const double* E, int32_t K) {
+    double Eb = Estar;
+    int32_t kb = 0;
+    for (int32_t k = 1; k <= K; ++k)
+        if (E[k] < Eb) {
+            Eb = E[k];
+            kb = k;
+        }
+    return kb;
+}
+
+/* ----------------------------------------------------------------------------------------
  * Tracking of one frame: back-project with the pixel stride, then n_iters iterations with the
  * rate cycle rates[(i-1) mod n_rates] and s^(1) = (s1_deg, s1_m) (Sec. IV-A), then optional
  * polish of the best of {P^(I)} and the last iteration's particles on the densest view.
@@ -908,17 +925,13 @@ int64_t orc_track_frame(const orc_vol* V, const float* depth, const orc_intr* Ki
         const int last = i == prm->n_iters ||
                          (prm->stop_deg > 0.0 && prm->stop_m > 0.0 && s_rad < stop_rad && s_m < prm->stop_m);
         if (last) {
-            /* best of {P^(i)} (fitness E*) and the particles of iteration i (fitness E_k), all on
-             * S_i; ties go to P^(i), then to the lowest particle index */
-            double Eb = rec.Estar;
+            const int32_t kb = orc_best_candidate(rec.Estar, Ek, iter_K(prm, i));
             best = P;
-            for (int32_t k = 1; k <= iter_K(prm, i); ++k)
-                if (Ek[k] < Eb) {
-                    double dr[3], dt[3];
-                    orc_draw_delta(prm->seed, prm->frame_index, i, k, sr_prev, sm_prev, dr, dt);
-                    orc_compose(prm->compose_mode, dr, dt, &Pprev, &best);
-                    Eb = Ek[k];
-                }
+            if (kb > 0) {
+                double dr[3], dt[3];
+                orc_draw_delta(prm->seed, prm->frame_index, i, kb, sr_prev, sm_prev, dr, dt);
+                orc_compose(prm->compose_mode, dr, dt, &Pprev, &best);
+            }
             break;
         }
     }

@@ -276,7 +276,9 @@ int32_t backproject(const float* depth, const pf_intrinsics* K, int32_t pixel_st
  * px, py, pz: device, n_pts floats (camera coordinates, metres), n_pts >= 1.
  * poses: device, [K][12] float32, row-major 3x4 [R | t] camera -> world.
  * fitness: device, K floats; n_valid: device, K int32 (|X_k|).
- * Sums are FP32 in a fixed order, so results are bitwise reproducible. */
+ * Each valid |T| is converted to 32-bit fixed point (units of 2^-32; 2^-17 stored units for
+ * int16) and summed exactly in 64-bit integers, so E_k does not depend on the launch shape or on
+ * how points are split: results are bitwise reproducible. E_k = sum / |X_k| rounded to FP32. */
 int32_t particles_score(const pf_tsdf* v, const float* px, const float* py, const float* pz,
                         int32_t n_pts, const float* poses, int32_t K, float* fitness,
                         int32_t* n_valid, void* stream);
@@ -303,7 +305,8 @@ int32_t particles_score_grad(const pf_tsdf* v, const float* px, const float* py,
  * needs >= 256), or 0 and 0 (the default) for the automatic shape, 4 poses x 256 threads (fewer
  * poses per workgroup when K is too small to fill the GPU); track_frame then also picks, per
  * iteration, the launch of the spread regime of the search size that drew its particles (see
- * pf_score_mask). Process-wide. Fitness sums are exact (64-bit fixed point), so every shape, and
+ * pf_score_mask). Process-wide: a launch in flight on another thread takes the old or the new
+ * shape. Fitness sums are exact (64-bit fixed point), so every shape, and
  * the batched path, gives bitwise identical results; the shape changes speed only. Returns
  * PF_EINVAL for an unsupported shape. */
 int32_t pf_score_config(int32_t poses_per_group, int32_t group_size);
@@ -425,7 +428,8 @@ void track_batch_destroy(pf_batch* b);
 /* Kernel timing of the particle-scoring launches made by track_frame: when enabled, each such
  * launch is bracketed by HIP events on the call's stream and, once track_frame has synchronised,
  * the elapsed times, the number of launches and the number of evaluated (pose, point) samples
- * (sum of poses x points per launch) are accumulated in process-wide counters. */
+ * (sum of poses x points per launch) are accumulated. Switch, events and counters belong to the
+ * calling host thread: enable and read on the thread that calls track_frame. */
 int32_t pf_timing_enable(int32_t on);
 
 /* Reads the counters (any pointer may be NULL) and optionally resets them. */

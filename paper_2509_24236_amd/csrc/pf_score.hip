@@ -16,6 +16,8 @@
 // contraction, so it runs on the vector ALUs, not on the matrix cores.
 #include <math.h>
 
+#include <atomic>
+
 #include "pf_steps.hpp"
 
 namespace pf {
@@ -44,13 +46,15 @@ int32_t launch_t(const VolView& vv, const Points& p, const float* poses, int K, 
 
 
 // Launch shape of the many-pose scoring launches (pf_score_config): poses per workgroup and
-// workgroup size, or 0 and 0 for the shape by spread regime (the default).
-int g_tk = 0, g_block = 0;
+// workgroup size, or 0 and 0 for the shape by spread regime (the default). Process-wide settings
+// read by every caller; atomics, so a change while another thread launches is no data race (that
+// launch takes the old or the new shape, which gives the same bits: the sums are exact).
+std::atomic<int> g_tk{0}, g_block{0};
 
 // Spread regimes whose automatic launches read the cell-validity mask (pf_score_mask), bit r for
 // regime r; kMaskAlways also masks the launches without a spread (particles_score).
 constexpr int kMaskAlways = 8;
-int g_mask_regimes = kMaskRegimes;
+std::atomic<int> g_mask_regimes{kMaskRegimes};
 
 // Automatic shape for K poses: 4x256 (measured at K = 3073: the masked, compacting launch of the
 // spread regime ran the headline sequence at 4.01 ms per frame at 4x256, 4.09 at 2x256, 4.16 at

@@ -11,6 +11,8 @@
 namespace pf {
 
 // ------------------------------------------------------------------ optional kernel timing
+// Per host thread: each thread that calls track_frame brackets its own launches with its own
+// events and accumulates its own counters, so concurrent callers do not share event slots.
 struct Timing {
     bool on = false;
     double ms = 0.0;
@@ -18,7 +20,7 @@ struct Timing {
     hipEvent_t ev[2 * (PF_MAX_ITERS + 1)] = {};
     bool created = false;
 };
-static Timing g_timing;
+thread_local Timing g_timing;
 
 int32_t timing_enable(int on) {
     if (on && !g_timing.created) {

@@ -11,7 +11,8 @@
  *           Arguments are validated before any launch; on PF_EINVAL nothing was enqueued.
  * Memory:   every pointer documented as "device" is caller-owned device memory of the current
  *           HIP device (for example torch tensors). The library never allocates or frees
- *           device memory in these calls; scratch space is passed in as `workspace`.
+ *           device memory in these calls; scratch space is passed in as `workspace` (except in
+ *           track_frame_noalloc, whose workspace is a fixed array the library holds per GPU).
  *           "host" pointers are read during the call only.
  * Streams:  `stream` is a hipStream_t (NULL = the default stream). All work is enqueued on it
  *           and the calls return without waiting, except where a call says it synchronises.
@@ -374,6 +375,21 @@ size_t track_workspace_bytes(const pf_intrinsics* K, const pf_track_params* p);
 int32_t track_frame(const pf_tsdf* v, const float* depth, const pf_intrinsics* K,
                     const pf_pose* init, const pf_track_params* p, pf_pose* out,
                     pf_track_stats* stats, void* workspace, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): track_frame with its workspace in an array the library holds on each GPU instead
+ * of a caller buffer. Same arguments, results and synchronisation as track_frame, bit for bit,
+ * without workspace and ws_bytes. The array is PF_NOALLOC_WORKSPACE_BYTES per GPU (enough for
+ * 1280x960 depth at PF_MAX_K particles); it is set up on the first call on a device and held until
+ * the process ends. The call allocates and frees nothing. A call whose track_workspace_bytes()
+ * exceeds the array returns PF_ENOMEM with a message, before any launch. Every call on a GPU
+ * uses that GPU's one array: calls that overlap on one GPU (other host threads, or other streams
+ * before this call has returned) race and must be serialised by the caller. Nothing in the
+ * array needs clearing between calls; each call rewrites what it reads. */
+#define PF_NOALLOC_WORKSPACE_BYTES (32u << 20)
+int32_t track_frame_noalloc(const pf_tsdf* v, const float* depth, const pf_intrinsics* K,
+                            const pf_pose* init, const pf_track_params* p, pf_pose* out,
+                            pf_track_stats* stats, void* stream);
 
 /* ------------------------------------------------------------------------------ batches */
 

@@ -6,6 +6,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "pf_internal.hpp"
 
 namespace pf {
@@ -236,6 +238,36 @@ int32_t check_problem(const pf_batch_problem& q, int idx) {
     return PF_OK;
 }
 
+// Workspace of track_frame_noalloc: one array per GPU, held until the process ends. In host code
+// `scratch` names a host-side stand-in, not device memory: its device address is looked up once
+// per device (with that device current) and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[PF_NOALLOC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's `scratch`, looked up on the first call on that device.
+int32_t scratch_of_current_device(void** ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(PF_EHIP, "track_frame_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(PF_EUNSUPPORTED, "track_frame_noalloc: device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(PF_EHIP, "track_frame_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return PF_OK;
+}
+}  // namespace
+
 }  // namespace pf
 
 using namespace pf;
@@ -426,6 +458,23 @@ int32_t track_frame(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
     if ((rc = check_params(p, "track_frame"))) return rc;
     if (!depth || !out || !workspace) return set_error(PF_EINVAL, "track_frame: null pointer");
     return track(v, depth, K, init, p, out, stats, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int32_t track_frame_noalloc(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* init,
+                            const pf_track_params* p, pf_pose* out, pf_track_stats* stats, void* stream) {
+    int32_t rc;
+    if ((rc = check_tsdf(v, "track_frame_noalloc", false))) return rc;
+    if ((rc = check_intr(K, "track_frame_noalloc"))) return rc;
+    if ((rc = check_pose(init, "track_frame_noalloc"))) return rc;
+    if ((rc = check_params(p, "track_frame_noalloc"))) return rc;
+    if (!depth || !out) return set_error(PF_EINVAL, "track_frame_noalloc: null pointer");
+    const size_t need = workspace_bytes(K, p);
+    if (need > (size_t)PF_NOALLOC_WORKSPACE_BYTES)
+        return set_error(PF_ENOMEM, "track_frame_noalloc: needs %zu bytes of workspace, the library's array holds %zu",
+                         need, (size_t)PF_NOALLOC_WORKSPACE_BYTES);
+    void* ws = nullptr;
+    if ((rc = scratch_of_current_device(&ws))) return rc;
+    return track(v, depth, K, init, p, out, stats, ws, (size_t)PF_NOALLOC_WORKSPACE_BYTES, (hipStream_t)stream);
 }
 
 int32_t pf_timing_enable(int32_t on) { return timing_enable(on); }

@@ -199,6 +199,34 @@ def test_params_validation(pf):
     assert L.track_workspace_bytes(C.byref(intr), C.byref(c)) == 0
 
 
+def test_noalloc_rejects_before_launch(pf):
+    """track_frame_noalloc validates like track_frame, and refuses a frame whose workspace would not
+    fit the library's array with PF_ENOMEM, before touching a device."""
+    L = pf.lib()
+    init = pf.make_pose(np.eye(3), np.zeros(3))
+    out = pf.pf_pose()
+    p = C.c_void_p(0x4000)
+    intr = pf.pf_intrinsics(120.0, 120.0, 80.0, 60.0, 160, 120)
+    c = pf.TrackParams(K=256, n_iters=10, rates=(1,), pixel_stride=2).c()
+    c.K = -3
+    _rc(pf, L.track_frame_noalloc(C.byref(_desc(pf)), p, C.byref(intr), C.byref(init), C.byref(c), C.byref(out),
+                                  None, None), "K")
+    c.K = 256
+    _rc(pf, L.track_frame_noalloc(C.byref(_desc(pf)), None, C.byref(intr), C.byref(init), C.byref(c), C.byref(out),
+                                  None, None), "null")
+    big = pf.pf_intrinsics(1000.0, 1000.0, 960.0, 540.0, 1920, 1080)
+    c = pf.TrackParams(K=65536, n_iters=20, rates=(8, 16, 32), pixel_stride=1).c()
+    need = L.track_workspace_bytes(C.byref(big), C.byref(c))
+    assert need > pf.NOALLOC_WORKSPACE_BYTES
+    rc = L.track_frame_noalloc(C.byref(_desc(pf)), p, C.byref(big), C.byref(init), C.byref(c), C.byref(out), None,
+                               None)
+    assert rc == pf.PF_ENOMEM
+    assert str(need) in pf.last_error() and "array holds" in pf.last_error()
+    # the largest frame the header promises fits: 1280x960 at the maximum particle count
+    c960 = pf.pf_intrinsics(700.0, 700.0, 640.0, 480.0, 1280, 960)
+    assert 0 < L.track_workspace_bytes(C.byref(c960), C.byref(c)) <= pf.NOALLOC_WORKSPACE_BYTES
+
+
 def test_batch_validation(pf):
     L = pf.lib()
     q = (pf.pf_batch_problem * 2)()

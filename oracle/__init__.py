@@ -115,6 +115,8 @@ def lib():
         L.orc_fitness.argtypes = [P(Vol), dp, C.c_int64, P(Pose), dp, i64p]
         L.orc_fitness_many.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, dp, i64p]
         L.orc_fitness_interval_many.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, C.c_double, dp, dp, i64p]
+        L.orc_fitness_interval_rounded_many.argtypes = [P(Vol), dp, C.c_int64, P(Pose), C.c_int32, C.c_double,
+                                                        C.c_double, C.c_double, dp, dp]
         L.orc_draw_delta.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, dp, dp]
         L.orc_ro_iteration.argtypes = [P(Vol), dp, C.c_int64, P(Params), C.c_int32, P(Pose), dp, dp, dp, i64p, P(IterRec)]
         L.orc_advantage_update.restype = C.c_int64
@@ -306,6 +308,17 @@ class Volume:
         lib().orc_fitness_interval_many(C.byref(self.c()), _dp(x), x.shape[0], arr, K, eps, _dp(lo), _dp(hi),
                                         na.ctypes.data_as(C.POINTER(C.c_int64)))
         return lo, hi, na
+
+    def fitness_interval_rounded_many(self, xyz, poses: Sequence, eps=1e-3, qrel=0.0, qabs=0.0):
+        """[E_lo, E_hi] over every storage rounding of this volume's values by at most
+        qrel |T| + qabs per voxel (and the near-face cell choices within eps)."""
+        x = _f64(xyz)
+        K = len(poses)
+        arr = (Pose * K)(*[Pose.of(R, t) for R, t in poses])
+        lo, hi = np.zeros(K), np.zeros(K)
+        lib().orc_fitness_interval_rounded_many(C.byref(self.c()), _dp(x), x.shape[0], arr, K, eps, qrel, qabs,
+                                                _dp(lo), _dp(hi))
+        return lo, hi
 
     def fitness_grad(self, xyz, R, t, mode=COMPOSE_DECOUPLED):
         x = _f64(xyz)

@@ -457,6 +457,97 @@ void orc_fitness_interval_many(const orc_vol* V, const double* xyz, int64_t n, c
     for (int32_t k = 0; k < K; ++k) orc_fitness_interval(V, xyz, n, P + k, eps, E_lo + k, E_hi + k, n_amb + k);
 }
 
+/* Interval form for a volume held in a rounded storage format (form (1): scaled int16 or FP16
+ * values). Each stored corner may differ from its FP64 value x by up to d(x) = qrel |x| + qabs
+ * (int16: half a step of 1/32767; FP16: half an ulp, at most 2^-11 |x|), on top of which the
+ * near-face rule of orc_fitness_interval applies. Per cell choice, a corner with |x| >= 1 is out of
+ * the band in any storage (rounding keeps it at or beyond 1); one with 1 - d(x) <= |x| < 1 may land
+ * on either side, so a sample with such a corner may or may not be valid; otherwise the sample is
+ * valid and, the trilinear weights summing to 1, its value moves by at most the largest d of its 8
+ * corners. The bounds combine samples as orc_fitness_interval does (smallest and largest |value|
+ * contribution, largest and smallest count), so [E_lo, E_hi] holds the fitness of every volume
+ * within those roundings. With qrel = qabs = 0 it is orc_fitness_interval. */
+static int sample_cell_rounded(const orc_vol* V, const double g[3], const int64_t c[3], double qrel, double qabs,
+                               double* amin, double* amax) {
+    /* returns 0: invalid in every storage; 1: valid; 2: either */
+    if (c[0] < 0 || c[1] < 0 || c[2] < 0 || c[0] > V->nx - 2 || c[1] > V->ny - 2 || c[2] > V->nz - 2) return 0;
+    double f[3] = {g[0] - (double)c[0], g[1] - (double)c[1], g[2] - (double)c[2]};
+    double t[2][2][2];
+    double dmax = 0.0;
+    int edge = 0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                int64_t idx = ((c[2] + dz) * V->ny + (c[1] + dy)) * V->nx + (c[0] + dx);
+                double x = V->T[idx];
+                if (!(fabs(x) < 1.0)) return 0;
+                double d = qrel * fabs(x) + qabs;
+                if (fabs(x) >= 1.0 - d) edge = 1;
+                if (d > dmax) dmax = d;
+                t[dz][dy][dx] = x;
+            }
+    double a00 = t[0][0][0] + f[0] * (t[0][0][1] - t[0][0][0]);
+    double a10 = t[0][1][0] + f[0] * (t[0][1][1] - t[0][1][0]);
+    double a01 = t[1][0][0] + f[0] * (t[1][0][1] - t[1][0][0]);
+    double a11 = t[1][1][0] + f[0] * (t[1][1][1] - t[1][1][0]);
+    double b0 = a00 + f[1] * (a10 - a00);
+    double b1 = a01 + f[1] * (a11 - a01);
+    double v = fabs(b0 + f[2] * (b1 - b0));
+    *amin = v > dmax ? v - dmax : 0.0;
+    *amax = v + dmax;
+    return edge ? 2 : 1;
+}
+
+void orc_fitness_interval_rounded(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P, double eps,
+                                  double qrel, double qabs, double* E_lo, double* E_hi) {
+    double s_lo = 0.0, s_hi = 0.0;
+    int64_t c_lo = 0, c_hi = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        double y[3], g[3];
+        transform(P, xyz + 3 * j, y);
+        grid_coord(V, y, g);
+        int64_t opts[3][2];
+        int nopt[3];
+        for (int a = 0; a < 3; ++a) {
+            double fl = floor(g[a]);
+            opts[a][0] = (int64_t)fl;
+            nopt[a] = 1;
+            double fr = g[a] - fl;
+            if (fr < eps) { opts[a][1] = (int64_t)fl - 1; nopt[a] = 2; }
+            else if (fr > 1.0 - eps) { opts[a][1] = (int64_t)fl + 1; nopt[a] = 2; }
+        }
+        double amin = 2.0, amax = -1.0;
+        int cmin = 1, cmax = 0;
+        for (int ox = 0; ox < nopt[0]; ++ox)
+            for (int oy = 0; oy < nopt[1]; ++oy)
+                for (int oz = 0; oz < nopt[2]; ++oz) {
+                    int64_t c[3] = {opts[0][ox], opts[1][oy], opts[2][oz]};
+                    double lo = 0.0, hi = 0.0;
+                    int st = sample_cell_rounded(V, g, c, qrel, qabs, &lo, &hi);
+                    /* an invalid outcome contributes 0 with count 0 */
+                    double olo = st == 1 ? lo : 0.0, ohi = st == 0 ? 0.0 : hi;
+                    int ocmin = st == 1 ? 1 : 0, ocmax = st == 0 ? 0 : 1;
+                    if (olo < amin) amin = olo;
+                    if (ohi > amax) amax = ohi;
+                    if (ocmin < cmin) cmin = ocmin;
+                    if (ocmax > cmax) cmax = ocmax;
+                }
+        s_lo += amin;
+        s_hi += amax;
+        c_lo += cmin;
+        c_hi += cmax;
+    }
+    *E_lo = c_hi > 0 ? s_lo / (double)c_hi : 1.0;
+    *E_hi = c_lo > 0 ? s_hi / (double)c_lo : 1.0;
+    if (c_lo == 0) *E_hi = 1.0 > *E_hi ? 1.0 : *E_hi;
+}
+
+void orc_fitness_interval_rounded_many(const orc_vol* V, const double* xyz, int64_t n, const orc_pose* P,
+                                       int32_t K, double eps, double qrel, double qabs, double* E_lo, double* E_hi) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t k = 0; k < K; ++k) orc_fitness_interval_rounded(V, xyz, n, P + k, eps, qrel, qabs, E_lo + k, E_hi + k);
+}
+
 /* ----------------------------------------------------------------------------------------
  * Randomized optimization of one frame (Sec. III-B; schedule of Sec. IV-A).
  * ---------------------------------------------------------------------------------------- */

@@ -109,3 +109,68 @@ def test_autotuner_records_a_plan(pf, problems, tmp_path):
     best = autotune.tune(problems, cands, reps=2, path=path, log=say)
     assert best in cands
     assert autotune.plan_for(problems, path) == best
+
+
+@pytest.fixture(scope="module")
+def problems16(pf):
+    """Sixteen problems of the batching workload (seeds 40..55): all four resolutions, K from 256 to
+    4096 (the drawn counts, with the two ends of the range forced on problems 13 and 1)."""
+    dev = torch.device("cuda:0")
+    out = []
+    for p in range(16):
+        d = synth.random_depth_for_batch(p)
+        K = {13: 256, 1: 4096}.get(p, d["K"])
+        vol = pf.Tsdf(d["vol"], device=dev)
+        vol.integrate(torch.as_tensor(d["depth1"]).to(dev), d["intr"], np.eye(3), np.zeros(3))
+        prm = pf.TrackParams(seed=40 + p, frame_index=1, n_iters=10, K=K, rates=(1,), pixel_stride=2,
+                             s1_deg=10.0, s1_m=0.10)
+        out.append((vol, torch.as_tensor(d["depth2"]).to(dev), d["intr"], *d["init2"], prm))
+    torch.cuda.synchronize()
+    return out
+
+
+def test_batch_matches_oracle(pf, orc, problems16):
+    """Every problem of a 16-problem batch (the autotuner's plan) lands within 1 mm / 0.05 deg of the
+    FP64 oracle's track_frame on that problem's own volume with the same random stream."""
+    import math
+    from paper_2509_24236_amd import autotune
+    widths = sorted({p[2].width for p in problems16})
+    Ks = [p[5].K for p in problems16]
+    say(f"[batch] 16 problems, widths {widths}, K {min(Ks)}..{max(Ks)}, plan {autotune.plan_for(problems16)}")
+    assert widths == [160, 320, 480, 640] and min(Ks) == 256 and max(Ks) == 4096
+    b = pf.Batch(problems16, autotune.plan_for(problems16))
+    b.run()
+    got = b.results()
+    b.close()
+    worst = (0.0, 0.0)
+    for q, ((vol, depth, intr, R0, t0, prm), (R, t, st)) in enumerate(zip(problems16, got)):
+        T, W = vol.export_linear()
+        ov = orc.Volume(vol.spec, T=T.cpu().numpy().astype(np.float64), W=W.cpu().numpy())
+        del T, W
+        oprm = orc.make_params(seed=prm.seed, frame_index=1, n_iters=10, K=prm.K, rates=(1,), pixel_stride=2,
+                               s1_deg=10.0, s1_m=0.10)
+        Ro, to, recs = ov.track_frame(depth.cpu().numpy(), intr, R0, t0, oprm)
+        dr, dt = math.degrees(orc.rot_err(R, Ro)), float(np.linalg.norm(t - to))
+        worst = (max(worst[0], dr), max(worst[1], dt))
+        say(f"    problem {q}: {intr.width}x{intr.height}, K {prm.K}: vs oracle {dr:.2e} deg {dt * 1e3:.2e} mm")
+        assert dr <= 0.05 and dt <= 1e-3, f"problem {q}"
+        assert [st.n_sub[i] for i in range(10)] == [r.n_pts for r in recs]
+        del ov
+    say(f"    worst {worst[0]:.2e} deg, {worst[1] * 1e3:.2e} mm")
+
+
+def test_batch_rate_cycle_equals_plain(pf, problems):
+    """The batched sub-sampled views (rates 8, 16, 32 over every pixel) and the per-rate partial sums
+    of E* reproduce track_frame bit for bit, under two plans."""
+    import dataclasses
+    say("[batch] rates 8/16/32 at pixel stride 1, 9 iterations, batched vs plain")
+    probs = [(v, d, k, R, t, dataclasses.replace(prm, n_iters=9, rates=(8, 16, 32), pixel_stride=1))
+             for v, d, k, R, t, prm in problems]
+    ref = plain(pf, probs)
+    for plan in (pf.BatchPlan(0, 1024, 1), pf.BatchPlan(2, 512, 0)):
+        b = pf.Batch(probs, plan)
+        b.run()
+        got = b.results()
+        b.close()
+        same(got, ref)
+        assert [list(s.n_sub[:9]) for _, _, s in got] == [list(s.n_sub[:9]) for _, _, s in ref]

@@ -232,6 +232,18 @@ __device__ inline Partial* state_partials(pf_track_state* st, int K) {
     return reinterpret_cast<Partial*>(reinterpret_cast<char*>(st) + partials_offset(K));
 }
 
+// The second set of partials: the pose just computed scored on the next iteration's view, which is
+// that iteration's E_0 (slot 0), so the particle launch scores the K particles alone.
+__device__ inline Partial* state_partials_next(pf_track_state* st, int K) { return state_partials(st, K) + kMaxPartials; }
+
+// The view of the next iteration (x == nullptr: none).
+struct NextView {
+    const float* x;
+    const float* y;
+    const float* z;
+    const int* n_dev;
+};
+
 
 constexpr int kAdvThreads = 256;
 
@@ -245,10 +257,15 @@ constexpr int kAdvThreads = 256;
 // same fixed order (so all compute the same P^(i) in FP64), then scores P^(i) on its chunk of
 // S_i; the chunk's (sum, count) goes to the partials. ADV = false scores the pending pose P
 // (used for the returned pose's final fitness).
+//
+// With a next view `nv` (x != nullptr), the workgroup also scores the new pose (ADV) or the pending
+// pose (not ADV) on its chunk of that view, into the second set of partials: next_step turns them
+// into the next iteration's E_0. Without ADV the first set is then left alone.
 template <int FMT, int LAYOUT, bool ADV>
 __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px, const float* __restrict__ py,
                                 const float* __restrict__ pz, int n_host, const int* __restrict__ n_dev,
-                                const float* __restrict__ fitness, pf_track_state* st, int K, int blk, int nblk) {
+                                const float* __restrict__ fitness, pf_track_state* st, int K, int blk, int nblk,
+                                NextView nv = NextView{nullptr, nullptr, nullptr, nullptr}) {
     if (st->K != K) {
         if (blk == 0 && threadIdx.x == 0) st->flags |= 1;
         return;
@@ -339,34 +356,81 @@ __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px,
         }
     }
     __syncthreads();
-    // this workgroup's chunk of the view, scored with the scoring kernel's arithmetic
+    // this workgroup's chunk of the view (and of the next view), scored with the scoring kernel's
+    // arithmetic
     const Gather<FMT, LAYOUT> G = make_gather<FMT, LAYOUT>(vv);
     GridPose g[1] = {fold_pose(pose_sh, vv.inv_vs, vv.gx0, vv.gy0, vv.gz0)};
     const unsigned lx = (unsigned)(vv.nx - 1), ly = (unsigned)(vv.ny - 1), lz = (unsigned)(vv.nz - 1);
-    const int chunk = (n + nblk - 1) / nblk;
-    const int q0 = blk * chunk, q1 = min(n, q0 + chunk);
-    FixSum sum[1] = {0};
-    int cnt[1] = {0};
     const float sc = vv.inv_vs;
-    for (int q = q0 + (int)threadIdx.x; q < q1; q += kAdvThreads)
-        eval_poses<FMT, LAYOUT, 1>(G, lx, ly, lz, g, px[q] * sc, py[q] * sc, pz[q] * sc, sum, cnt);
-    block_reduce<1, kAdvThreads>(sum, cnt);
-    if (threadIdx.x == 0) {
-        Partial* pt = state_partials(st, K);
-        pt[blk].sum = sum[0];
-        pt[blk].cnt = cnt[0];
-    }
-    __syncthreads();
+    auto chunk_sums = [&](const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
+                          int m, Partial* pt) {
+        const int chunk = (m + nblk - 1) / nblk;
+        const int q0 = blk * chunk, q1 = min(m, q0 + chunk);
+        FixSum sum[1] = {0};
+        int cnt[1] = {0};
+        for (int q = q0 + (int)threadIdx.x; q < q1; q += kAdvThreads)
+            eval_poses<FMT, LAYOUT, 1>(G, lx, ly, lz, g, x[q] * sc, y[q] * sc, z[q] * sc, sum, cnt);
+        block_reduce<1, kAdvThreads>(sum, cnt);
+        if (threadIdx.x == 0) {
+            pt[blk].sum = sum[0];
+            pt[blk].cnt = cnt[0];
+        }
+        __syncthreads();
+    };
+    if (ADV || !nv.x) chunk_sums(px, py, pz, n, state_partials(st, K));
+    if (nv.x) chunk_sums(nv.x, nv.y, nv.z, *nv.n_dev, state_partials_next(st, K));
 }
 
 // Completes iteration i (unless FIRST) and draws the K particles of the next one:
 // E* from the partials in order, s^(i+1) = s^(i) (beta + (1 - beta) E*), then particle k is the
 // delta (omega a[0:3], v a[3:6]) with a from the counter stream, composed with P^(i) in FP64 and
 // rounded to FP32; slot 0 is P^(i). FIRST draws iteration 1 around the initial state.
+//
+// e0_partials > 0: the second set of partials (that many) holds P^(i) (FIRST: the initial pose)
+// scored on the drawn iteration's view, and workgroup 0 writes that E_0 and its count to fit0[0] and
+// nv0[0], the slot 0 the particle launch no longer scores.
+template <int FMT>
+__device__ inline void partials_sum(const Partial* pt, int n_partials, FixSum& out_sum, int& out_cnt) {
+    __shared__ FixSum rs[256 / kWave];
+    __shared__ int rc[256 / kWave];
+    FixSum sum = 0;
+    int cnt = 0;
+    for (int b = threadIdx.x; b < n_partials; b += 256) {
+        sum += pt[b].sum;
+        cnt += pt[b].cnt;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        sum += __shfl_xor(sum, off);
+        cnt += __shfl_xor(cnt, off);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        rs[threadIdx.x / kWave] = sum;
+        rc[threadIdx.x / kWave] = cnt;
+    }
+    __syncthreads();
+    out_sum = 0;
+    out_cnt = 0;
+    for (int w = 0; w < 256 / kWave; ++w) {
+        out_sum += rs[w];
+        out_cnt += rc[w];
+    }
+    __syncthreads();
+}
+
 template <int FMT, bool FIRST>
 __device__ inline void next_step(pf_track_state* st, int K, int n_partials, int draw, float* next_poses, IterRec* recs,
-                                 int blk) {
+                                 int blk, int e0_partials = 0, float* fit0 = nullptr, int* nv0 = nullptr) {
     if (st->K != K || st->done) return;
+    if (e0_partials > 0 && draw && blk == 0) {
+        FixSum sum;
+        int cnt;
+        partials_sum<FMT>(state_partials_next(st, K), e0_partials, sum, cnt);
+        if (threadIdx.x == 0) {
+            fit0[0] = fitness_from<FMT>(sum, cnt);
+            nv0[0] = cnt;
+        }
+    }
     __shared__ double sh_s[2];
     __shared__ int sh_cnt;
     __shared__ float sh_E;

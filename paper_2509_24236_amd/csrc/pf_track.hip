@@ -82,14 +82,16 @@ template <int FMT, int LAYOUT, bool ADV>
 __global__ __launch_bounds__(kAdvThreads) void k_adv(VolView vv, const float* __restrict__ px,
                                                      const float* __restrict__ py, const float* __restrict__ pz,
                                                      int n_host, const int* __restrict__ n_dev,
-                                                     const float* __restrict__ fitness, pf_track_state* st, int K) {
-    adv_step<FMT, LAYOUT, ADV>(vv, px, py, pz, n_host, n_dev, fitness, st, K, blockIdx.x, gridDim.x);
+                                                     const float* __restrict__ fitness, pf_track_state* st, int K,
+                                                     NextView nv) {
+    adv_step<FMT, LAYOUT, ADV>(vv, px, py, pz, n_host, n_dev, fitness, st, K, blockIdx.x, gridDim.x, nv);
 }
 
 template <int FMT, bool FIRST>
 __global__ __launch_bounds__(256) void k_next(pf_track_state* st, int K, int n_partials, int draw,
-                                              float* next_poses, IterRec* recs) {
-    next_step<FMT, FIRST>(st, K, n_partials, draw, next_poses, recs, blockIdx.x);
+                                              float* next_poses, IterRec* recs, int e0_partials, float* fit0,
+                                              int* nv0) {
+    next_step<FMT, FIRST>(st, K, n_partials, draw, next_poses, recs, blockIdx.x, e0_partials, fit0, nv0);
 }
 
 }  // namespace
@@ -103,33 +105,37 @@ namespace {
 
 template <int FMT, int LAYOUT>
 int32_t launch_adv_t(bool adv, const VolView& vv, const Points& p, int G, const float* fitness, pf_track_state* st,
-                     int K, hipStream_t s) {
+                     int K, const NextView& nv, hipStream_t s) {
     if (adv)
         hipLaunchKernelGGL((k_adv<FMT, LAYOUT, true>), dim3(G), dim3(kAdvThreads), 0, s, vv, p.x, p.y, p.z, p.n,
-                           p.n_dev, fitness, st, K);
+                           p.n_dev, fitness, st, K, nv);
     else
         hipLaunchKernelGGL((k_adv<FMT, LAYOUT, false>), dim3(G), dim3(kAdvThreads), 0, s, vv, p.x, p.y, p.z, p.n,
-                           p.n_dev, fitness, st, K);
+                           p.n_dev, fitness, st, K, nv);
     return check_launch("particles_update");
 }
 
 // adv = true: advantage set, P^(i) and the partials of E*; false: partials of the pending pose.
+// With a next view, also the partials of that pose on it (the next iteration's E_0).
 int32_t launch_adv(bool adv, const VolView& vv, const Points& p, int G, const float* fitness, pf_track_state* st,
-                   int K, hipStream_t s) {
+                   int K, hipStream_t s, const NextView& nv = NextView{nullptr, nullptr, nullptr, nullptr}) {
     return with_volume(vv.format, vv.layout, [&](auto fmt, auto layout) {
-        return launch_adv_t<decltype(fmt)::value, decltype(layout)::value>(adv, vv, p, G, fitness, st, K, s);
+        return launch_adv_t<decltype(fmt)::value, decltype(layout)::value>(adv, vv, p, G, fitness, st, K, nv, s);
     });
 }
 
+// e0_partials > 0: also turns the second partials into the drawn iteration's E_0 at fit0[0] / nv0[0].
 int32_t launch_next(int format, bool first, pf_track_state* st, int K, int G, bool draw, float* next_poses,
-                    IterRec* recs, hipStream_t s) {
+                    IterRec* recs, hipStream_t s, int e0_partials = 0, float* fit0 = nullptr, int* nv0 = nullptr) {
     const int blocks = draw ? (K + 1 + 255) / 256 : 1;
     const int d = draw ? 1 : 0;
-#define PF_NEXT(F)                                                                                              \
-    if (first)                                                                                                  \
-        hipLaunchKernelGGL((k_next<F, true>), dim3(blocks), dim3(256), 0, s, st, K, G, d, next_poses, recs); \
-    else                                                                                                        \
-        hipLaunchKernelGGL((k_next<F, false>), dim3(blocks), dim3(256), 0, s, st, K, G, d, next_poses, recs);
+#define PF_NEXT(F)                                                                                             \
+    if (first)                                                                                                 \
+        hipLaunchKernelGGL((k_next<F, true>), dim3(blocks), dim3(256), 0, s, st, K, G, d, next_poses, recs,   \
+                           e0_partials, fit0, nv0);                                                            \
+    else                                                                                                       \
+        hipLaunchKernelGGL((k_next<F, false>), dim3(blocks), dim3(256), 0, s, st, K, G, d, next_poses, recs,  \
+                           e0_partials, fit0, nv0);
     switch (format) {
         case PF_F32_W_F32: PF_NEXT(PF_F32_W_F32) break;
         case PF_F16_W_U8: PF_NEXT(PF_F16_W_U8) break;
@@ -210,7 +216,7 @@ WsLayout ws_layout(const pf_intrinsics* K, const pf_track_params* p) {
     L.nv = off;
     off += align_up((size_t)(p->K + 1) * sizeof(int));
     L.state = off;
-    off += align_up(partials_offset(p->K) + kMaxPartials * sizeof(Partial));
+    off += align_up(partials_offset(p->K) + 2 * kMaxPartials * sizeof(Partial));
     L.recs = off;
     off += align_up(PF_MAX_ITERS * sizeof(IterRec) + 2 * sizeof(int));
     L.polish = off;
@@ -223,7 +229,7 @@ WsLayout ws_layout(const pf_intrinsics* K, const pf_track_params* p) {
 
 }  // namespace
 
-size_t state_bytes(int K) { return partials_offset(K) + kMaxPartials * sizeof(Partial); }
+size_t state_bytes(int K) { return partials_offset(K) + 2 * kMaxPartials * sizeof(Partial); }
 
 pf_track_state initial_state(const pf_pose* init, const pf_track_params* p) { return make_state(init, p); }
 
@@ -360,7 +366,18 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
                            K->width, vs);
         if ((rc = check_launch("track_frame views"))) return rc;
     }
-    if ((rc = state_init(st, init, p, vv.format, poses, s))) return rc;
+    // the initial state, the initial pose scored on the first view (slot 0 of iteration 1) and
+    // the particles of iteration 1
+    {
+        pf_track_state h = make_state(init, p);
+        hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, s, st, h);
+        if ((rc = check_launch("track_frame"))) return rc;
+        const Points& S1 = views[0];
+        const NextView nv1{S1.x, S1.y, S1.z, S1.n_dev};
+        const int G1 = n_partials_for((int)((npix + p->rates[0] - 1) / p->rates[0]));
+        if ((rc = launch_adv(false, vv, S1, G1, fit, st, p->K, s, nv1))) return rc;
+        if ((rc = launch_next(vv.format, true, st, p->K, 0, true, poses, nullptr, s, G1, fit, nv))) return rc;
+    }
     const bool timed = g_timing.on;
     const bool forecast = forecast_matches(g_forecast, p, vv.inv_vs);
     int Gv[3];
@@ -371,11 +388,20 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
         const int K_i = p->alt_K ? p->Ks[r] : p->K;
         if (timed) (void)hipEventRecord(g_timing.ev[2 * (i - 1)], s);
         const int expect = forecast ? g_forecast.regime[i - 1] : -1;
-        if ((rc = launch_score(vv, S, poses, K_i + 1, fit, nv, s, st, expect))) return rc;
+        // the particles 1..K_i; slot 0 (E_0, the current pose on this view) was scored by the
+        // previous update step
+        const Points Sp{S.x, S.y, S.z, S.n, S.n_dev};
+        if ((rc = launch_score(vv, Sp, poses + 12, K_i, fit + 1, nv + 1, s, st, expect))) return rc;
         if (timed) (void)hipEventRecord(g_timing.ev[2 * (i - 1) + 1], s);
-        if ((rc = launch_adv(true, vv, S, Gv[r], fit, st, p->K, s))) return rc;
-        // the last iteration only completes (E*, s); its particles stay in `poses` / `fit`
-        if ((rc = launch_next(vv.format, false, st, p->K, Gv[r], i < p->n_iters, poses, recs, s))) return rc;
+        // the update also scores the new pose on the next iteration's view (its slot 0); the last
+        // iteration only completes (E*, s), its particles stay in `poses` / `fit`
+        const bool more = i < p->n_iters;
+        const int rn = i % p->n_rates;
+        const int G = more ? (Gv[r] > Gv[rn] ? Gv[r] : Gv[rn]) : Gv[r];
+        const NextView nvn = more ? NextView{views[rn].x, views[rn].y, views[rn].z, views[rn].n_dev}
+                                  : NextView{nullptr, nullptr, nullptr, nullptr};
+        if ((rc = launch_adv(true, vv, S, G, fit, st, p->K, s, nvn))) return rc;
+        if ((rc = launch_next(vv.format, false, st, p->K, G, more, poses, recs, s, more ? G : 0, fit, nv))) return rc;
     }
     // optional gradient polish of the best candidate, on the densest view
     int densest = 0;
@@ -429,7 +455,7 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
             float ms = 0.0f;
             if (hipEventElapsedTime(&ms, g_timing.ev[2 * i], g_timing.ev[2 * i + 1]) == hipSuccess) g_timing.ms += ms;
             g_timing.launches += 1;
-            g_timing.evals += (int64_t)(hr[i].n_particles + 1) * hr[i].n_sub;
+            g_timing.evals += (int64_t)hr[i].n_particles * hr[i].n_sub;
         }
     }
     for (int q = 0; q < 9; ++q) out->R[q] = hs.R[q];

@@ -181,7 +181,7 @@ def test_params_validation(pf):
     _rc(pf, rc, "K")
     assert L.particles_state_bytes(0) == 0
     # header, then the FP64 deltas at 512, then 256-byte aligned per-workgroup partials
-    assert L.particles_state_bytes(10) == 512 + 768 + 256 * 16
+    assert L.particles_state_bytes(10) == 512 + 768 + 2 * 256 * 16
     # the paper's schedule: Ks paired with the rates, each in 1..K; a finite, non-negative stop size
     sched = pf.TrackParams(K=256, n_iters=10, rates=(1, 2, 3), pixel_stride=2, Ks=(64, 128, 256), stop_deg=0.05,
                            stop_m=0.0005)

@@ -83,21 +83,43 @@ def test_adjoint_parity_1000_poses(pf, orc, dev, setup, mode):
 @pytest.mark.parametrize("mode", [0, 1])
 def test_adjoint_chain_vs_central_differences(pf, orc, dev, setup, mode):
     """dE/dxi at xi != 0 vs central differences (h = 1e-4) of the oracle's frozen objective."""
-    say(f"[grad] chain rule vs central differences, mode {mode}")
+    say(f"[grad] chain rule vs central differences, 1000 poses, mode {mode}")
     d, v32, gv, X32, pts = setup
+    B = 1000
     rng = np.random.default_rng(31)
-    poses = cfg3_poses(orc, d, 16, seed=32)
-    xi = np.concatenate([rng.uniform(-0.02, 0.02, (16, 3)), rng.uniform(-0.06, 0.06, (16, 3))], 1)
+    poses = cfg3_poses(orc, d, B, seed=32)
+    xi = np.concatenate([rng.uniform(-0.02, 0.02, (B, 3)), rng.uniform(-0.06, 0.06, (B, 3))], 1)
     base = torch.as_tensor(rows(poses)).to(dev)
     E, g, nv = pf.particles_score_grad(gv, *pts, base, torch.as_tensor(xi).to(dev), mode)
     g = g.cpu().numpy().astype(np.float64)
-    worst = 0.0
+    X64 = X32.astype(np.float64)
+    # Bound per pose and component. The frozen set (cells and signs) can differ between the GPU's
+    # FP32 pose and the oracle's FP64 one only for samples within rounding of a cell face or of a
+    # zero of T; the oracle's interval [lo, hi] at the FP32 pose takes every such choice for the
+    # gradient with respect to a delta applied there, and the gradient with respect to xi is that
+    # one through J(phi)^T (and, LITERAL, a rho x term): with |phi| <= 0.11 and |rho| <= 0.035 m its
+    # rows sum to less than 1.25, so |gpu - fd| <= 1.25 max(hi - lo) + arithmetic. The
+    # arithmetic is a fixed-order FP32 sum of ~4800 terms, ~(log2 4800 + 2) 2^-24 = 9e-7 of the
+    # terms' magnitudes, times the cancellation of the sum (below 20 here), plus O(h^2) = 1e-8 of
+    # the central differences: 2e-5 of the gradient's largest component.
+    comp = [orc.compose(xi[b, 3:], xi[b, :3], R, t, mode) for b, (R, t) in enumerate(poses)]
+    P32 = pf.poses_to_f32(comp).astype(np.float64).reshape(-1, 3, 4)
+    lo, hi = v32.fitness_grad_interval_many(X64, [(P[:, :3], P[:, 3]) for P in P32], mode, eps=1e-3, sign_eps=1e-4)
+    width = np.repeat((hi - lo)[:, 1:].max(1, keepdims=True), 6, 1)
+    dev_abs = np.zeros((B, 6))
+    scale = np.zeros(B)
     for b, (R, t) in enumerate(poses):
-        ref = v32.grad_xi_fd(X32.astype(np.float64), R, t, xi[b], mode, h=1e-4)
-        err = np.abs(g[b] - ref).max() / np.abs(ref).max()
-        worst = max(worst, err)
-    say(f"    worst relative deviation {worst:.2e}")
-    assert worst <= 5e-3
+        ref = v32.grad_xi_fd(X64, R, t, xi[b], mode, h=1e-4)
+        dev_abs[b] = np.abs(g[b] - ref)
+        scale[b] = np.abs(ref).max()
+    err = dev_abs.max(1) / scale
+    bound = 1.25 * width + 2e-5 * scale[:, None]
+    q = np.percentile(err, [50, 90, 99, 100])
+    say(f"    relative deviation: median {q[0]:.2e}, 90% {q[1]:.2e}, 99% {q[2]:.2e}, max {q[3]:.2e}; largest "
+        f"deviation over its bound {np.max(dev_abs / bound):.2f}; interval width / gradient median "
+        f"{np.median(width.max(1) / scale):.2e}")
+    bad = np.flatnonzero((dev_abs > bound).any(1))
+    assert bad.size == 0, f"{bad.size} poses beyond the bound, e.g. {bad[:5]}"
 
 
 def test_autograd_function(pf, orc, dev, setup):

@@ -388,7 +388,8 @@ __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px,
 //
 // e0_partials > 0: the second set of partials (that many) holds P^(i) (FIRST: the initial pose)
 // scored on the drawn iteration's view, and workgroup 0 writes that E_0 and its count to fit0[0] and
-// nv0[0], the slot 0 the particle launch no longer scores.
+// nv0[0], the slot 0 the particle launch no longer scores (or, after the last iteration, the
+// returned pose's fitness on the densest view).
 template <int FMT>
 __device__ inline void partials_sum(const Partial* pt, int n_partials, FixSum& out_sum, int& out_cnt) {
     __shared__ FixSum rs[256 / kWave];
@@ -422,7 +423,7 @@ template <int FMT, bool FIRST>
 __device__ inline void next_step(pf_track_state* st, int K, int n_partials, int draw, float* next_poses, IterRec* recs,
                                  int blk, int e0_partials = 0, float* fit0 = nullptr, int* nv0 = nullptr) {
     if (st->K != K || st->done) return;
-    if (e0_partials > 0 && draw && blk == 0) {
+    if (e0_partials > 0 && blk == 0) {
         FixSum sum;
         int cnt;
         partials_sum<FMT>(state_partials_next(st, K), e0_partials, sum, cnt);

@@ -78,6 +78,32 @@ __global__ __launch_bounds__(256) void k_view_scatter(const float* px, const flo
 
 __global__ void k_state_set(pf_track_state* st, pf_track_state init) { *st = init; }
 
+// What track_frame reads back at the end of a frame, gathered into one block so that one copy
+// brings it to the host.
+struct Readback {
+    pf_track_state st;
+    IterRec recs[PF_MAX_ITERS];
+    float ef;
+    int nvf, nall, accepted;
+};
+
+__global__ __launch_bounds__(256) void k_readback(const pf_track_state* st, const IterRec* recs, const float* ef,
+                                                  const int* nvf, const int* nall, const int* accepted,
+                                                  Readback* rb) {
+    const unsigned* a = reinterpret_cast<const unsigned*>(st);
+    unsigned* b = reinterpret_cast<unsigned*>(&rb->st);
+    for (int q = threadIdx.x; q < (int)(sizeof(pf_track_state) / 4); q += 256) b[q] = a[q];
+    const unsigned* c = reinterpret_cast<const unsigned*>(recs);
+    unsigned* d = reinterpret_cast<unsigned*>(rb->recs);
+    for (int q = threadIdx.x; q < (int)(sizeof(rb->recs) / 4); q += 256) d[q] = c[q];
+    if (threadIdx.x == 0) {
+        rb->ef = *ef;
+        rb->nvf = *nvf;
+        rb->nall = *nall;
+        rb->accepted = accepted ? *accepted : 0;
+    }
+}
+
 template <int FMT, int LAYOUT, bool ADV>
 __global__ __launch_bounds__(kAdvThreads) void k_adv(VolView vv, const float* __restrict__ px,
                                                      const float* __restrict__ py, const float* __restrict__ pz,
@@ -174,7 +200,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
     size_t pts, pix, counts, views[3], tiles_mask[3], tiles_start[3], vcount, poses, fit, nv, state, recs, polish, fin,
-        total;
+        rb, total;
 };
 
 WsLayout ws_layout(const pf_intrinsics* K, const pf_track_params* p) {
@@ -223,6 +249,8 @@ WsLayout ws_layout(const pf_intrinsics* K, const pf_track_params* p) {
     off += align_up(polish_scratch_bytes(kMaxPartials));
     L.fin = off;
     off += align_up(256 + kMaxPartials * 8);
+    L.rb = off;
+    off += align_up(sizeof(Readback));
     L.total = off;
     return L;
 }
@@ -382,6 +410,14 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
     const bool forecast = forecast_matches(g_forecast, p, vv.inv_vs);
     int Gv[3];
     for (int r = 0; r < p->n_rates; ++r) Gv[r] = n_partials_for((int)((npix + p->rates[r] - 1) / p->rates[r]));
+    int densest = 0;
+    for (int r = 1; r < p->n_rates; ++r)
+        if (p->rates[r] < p->rates[densest]) densest = r;
+    float* ef_dev = reinterpret_cast<float*>(recs + PF_MAX_ITERS);
+    int* nvf_dev = reinterpret_cast<int*>(ef_dev + 1);
+    // With no polish and no stop rule the returned pose is P^(I): the last update step scores it on
+    // the densest view as it goes (E_final), instead of a separate pass after the loop.
+    const bool final_in_loop = p->polish_steps == 0 && !(p->stop_deg > 0.0 && p->stop_m > 0.0);
     for (int i = 1; i <= p->n_iters; ++i) {
         const int r = (i - 1) % p->n_rates;
         const Points& S = views[r];
@@ -396,40 +432,41 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
         // the update also scores the new pose on the next iteration's view (its slot 0); the last
         // iteration only completes (E*, s), its particles stay in `poses` / `fit`
         const bool more = i < p->n_iters;
-        const int rn = i % p->n_rates;
-        const int G = more ? (Gv[r] > Gv[rn] ? Gv[r] : Gv[rn]) : Gv[r];
-        const NextView nvn = more ? NextView{views[rn].x, views[rn].y, views[rn].z, views[rn].n_dev}
-                                  : NextView{nullptr, nullptr, nullptr, nullptr};
+        const int rn = more ? i % p->n_rates : densest;
+        const bool second = more || final_in_loop;
+        const int G = second ? (Gv[r] > Gv[rn] ? Gv[r] : Gv[rn]) : Gv[r];
+        const NextView nvn = second ? NextView{views[rn].x, views[rn].y, views[rn].z, views[rn].n_dev}
+                                    : NextView{nullptr, nullptr, nullptr, nullptr};
         if ((rc = launch_adv(true, vv, S, G, fit, st, p->K, s, nvn))) return rc;
-        if ((rc = launch_next(vv.format, false, st, p->K, G, more, poses, recs, s, more ? G : 0, fit, nv))) return rc;
+        if ((rc = launch_next(vv.format, false, st, p->K, G, more, poses, recs, s, second ? G : 0,
+                              more ? fit : ef_dev, more ? nv : nvf_dev)))
+            return rc;
     }
     // optional gradient polish of the best candidate, on the densest view
-    int densest = 0;
-    for (int r = 1; r < p->n_rates; ++r)
-        if (p->rates[r] < p->rates[densest]) densest = r;
     if (p->polish_steps > 0 &&
         (rc = launch_polish(vv, views[densest], Gv[densest], st, p->K, fit, p->compose_mode, v->voxel_size,
                             p->polish_steps, ws + L.polish, s)))
         return rc;
     // fitness of the returned pose on the densest view
-    float* ef_dev = reinterpret_cast<float*>(recs + PF_MAX_ITERS);
-    int* nvf_dev = reinterpret_cast<int*>(ef_dev + 1);
-    if ((rc = launch_state_fitness(vv, views[densest], Gv[densest], st, ws + L.fin, ef_dev, nvf_dev, s))) return rc;
+    if (!final_in_loop &&
+        (rc = launch_state_fitness(vv, views[densest], Gv[densest], st, ws + L.fin, ef_dev, nvf_dev, s)))
+        return rc;
 
-    pf_track_state hs;
-    IterRec hr[PF_MAX_ITERS];
-    float ef;
-    int nvf, nall, accepted = 0;
-    if (hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(hr, recs, sizeof(IterRec) * p->n_iters, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(&ef, ef_dev, sizeof ef, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(&nvf, nvf_dev, sizeof nvf, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(&nall, vcount, sizeof nall, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        (p->polish_steps > 0 && hipMemcpyAsync(&accepted, ws + L.polish + polish_accepted_offset(), sizeof accepted,
-                                               hipMemcpyDeviceToHost, s) != hipSuccess))
+    Readback* rb = reinterpret_cast<Readback*>(ws + L.rb);
+    hipLaunchKernelGGL(k_readback, dim3(1), dim3(256), 0, s, st, recs, ef_dev, nvf_dev, vcount,
+                       p->polish_steps > 0 ? reinterpret_cast<const int*>(ws + L.polish + polish_accepted_offset())
+                                           : nullptr,
+                       rb);
+    if ((rc = check_launch("track_frame read-back"))) return rc;
+    Readback hrb;
+    if (hipMemcpyAsync(&hrb, rb, sizeof hrb, hipMemcpyDeviceToHost, s) != hipSuccess)
         return set_error(PF_EHIP, "track_frame: read-back failed: %s", hipGetErrorString(hipGetLastError()));
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return set_error(PF_EHIP, "track_frame: %s", hipGetErrorString(e));
+    const pf_track_state& hs = hrb.st;
+    const IterRec* hr = hrb.recs;
+    const float ef = hrb.ef;
+    const int nvf = hrb.nvf, nall = hrb.nall, accepted = hrb.accepted;
     if (hs.flags) return set_error(PF_EINVAL, "track_frame: inconsistent optimizer state (flags %d)", hs.flags);
     // iterations that ran (all n_iters unless the stop rule ended the optimization)
     const int n_run = hs.iter_done;

@@ -29,6 +29,25 @@ if ROOT not in sys.path:
 METRIC = "particle·point fitness evals/s + ms/frame (track+fuse) at 640×480, 3072 particles"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_EVAL = 32  # 8 stencil corners x 4 B (validity is carried by T, W is not read)
+FUSE_BYTES_PER_VOXEL = 16   # T and W (FP32) read and written for each voxel a fusion updates
+# Vector-ALU peak in lane operations per second: 256 compute units x 4 SIMDs x 16 lanes x 2.4 GHz (a
+# wave of 64 lanes issues one instruction per 4 cycles on a SIMD); an FMA counts as one operation.
+# The 157.3 TFLOP/s FP32 figure counts an FMA as two flops and doubles again for packed FP32.
+CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
+VALU_CYCLES_PER_INST = 4
+VALU_PEAK_TOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_HZ / 1e12
+# The method's vector arithmetic per sample (pose k, point x): the transform into grid coordinates
+# (9 multiply-adds, the voxel size and origin folded into the pose), floor and fraction on 3 axes (6),
+# the in-grid test (3), the cell index (2), the trilinear interpolation (7 lerps of a subtraction and a
+# multiply-add: 14), and the absolute value converted and added to the pose's sum and count (4).
+OPS_PER_EVAL = 9 + 6 + 3 + 2 + 14 + 4
+
+
+def rot_err(Ra, Rb):
+    """Angle of Ra^T Rb (radians)."""
+    import numpy as np
+    c = (np.trace(np.asarray(Ra).T @ np.asarray(Rb)) - 1.0) / 2.0
+    return math.acos(max(-1.0, min(1.0, float(c))))
 
 
 def log(msg):
@@ -98,7 +117,7 @@ def cpu_baseline(frames, vol_spec, intr, n_frames, seconds, schedule="fixed"):
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_score_sequence_counters.txt")
-SCORE_SOURCES = ("pf_sample.hpp", "pf_steps.hpp", "pf_score.hip", "pf_internal.hpp")
+SCORE_SOURCES = ("pf_sample.hpp", "pf_score_steps.hpp", "pf_score.hip", "pf_internal.hpp")
 
 
 def score_source_hash():
@@ -116,12 +135,11 @@ def score_source_hash():
     return h.hexdigest()
 
 
-def counter_traffic(avg_launch_ms):
-    """HBM traffic of one scoring launch from the committed FETCH_SIZE / WRITE_SIZE summary, each
-    scaled by what the counter reads for a plain copy of known size, as GB/s over the measured
-    average launch time. None when there is no summary or the kernel changed since it was taken."""
+def read_counters():
+    """The committed counter summary of the scoring launch, as a dict of numbers, or None when there is
+    none or the scoring kernel's sources changed since it was taken."""
     if not os.path.exists(COUNTERS):
-        return None, None
+        return None
     vals = {}
     with open(COUNTERS) as f:
         for line in f:
@@ -129,10 +147,48 @@ def counter_traffic(avg_launch_ms):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("score_source_sha256") != score_source_hash():
-        return None, None
-    per_launch = (float(vals["fetch_kib_per_dispatch"]) * 1024.0 * float(vals["fetch_scale"]) +
-                  float(vals["write_kib_per_dispatch"]) * 1024.0 * float(vals["write_scale"]))
-    return per_launch / (avg_launch_ms * 1e-3) / 1e9, per_launch
+        return None
+    return {k: float(v) for k, v in vals.items() if k != "score_source_sha256"}
+
+
+def roofline(avg_launch_ms, evals_per_launch):
+    """Roofline of the particle-scoring launch. The launch is bound by vector-ALU issue (the counters
+    show HBM traffic far below peak and the VALU busy), so `achieved` is the method's own vector
+    arithmetic per sample (OPS_PER_EVAL lane operations) times the samples per launch over the
+    launch's measured time, against the chip's lane-operation rate. The committed counter summary, when
+    it matches the kernel's sources, adds the measured instruction issue, HBM traffic (FETCH_SIZE +
+    WRITE_SIZE scaled by a plain copy's reading) and L2 figures, scaled to this run's samples per
+    launch."""
+    t = avg_launch_ms * 1e-3
+    achieved = OPS_PER_EVAL * evals_per_launch / t / 1e12
+    out = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+           "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+           "kernel": "particles_score per iteration (k_score<f32, cells>, 4 poses x 256 threads, K poses; through "
+                     "the cell-validity mask with compaction while the particles are spread over more than a quarter "
+                     "voxel), timed with HIP events on its stream",
+           "ops_per_eval": OPS_PER_EVAL, "avg_launch_ms": avg_launch_ms, "evals_per_launch": evals_per_launch,
+           "algorithmic_stencil_GBps": BYTES_PER_EVAL * evals_per_launch / t / 1e9,
+           "counters": None}
+    c = read_counters()
+    if c:
+        scale = evals_per_launch / c["evals_per_dispatch"]
+        traffic_bytes = (c["fetch_kib_per_dispatch"] * c["fetch_scale"] +
+                         c["write_kib_per_dispatch"] * c["write_scale"]) * 1024.0 * scale
+        out["traffic"] = traffic_bytes / t / 1e9
+        out["traffic_bytes_per_launch"] = traffic_bytes
+        l1l2 = c["tcp_tcc_read_req_per_dispatch"] * 64.0 * scale
+        hit, miss = c["tcc_hit_per_dispatch"], c["tcc_miss_per_dispatch"]
+        valu = c["valu_insts_per_dispatch"] * scale
+        out["counters"] = {
+            "valu_issue_frac": valu * VALU_CYCLES_PER_INST / (CUS * SIMDS_PER_CU * CLOCK_HZ) / t,
+            "valu_lane_insts_per_eval": c["valu_insts_per_dispatch"] * 64.0 / c["evals_per_dispatch"],
+            "hbm_GBps": out["traffic"], "hbm_frac": out["traffic"] / HBM_PEAK_GBS,
+            "l2_hit_rate": hit / max(1.0, hit + miss),
+            "l1_to_l2_GBps": l1l2 / t / 1e9,
+            "gather_efficiency": BYTES_PER_EVAL * evals_per_launch / max(1.0, l1l2),
+            "source": os.path.relpath(COUNTERS, ROOT),
+        }
+    return out
 
 
 def copy_calibration():
@@ -659,6 +715,8 @@ def main():
                     help="sequence, accuracy: dense = the 512^3 cell-replica grid centred on the room (the "
                          "headline); bricks = a sparse brick pool over the whole room at the same 1 cm voxels")
     ap.add_argument("--max-bricks", type=int, default=120000, help="bricks: pool slots")
+    ap.add_argument("--only-tracked", action="store_true",
+                    help="sequence: skip the run fused at the ground-truth poses (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures the single-GPU path only (--gpus {args.gpus} requested); the multi-GPU "
@@ -691,7 +749,7 @@ def main():
 
     pf.lib()
     dev = torch.device("cuda:0")
-    n_frames = args.warmup + args.steps + 1
+    n_frames = args.warmup + args.steps + 2
     log(f"[bench] rendering {n_frames} frames of the paper-scale sequence")
     frames = synth.cfg2_frames(n_frames)
     intr, spec = frames["intr"], frames["vol"]
@@ -714,61 +772,94 @@ def main():
     trk = pf.Tracker(intr, params, device=dev)
     torch.cuda.synchronize()
 
-    est = [(np.eye(3), np.zeros(3))]
-    vol.integrate(depth[0], intr, *est[0])
+    def run_sequence(fuse_at_gt):
+        """Fuses frame 0 at the identity, then tracks and fuses frames 1.. (the warm-up ones untimed).
+        Each frame starts from the previous estimate composed with the stand-in; the frame is fused at
+        the tracked pose, or (fuse_at_gt) at the ground-truth pose."""
+        vol.init()
+        est = [(np.eye(3), np.zeros(3))]
+        vol.integrate(depth[0], intr, *est[0])
+        iters_run, fuse_events, method_evals = [], [], [0]
 
-    iters_run = []
-    fuse_events = []
-    method_evals = [0]
+        def step(t):
+            Rp, tp = est[t - 1]
+            Rr, tr = rel[t]
+            R0, t0 = Rp @ Rr, Rp @ tr + tp            # P_t^(0) = P_{t-1} P_(t,t-1)
+            trk.set_frame(t)
+            R, tt, st = trk.track(vol, depth[t], R0, t0)
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            ev[0].record()
+            vol.integrate(depth[t], intr, *(frames["gt"][t] if fuse_at_gt else (R, tt)))
+            ev[1].record()
+            fuse_events.append(ev)
+            est.append((R, tt))
+            iters_run.append(st.n_iters)
+            # the method's samples: each iteration scores its particles and the current pose on S_i
+            method_evals[0] += sum((st.n_particles[i] + 1) * st.n_sub[i] for i in range(st.n_iters))
 
-    def step(t):
-        Rp, tp = est[t - 1]
-        Rr, tr = rel[t]
-        R0, t0 = Rp @ Rr, Rp @ tr + tp            # P_t^(0) = P_{t-1} P_(t,t-1)
-        trk.set_frame(t)
-        R, tt, st = trk.track(vol, depth[t], R0, t0)
-        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-        ev[0].record()
-        vol.integrate(depth[t], intr, R, tt)
-        ev[1].record()
-        fuse_events.append(ev)
-        est.append((R, tt))
-        iters_run.append(st.n_iters)
-        # the method's samples: each iteration scores its particles and the current pose on S_i
-        method_evals[0] += sum((st.n_particles[i] + 1) * st.n_sub[i] for i in range(st.n_iters))
-        return st
+        for t in range(1, args.warmup + 1):
+            step(t)
+        torch.cuda.synchronize()
+        pf.timing_enable(True)
+        pf.timing_read(reset=True)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        del iters_run[:]
+        del fuse_events[:]
+        method_evals[0] = 0
+        for t in range(args.warmup + 1, args.warmup + args.steps + 1):
+            step(t)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        score_ms, launches, evals = pf.timing_read(reset=True)
+        pf.timing_enable(False)
+        fuse_ms = sum(a.elapsed_time(b) for a, b in fuse_events) / max(1, len(fuse_events))
+        t_err = [float(np.linalg.norm(est[t][1] - frames["gt"][t][1])) for t in range(1, len(est))]
+        r_err = [math.degrees(rot_err(est[t][0], frames["gt"][t][0])) for t in range(1, len(est))]
+        return {"elapsed": elapsed, "ms_per_frame": 1e3 * elapsed / args.steps, "method_evals": method_evals[0],
+                "score_ms": score_ms, "launches": launches, "evals": evals, "fuse_ms": fuse_ms,
+                "iters_run": iters_run, "est": est,
+                "gt_error": {"translation_median_mm": 1e3 * float(np.median(t_err)),
+                             "translation_max_mm": 1e3 * float(np.max(t_err)),
+                             "rotation_median_deg": float(np.median(r_err)),
+                             "frames": len(t_err)}}
 
-    log(f"[bench] warmup {args.warmup} frames")
-    for t in range(1, args.warmup + 1):
-        step(t)
-    torch.cuda.synchronize()
-    pf.timing_enable(True)
-    pf.timing_read(reset=True)
-    log(f"[bench] timing {args.steps} frames")
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    del iters_run[:]
-    del fuse_events[:]
-    method_evals[0] = 0
-    for t in range(args.warmup + 1, args.warmup + args.steps + 1):
-        step(t)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    score_ms, launches, evals = pf.timing_read(reset=True)
-    pf.timing_enable(False)
-    ms_per_frame = 1e3 * elapsed / args.steps
+    log(f"[bench] sequence fused at the tracked poses: warmup {args.warmup}, timing {args.steps} frames")
+    run = run_sequence(False)
+    run_gt = None
+    if not args.only_tracked:
+        log(f"[bench] sequence fused at the ground-truth poses (reported beside)")
+        run_gt = run_sequence(True)
+    elapsed, launches, evals, score_ms = run["elapsed"], run["launches"], run["evals"], run["score_ms"]
+    ms_per_frame = run["ms_per_frame"]
     avg_launch_ms = score_ms / max(1, launches)
-    achieved = BYTES_PER_EVAL * (evals / max(1, launches)) / (avg_launch_ms * 1e-3) / 1e9
-    traffic, traffic_bytes = counter_traffic(avg_launch_ms)
-    fuse_ms = sum(a.elapsed_time(b) for a, b in fuse_events) / max(1, len(fuse_events))
-    gt_err = [np.linalg.norm(est[t][1] - frames["gt"][t][1]) for t in range(1, len(est))]
+    evals_per_launch = evals / max(1, launches)
+    fuse_ms = run["fuse_ms"]
     log(f"[bench] {ms_per_frame:.3f} ms/frame, scoring {avg_launch_ms:.4f} ms/launch avg, "
         f"{evals / max(score_ms, 1e-9) * 1e3:.3e} evals/s in-kernel; GT translation error median "
-        f"{1e3 * float(np.median(gt_err)):.2f} mm")
+        f"{run['gt_error']['translation_median_mm']:.2f} mm" +
+        (f" (fused at the truth: {run_gt['ms_per_frame']:.3f} ms/frame, "
+         f"{run_gt['gt_error']['translation_median_mm']:.2f} mm)" if run_gt else ""))
 
+    # fusion roofline: the voxels one fusion updates (W grows), from one more frame after the timing
+    n_next = args.warmup + args.steps + 1
+    W0 = vol.export_linear()[1]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    vol.integrate(depth[n_next], intr, *frames["gt"][n_next])
+    e1.record()
+    torch.cuda.synchronize()
+    W1 = vol.export_linear()[1]
+    n_upd = int((W1 != W0).sum().item())
+    del W0, W1
+    fuse1_ms = e0.elapsed_time(e1)
+    fuse_bytes = FUSE_BYTES_PER_VOXEL * n_upd + 4 * intr.width * intr.height
+    torch.cuda.empty_cache()
+
+    roof = roofline(avg_launch_ms, evals_per_launch)
     out = {
         "metric": METRIC,
-        "value": method_evals[0] / elapsed,
+        "value": run["method_evals"] / elapsed,
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -781,34 +872,35 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "paper-scale sequence: 640x480 depth, 512^3 FP32 TSDF at 1 cm (tau 4 cm), 3072 particles x "
-                        "20 iterations at point rates 1/8, 1/16, 1/32, then fusion; one step = one frame"
+                        "20 iterations at point rates 1/8, 1/16, 1/32, then fusion at the tracked pose; one step = "
+                        "one frame"
                         if args.schedule == "fixed" else
                         "paper-scale sequence: 640x480 depth, 512^3 FP32 TSDF at 1 cm (tau 4 cm), particles "
                         "alternating 1024 / 3072 / 10240 with point rates 1/8, 1/16, 1/32, at most 20 iterations, "
-                        "stop once the search size is below (0.05 deg, 0.5 mm), then fusion; one step = one frame",
+                        "stop once the search size is below (0.05 deg, 0.5 mm), then fusion at the tracked pose; "
+                        "one step = one frame",
             "frames_timed": args.steps,
             "particles": K if args.schedule == "fixed" else [1024, 3072, 10240],
             "iterations": I,
-            "mean_iterations_run": sum(iters_run) / max(1, len(iters_run)),
+            "mean_iterations_run": sum(run["iters_run"]) / max(1, len(run["iters_run"])),
             "tsdf": "512^3 f32 T + f32 W, cell-major f32 replica and cell-validity mask for scoring",
             "fusion_ms_per_frame": fuse_ms,
             "volume_bytes": vol_bytes,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "particles_score per iteration: k_score<f32, cells> in the shape of the particles' spread "
-                      "regime (4 poses x 256 threads; through the cell-validity mask with compaction while the "
-                      "particles are spread over more than a quarter voxel), forecast from the previous frame",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "traffic_bytes_per_launch": traffic_bytes,
-            "avg_launch_ms": avg_launch_ms,
-            "launches": launches,
-            "evals_per_launch": evals / max(1, launches),
-        },
+        "accuracy": {"vs_ground_truth": run["gt_error"],
+                     "note": "the tracked trajectory drifts (the method as read does not track this sequence); the "
+                             "same sequence fused at the ground-truth poses is timed beside it"},
+        "fused_at_ground_truth": None if run_gt is None else {
+            "value": run_gt["method_evals"] / run_gt["elapsed"], "unit": "evals/s",
+            "ms_per_step": run_gt["ms_per_frame"], "fusion_ms_per_frame": run_gt["fuse_ms"],
+            "scoring_ms_per_launch": run_gt["score_ms"] / max(1, run_gt["launches"]),
+            "vs_ground_truth": run_gt["gt_error"]},
+        "roofline": roof,
+        "fusion_roofline": {"bound": "hbm", "achieved": fuse_bytes / (fuse1_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": fuse_bytes / (fuse1_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                            "updated_voxels": n_upd, "bytes": fuse_bytes, "ms": fuse1_ms,
+                            "note": f"{FUSE_BYTES_PER_VOXEL} B per updated voxel (T and W read and written) plus the "
+                                    "depth image, over one fusion of the frame after the timed ones"},
     }
     if args.volume == "bricks":
         used, overflow = vol.bricks_used()
@@ -822,7 +914,7 @@ def main():
                      f"voxels), {used * 512 / (spec.nx * spec.ny * spec.nz):.1%} of them stored")
         c["bricks_used"] = used
         out["roofline"]["kernel"] = ("particles_score per iteration: k_score<f32, bricks>, 4 poses x 256 threads")
-        out["roofline"]["traffic"] = out["roofline"]["traffic_bytes_per_launch"] = None
+        out["roofline"]["counters"] = out["roofline"]["traffic"] = None
         log(f"[bench] bricks {used}, fusion {fuse_ms:.3f} ms/frame, volume {vol_bytes / 2**30:.2f} GiB")
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")

@@ -18,7 +18,7 @@
 
 #include <atomic>
 
-#include "pf_steps.hpp"
+#include "pf_score_steps.hpp"
 
 namespace pf {
 namespace {

@@ -26,4 +26,20 @@ def test_counter_summary_matches_the_scoring_sources():
             vals[k.strip()] = v.strip()
     assert vals["score_source_sha256"] == bench.score_source_hash(), \
         "the scoring kernel changed since profiles/k_score_sequence_counters.txt was taken"
-    assert float(vals["fetch_scale"]) > 0 and float(vals["write_scale"]) > 0
+    for k in ("evals_per_dispatch", "fetch_kib_per_dispatch", "write_kib_per_dispatch", "fetch_scale", "write_scale",
+              "valu_insts_per_dispatch", "tcp_tcc_read_req_per_dispatch", "tcc_hit_per_dispatch",
+              "tcc_miss_per_dispatch"):
+        assert float(vals[k]) > 0, k
+    c = bench.read_counters()
+    r = bench.roofline(0.15, c["evals_per_dispatch"])
+    assert 0 < r["frac"] <= 1 and 0 < r["counters"]["valu_issue_frac"] <= 1 and r["counters"]["hbm_frac"] < 1
+
+
+def test_roofline_bound_is_a_rate_below_peak():
+    """The scoring roofline counts the method's own vector operations per sample against the chip's
+    lane-operation rate: 38 operations per sample, 256 x 4 x 16 lanes at 2.4 GHz."""
+    import bench
+    assert bench.OPS_PER_EVAL == 38
+    assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
+    r = bench.roofline(1.0, 1e9)   # 1e9 samples in 1 ms
+    assert r["bound"] == "alu" and abs(r["achieved"] - 38.0) < 1e-9 and r["frac"] < 1

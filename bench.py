@@ -437,95 +437,104 @@ _RENDER = {}
 
 
 def bench_precision(args):
-    """Precision workload (form 1): the paper-scale room in a 1024^3 grid at 0.5 cm (tau 2 cm), 640x480
-    depth, 4096 particles x 20 iterations at rates 1/8, 1/16, 1/32, then fusion, in each storage format
-    (FP32 T + FP32 W, FP16 T + uint8 W, int16 T + uint8 W; sums FP32-exact, pose math FP64). Frame 0
-    is fused at the true pose, later frames start from the previous estimate composed with the stand-in.
-    Reports per format the tracked frames' throughput, and for the first tracked frame: the pose
-    against the FP64 oracle tracking from the same init with the same random stream (a) on this
-    format's own volume, dequantized, and (b) on the oracle's own FP64 fusion of frame 0; and the
-    fitness of the tracked pose against its FP64 value on that fusion.
-    Prints one JSON line."""
+    """Precision workload (form 1) on the first frames of the paper-scale sequence: the room in a 1024^3
+    grid at 0.5 cm (tau 2 cm), 640x480 depth, 4096 particles x 20 iterations at rates 1/8, 1/16, 1/32,
+    then fusion at the tracked pose, in each storage format (FP32 T + FP32 W, FP16 T + uint8 W, int16
+    T + uint8 W; sums exact, pose math FP64). Frame 0 is fused at the true pose; frame t starts from
+    the previous estimate composed with the stand-in. Per frame (t = 1 .. args.frames) and format:
+    - the pose against the FP64 oracle tracking from the same initial pose with the same random
+      stream on this format's own volume as it stood (dequantized): the kernels' arithmetic;
+    - the fitness of the tracked pose on the densest view against its FP64 value on that same
+      volume, and against the FP64 fusion of the same frames at the same poses (no storage rounding):
+      the error of the form itself;
+    - the oracle's count of particle/pose near-ties (|E_k - E_0| <= 1e-4 E_0) over the iterations, the
+      decisions FP32 rounding can flip.
+    GPU time per frame (track + fuse) excludes the oracle's work. Prints one JSON line."""
     import numpy as np
     import torch
     import oracle
     import paper_2509_24236_amd as pf
     import synth
     dev = torch.device("cuda:0")
-    n_frames = args.warmup + args.steps + 1
+    n_frames = args.frames + 1
     log(f"[precision] rendering {n_frames} frames")
     f = synth.cfg2_frames(n_frames)
     intr, rel = f["intr"], f["rel"]
     spec = synth.VolumeSpec.centred(1024, 0.005, 0.02, synth.room_centre_world(f["scene"]))
     depth = [torch.as_tensor(f["depth"](t)).to(dev) for t in range(n_frames)]
     K, I, rates = 4096, 20, (8, 16, 32)
-    params = pf.TrackParams(seed=15, frame_index=1, n_iters=I, K=K, rates=rates, pixel_stride=1, s1_deg=10.0,
-                            s1_m=0.10)
-    R1, t1 = f["gt"][0][0] @ rel[1][0], f["gt"][0][0] @ rel[1][1] + f["gt"][0][1]
-    log("[precision] FP64 oracle: fusion of frame 0 and tracking of frame 1")
-    ov = oracle.Volume(spec)
-    ov.integrate(f["depth"](0), intr, *f["gt"][0])
-    oprm = oracle.make_params(seed=15, frame_index=1, n_iters=I, K=K, rates=rates, pixel_stride=1, s1_deg=10.0,
-                              s1_m=0.10)
-    Ro, to, _ = ov.track_frame(f["depth"](1), intr, R1, t1, oprm)
-    X1, _ = oracle.backproject(f["depth"](1), intr, 1)
-    S8 = oracle.subsample(X1, min(rates))          # the densest view, on which E_final is reported
     names = {pf.F32_W_F32: "f32", pf.F16_W_U8: "f16+u8", pf.I16_W_U8: "i16+u8"}
+    fmts = {"f32": pf.F32_W_F32, "f16": pf.F16_W_U8, "i16": pf.I16_W_U8}
     res = {}
-    for fmt in (pf.F32_W_F32, pf.F16_W_U8, pf.I16_W_U8):
+    for key in args.formats.split(","):
+        fmt = fmts[key]
         vol = pf.Tsdf(spec, fmt=fmt, device=dev)
-        trk = pf.Tracker(intr, params, device=dev)
+        trk = pf.Tracker(intr, pf.TrackParams(seed=15, frame_index=1, n_iters=I, K=K, rates=rates, pixel_stride=1,
+                                              s1_deg=10.0, s1_m=0.10), device=dev)
         vol.integrate(depth[0], intr, *f["gt"][0])
-        # the oracle on this format's own volume (dequantized), tracking frame 1 from the same init:
-        # isolates the kernels' arithmetic from the storage format's rounding
-        Tq, Wq = vol.export_linear()
-        oq = oracle.Volume(spec, T=Tq.cpu().numpy(), W=Wq.cpu().numpy())
-        del Tq, Wq
-        Rq, tq, _ = oq.track_frame(f["depth"](1), intr, R1, t1, oprm)
-        del oq
+        ov = oracle.Volume(spec)                  # FP64 fusion of the same frames at the same poses
+        ov.integrate(f["depth"](0), intr, *f["gt"][0])
         est = [f["gt"][0]]
-        first = None
-        evals = 0
+        rows, gpu_s, evals = [], 0.0, 0
         for t in range(1, n_frames):
-            if t == args.warmup + 1:
-                torch.cuda.synchronize()
-                t_start = time.perf_counter()
             Rp, tp = est[-1]
             R0, t0 = Rp @ rel[t][0], Rp @ rel[t][1] + tp
+            # the oracle on this format's volume as it stands (dequantized), same init and stream
+            Tq, Wq = vol.export_linear()
+            oq = oracle.Volume(spec, T=Tq.cpu().numpy(), W=Wq.cpu().numpy())
+            del Tq, Wq
+            oprm = oracle.make_params(seed=15, frame_index=t, n_iters=I, K=K, rates=rates, pixel_stride=1,
+                                      s1_deg=10.0, s1_m=0.10)
+            Rq, tq, recs = oq.track_frame(f["depth"](t), intr, R0, t0, oprm)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
             trk.set_frame(t)
             R, tt, st = trk.track(vol, depth[t], R0, t0)
             vol.integrate(depth[t], intr, R, tt)
+            torch.cuda.synchronize()
+            gpu_s += time.perf_counter() - t1
+            evals += sum((st.n_particles[i] + 1) * st.n_sub[i] for i in range(st.n_iters))
+            X, _ = oracle.backproject(f["depth"](t), intr, 1)
+            S8 = oracle.subsample(X, min(rates)).astype(np.float32).astype(np.float64)
+            Eq, _ = oq.fitness(S8, R, tt)           # FP64, same pose, this format's volume
+            E64, _ = ov.fitness(S8, R, tt)          # FP64, same pose, unrounded FP64 fusion
+            del oq
+            ov.integrate(f["depth"](t), intr, R, tt)
             est.append((R, tt))
-            if t == 1:
-                first = (R, tt, st)
-            if t > args.warmup:
-                evals += sum((K + 1) * st.n_sub[i] for i in range(st.n_iters))
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t_start
-        R, tt, st = first
-        dr = math.degrees(oracle.rot_err(R, Ro))
-        E64, _ = ov.fitness(S8, R, tt)             # the FP64 fitness of the same pose on the FP64 fusion
-        res[names[fmt]] = {"ms_per_frame": 1e3 * el / args.steps, "evals_per_s": evals / el,
-                           "frame1_vs_oracle_same_volume_deg": math.degrees(oracle.rot_err(R, Rq)),
-                           "frame1_vs_oracle_same_volume_mm": 1e3 * float(np.linalg.norm(tt - tq)),
-                           "frame1_vs_oracle_deg": dr, "frame1_vs_oracle_mm": 1e3 * float(np.linalg.norm(tt - to)),
-                           "frame1_E_final": float(st.E_final), "frame1_E_fp64": float(E64),
-                           "frame1_E_rel_err": abs(float(st.E_final) - E64) / E64,
-                           "volume_bytes": vol.T.numel() * vol.T.element_size() + vol.W.numel() * vol.W.element_size()}
-        log(f"[precision] {names[fmt]}: {res[names[fmt]]}")
-        del vol, trk
+            row = {"frame": t, "vs_oracle_same_volume_deg": math.degrees(oracle.rot_err(R, Rq)),
+                   "vs_oracle_same_volume_mm": 1e3 * float(np.linalg.norm(tt - tq)),
+                   "E_final": float(st.E_final), "E_fp64_same_volume": Eq, "E_fp64_unrounded": E64,
+                   "E_rel_err_same_volume": abs(float(st.E_final) - Eq) / Eq,
+                   "E_rel_err_vs_fp64": abs(float(st.E_final) - E64) / E64,
+                   "near_ties": int(sum(r.n_near for r in recs)), "near_ties_iter1": int(recs[0].n_near),
+                   "vs_truth_mm": 1e3 * float(np.linalg.norm(tt - f["gt"][t][1]))}
+            rows.append(row)
+            log(f"[precision] {names[fmt]} frame {t}: pose vs oracle {row['vs_oracle_same_volume_deg']:.3f} deg "
+                f"{row['vs_oracle_same_volume_mm']:.3f} mm, E err {row['E_rel_err_same_volume']:.1e} (same volume) "
+                f"{row['E_rel_err_vs_fp64']:.1e} (vs FP64), near-ties {row['near_ties']}")
+        dd = np.array([r["vs_oracle_same_volume_deg"] for r in rows])
+        dm = np.array([r["vs_oracle_same_volume_mm"] for r in rows])
+        res[names[fmt]] = {
+            "ms_per_frame": 1e3 * gpu_s / len(rows), "evals_per_s": evals / gpu_s,
+            "frames": rows,
+            "frames_within_1mm_0.05deg": int(np.sum((dd <= 0.05) & (dm <= 1.0))),
+            "median_vs_oracle_deg": float(np.median(dd)), "median_vs_oracle_mm": float(np.median(dm)),
+            "max_E_rel_err_same_volume": max(r["E_rel_err_same_volume"] for r in rows),
+            "max_E_rel_err_vs_fp64": max(r["E_rel_err_vs_fp64"] for r in rows),
+            "volume_bytes": vol.T.numel() * vol.T.element_size() + vol.W.numel() * vol.W.element_size()}
+        del vol, trk, ov
         torch.cuda.empty_cache()
-    del ov
-    base = res["f32"]["ms_per_frame"]
-    for v in res.values():
-        v["speedup_vs_f32"] = base / v["ms_per_frame"]
+    if "f32" in res:
+        for v in res.values():
+            v["speedup_vs_f32"] = res["f32"]["ms_per_frame"] / v["ms_per_frame"]
+    main_key = "i16+u8" if "i16+u8" in res else next(iter(res))
     out = {"metric": "particle-point fitness evals/s + ms/frame (track+fuse) at 640x480, 4096 particles, by TSDF format",
-           "value": res["i16+u8"]["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": res["i16+u8"]["ms_per_frame"], "higher_is_better": True,
-           "dtype": "i16", "data": "synthetic",
-           "config": {"workload": "paper-scale room, 1024^3 TSDF at 0.5 cm (tau 2 cm), 640x480, 4096 particles x 20 "
-                                  "iterations at rates 1/8, 1/16, 1/32, then fusion; value = the int16 form",
-                      "formats": res}}
+           "value": res[main_key]["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": args.frames, "warmup": 0,
+           "ms_per_step": res[main_key]["ms_per_frame"], "higher_is_better": True,
+           "dtype": main_key.split("+")[0], "data": "synthetic",
+           "config": {"workload": f"paper-scale room, frames 1..{args.frames}, 1024^3 TSDF at 0.5 cm (tau 2 cm), "
+                                  "640x480, 4096 particles x 20 iterations at rates 1/8, 1/16, 1/32, then fusion; "
+                                  f"value = the {main_key} form", "formats": res}}
     print(json.dumps(out), flush=True)
 
 
@@ -699,7 +708,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true", help="run only a plain 1 GiB device copy")
-    ap.add_argument("--frames", type=int, default=200, help="accuracy: frames of the sequence")
+    ap.add_argument("--frames", type=int, default=None,
+                    help="accuracy: frames of the sequence (200); precision: frames tracked (20)")
     ap.add_argument("--workload", default="sequence", choices=["sequence", "batch", "regimes", "combined", "accuracy", "precision"],
                     help="sequence: the paper-scale sequence (the headline); batch: 64 heterogeneous problems; "
                          "regimes: the scoring kernel alone at four particle spreads (diagnostic); combined: "
@@ -715,6 +725,7 @@ def main():
                     help="sequence, accuracy: dense = the 512^3 cell-replica grid centred on the room (the "
                          "headline); bricks = a sparse brick pool over the whole room at the same 1 cm voxels")
     ap.add_argument("--max-bricks", type=int, default=120000, help="bricks: pool slots")
+    ap.add_argument("--formats", default="f32,f16,i16", help="precision: storage formats to run (f32, f16, i16)")
     ap.add_argument("--only-tracked", action="store_true",
                     help="sequence: skip the run fused at the ground-truth poses (counter runs)")
     args = ap.parse_args()
@@ -735,9 +746,11 @@ def main():
         bench_combined(args)
         return
     if args.workload == "accuracy":
+        args.frames = args.frames or 200
         bench_accuracy(args)
         return
     if args.workload == "precision":
+        args.frames = args.frames or 20
         bench_precision(args)
         return
 

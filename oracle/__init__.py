@@ -77,7 +77,7 @@ class Params(C.Structure):
 class IterRec(C.Structure):
     _fields_ = [("E0", C.c_double), ("Estar", C.c_double), ("s_rad", C.c_double), ("s_m", C.c_double),
                 ("n_adv", C.c_int64), ("n_pts", C.c_int64), ("nvalid0", C.c_int64), ("pose", Pose),
-                ("n_particles", C.c_int64)]
+                ("n_particles", C.c_int64), ("n_near", C.c_int64)]
 
 
 _lib = None

@@ -576,6 +576,8 @@ typedef struct {      /* per-iteration record, filled for i = 1..n_iters */
     int64_t n_adv, n_pts, nvalid0;
     orc_pose pose;
     int64_t n_particles;  /* K of the iteration */
+    int64_t n_near;       /* particles with |E_k - E_0| <= 1e-4 E_0: their membership in the advantage
+                             set is decided within FP32 rounding of the fitness (a count, not used) */
 } orc_iter_rec;
 
 /* Subsample view S_r of the compacted cloud: S_r[j] = M[j r], j = 0 .. ceil(n/r) - 1
@@ -648,6 +650,10 @@ void orc_ro_iteration(const orc_vol* V, const double* S, int64_t n, const orc_pa
         rec->s_m = *s_m;
         rec->pose = *P;
         rec->n_particles = K;
+        int64_t near = 0;
+        for (int32_t k = 1; k <= K; ++k)
+            if (fabs(E[k] - E[0]) <= 1e-4 * E[0]) near += 1;
+        rec->n_near = near;
     }
     *s_rad *= f;
     *s_m *= f;

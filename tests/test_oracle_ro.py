@@ -86,6 +86,26 @@ def test_search_size_special_cases(orc):
     assert abs(sr - 0.01) <= 1e-15
 
 
+def test_near_tie_count(orc):
+    """The record counts the particles whose fitness is within 1e-4 relative of E_0: all of them when
+    nothing is observed (every E_k = E_0 = 1), and otherwise exactly those the returned values show."""
+    spec = synth.VolumeSpec.centred(32, 0.02, 0.08, (0, 0, 1))
+    prm = orc.make_params(K=32, n_iters=1)
+    S = np.array([[0.0, 0.0, 1.0], [0.05, 0.0, 1.0]])
+    *_, E, nv, rec = orc.Volume(spec).ro_iteration(S, prm, 1, np.eye(3), np.zeros(3), 0.1, 0.05)
+    assert rec.n_near == 32
+    d = synth.cfg1_inputs()
+    vol = orc.Volume(d["vol"])
+    vol.integrate(d["depth1"], d["intr"], np.eye(3), np.zeros(3))
+    X, _ = orc.backproject(d["depth2"], d["intr"], 2)
+    prm = orc.make_params(K=512, n_iters=1)
+    for s_deg in (5.0, 0.001):
+        *_, E, nv, rec = vol.ro_iteration(X, prm, 1, *d["init2"], np.radians(s_deg), s_deg / 100.0)
+        near = int(np.sum(np.abs(E[1:] - E[0]) <= 1e-4 * E[0]))
+        assert rec.n_near == near
+    assert near > 100   # at a tiny spread most particles tie with the current pose
+
+
 def test_search_size_lower_bound_over_iterations(orc):
     d = synth.cfg1_inputs()
     vol = orc.Volume(d["vol"])

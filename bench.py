@@ -116,8 +116,8 @@ def cpu_baseline(frames, vol_spec, intr, n_frames, seconds, schedule="fixed"):
                       f"1..{done} on a 512^3 volume ({track_s:.1f} s timed)"}
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_score_sequence_counters.txt")
-SCORE_SOURCES = ("pf_sample.hpp", "pf_score_steps.hpp", "pf_score.hip", "pf_internal.hpp")
+COUNTERS = os.path.join(ROOT, "profiles", "k_draw_score_sequence_counters.txt")
+SCORE_SOURCES = ("pf_sample.hpp", "pf_score_steps.hpp", "pf_steps.hpp", "pf_draw_score.hip", "pf_internal.hpp")
 
 
 def score_source_hash():
@@ -163,9 +163,9 @@ def roofline(avg_launch_ms, evals_per_launch):
     achieved = OPS_PER_EVAL * evals_per_launch / t / 1e12
     out = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
            "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-           "kernel": "particles_score per iteration (k_score<f32, cells>, 4 poses x 256 threads, K poses; through "
-                     "the cell-validity mask with compaction while the particles are spread over more than a quarter "
-                     "voxel), timed with HIP events on its stream",
+           "kernel": "particle launch per iteration (k_draw_score<f32, cells>: draws its K particles, then scores "
+                     "them at 4 poses x 256 threads; through the cell-validity mask with compaction while the "
+                     "particles are spread over more than a quarter voxel), timed with HIP events on its stream",
            "ops_per_eval": OPS_PER_EVAL, "avg_launch_ms": avg_launch_ms, "evals_per_launch": evals_per_launch,
            "algorithmic_stencil_GBps": BYTES_PER_EVAL * evals_per_launch / t / 1e9,
            "counters": None}
@@ -926,7 +926,7 @@ def main():
                      f"per-brick cell blocks; {spec.nx}x{spec.ny}x{spec.nz} grid ({spec.nx * spec.ny * spec.nz / 1e6:.1f}M "
                      f"voxels), {used * 512 / (spec.nx * spec.ny * spec.nz):.1%} of them stored")
         c["bricks_used"] = used
-        out["roofline"]["kernel"] = ("particles_score per iteration: k_score<f32, bricks>, 4 poses x 256 threads")
+        out["roofline"]["kernel"] = ("particle launch per iteration: k_draw_score<f32, bricks>, 4 poses x 256 threads")
         out["roofline"]["counters"] = out["roofline"]["traffic"] = None
         log(f"[bench] bricks {used}, fusion {fuse_ms:.3f} ms/frame, volume {vol_bytes / 2**30:.2f} GiB")
     if not args.no_cpu_baseline:

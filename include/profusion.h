@@ -306,7 +306,9 @@ int32_t particles_score_grad(const pf_tsdf* v, const float* px, const float* py,
  * needs >= 256), or 0 and 0 (the default) for the automatic shape, 4 poses x 256 threads (fewer
  * poses per workgroup when K is too small to fill the GPU); track_frame then also picks, per
  * iteration, the launch of the spread regime of the search size that drew its particles (see
- * pf_score_mask). Process-wide: a launch in flight on another thread takes the old or the new
+ * pf_score_mask); with the automatic 4 x 256 shape and that regime known from the previous call
+ * with the same parameters, the particle launch also draws its particles (otherwise a separate
+ * launch draws them first). Process-wide: a launch in flight on another thread takes the old or the new
  * shape. Fitness sums are exact (64-bit fixed point), so every shape, and
  * the batched path, gives bitwise identical results; the shape changes speed only. Returns
  * PF_EINVAL for an unsupported shape. */
@@ -441,8 +443,9 @@ void track_batch_destroy(pf_batch* b);
 
 /* ------------------------------------------------------------------------------ timing */
 
-/* Kernel timing of the particle-scoring launches made by track_frame: when enabled, each such
- * launch is bracketed by HIP events on the call's stream and, once track_frame has synchronised,
+/* Kernel timing of the particle-scoring launches made by track_frame (the draw included when the
+ * launch draws its own particles): when enabled, each such launch is bracketed by HIP events on
+ * the call's stream (the interval includes the launch's dispatch) and, once track_frame has synchronised,
  * the elapsed times, the number of launches and the number of evaluated (pose, point) samples
  * (sum of poses x points per launch) are accumulated. Switch, events and counters belong to the
  * calling host thread: enable and read on the thread that calls track_frame. */

@@ -37,9 +37,16 @@ __device__ inline double draw_pm1(uint64_t seed, uint32_t t, uint32_t i, uint32_
     return 2.0 * u - 1.0;
 }
 
+// The FP64 pose functions below round every multiplication and addition on its own, in source
+// order (no fused multiply-add): with contraction the compiler may fuse them differently wherever
+// they are inlined, and every kernel that draws or composes a pose (the separate draw launch, the
+// particle launch that draws its own particles, the update step, the batched kernels, the polish)
+// must get the same bits from the same inputs.
+//
 // Rotation matrix of a rotation vector w (radians), row-major: I + a [w]x + b [w]x^2 with
 // a = sin(th)/th and b = (1 - cos th)/th^2, series a = 1 - th^2/6, b = 1/2 - th^2/24 below 1e-6.
 __device__ inline void rotvec_to_matrix(const double w[3], double M[9]) {
+#pragma clang fp contract(off)
     double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
     double th = sqrt(th2);
     double a, b;
@@ -67,6 +74,7 @@ __device__ inline void rotvec_to_matrix(const double w[3], double M[9]) {
 // Delta pose (rotation vector r, translation tau) applied to (R, t); see PF_COMPOSE_*.
 __device__ inline void apply_delta(int mode, const double r[3], const double tau[3], const double R[9],
                                    const double t[3], double Ro[9], double to[3]) {
+#pragma clang fp contract(off)
     double D[9];
     rotvec_to_matrix(r, D);
     for (int a = 0; a < 3; ++a)
@@ -184,6 +192,11 @@ int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int
 // Spread regime (0 wide, 1 mid, 2 tight) of particles drawn with search size (s_rad, s_m): the
 // host-side twin of the test the scoring launches make on the device.
 int spread_regime_of(double s_rad, double s_m, float inv_vs);
+// Whether the automatic launch for the K particles of an optimizer state has 4 poses x 256 threads
+// per workgroup (the shape of the particle launch that draws its own particles), and whether a
+// launch of spread regime `regime` reads the cell-validity mask of a volume of this layout.
+bool score_auto_4x256(int K);
+bool score_regime_masked(int layout, int regime);
 
 // Largest number of per-workgroup partial sums the single-pose passes use.
 constexpr int kMaxPartials = 256;

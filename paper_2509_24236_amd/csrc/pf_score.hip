@@ -161,4 +161,10 @@ int32_t launch_score(const VolView& vv, const Points& p, const float* poses, int
 
 int spread_regime_of(double s_rad, double s_m, float inv_vs) { return spread_regime_sm(s_rad, s_m, inv_vs); }
 
+bool score_auto_4x256(int K) { return g_tk.load() == 0 && K > 64 && auto_shape(K) == 0; }
+
+bool score_regime_masked(int layout, int regime) {
+    return layout != PF_LAYOUT_LINEAR && ((g_mask_regimes.load() >> regime) & 1) != 0;
+}
+
 }  // namespace pf

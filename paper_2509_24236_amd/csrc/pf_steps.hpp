@@ -382,15 +382,7 @@ __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px,
     if (nv.x) chunk_sums(nv.x, nv.y, nv.z, *nv.n_dev, state_partials_next(st, K));
 }
 
-// Completes iteration i (unless FIRST) and draws the K particles of the next one:
-// E* from the partials in order, s^(i+1) = s^(i) (beta + (1 - beta) E*), then particle k is the
-// delta (omega a[0:3], v a[3:6]) with a from the counter stream, composed with P^(i) in FP64 and
-// rounded to FP32; slot 0 is P^(i). FIRST draws iteration 1 around the initial state.
-//
-// e0_partials > 0: the second set of partials (that many) holds P^(i) (FIRST: the initial pose)
-// scored on the drawn iteration's view, and workgroup 0 writes that E_0 and its count to fit0[0] and
-// nv0[0], the slot 0 the particle launch no longer scores (or, after the last iteration, the
-// returned pose's fitness on the densest view).
+// (sum, count) of n_partials exact partials, in every thread of a 256-thread workgroup.
 template <int FMT>
 __device__ inline void partials_sum(const Partial* pt, int n_partials, FixSum& out_sum, int& out_cnt) {
     __shared__ FixSum rs[256 / kWave];
@@ -420,11 +412,32 @@ __device__ inline void partials_sum(const Partial* pt, int n_partials, FixSum& o
     __syncthreads();
 }
 
+// The draw of one iteration, the same in every thread of the grid: P (the pose the particles are
+// drawn around), the search size s, the iteration index, its particle count and the stop rule.
+struct DrawPlan {
+    double R[9], t[3], s_rad, s_m;
+    uint32_t it;
+    int K_it;
+    bool stop;
+};
+
+// Completes iteration i (unless FIRST) and plans the draw of iteration i + 1: E* from the
+// partials in order, s^(i+1) = s^(i) (beta + (1 - beta) E*), P = P^(i), and the stop rule on
+// s^(i+1). FIRST plans iteration 1 around the initial state. Returns false (uniformly) when the
+// state belongs to another K or the optimization has stopped.
+//
+// e0_partials > 0: the second set of partials (that many) holds P^(i) (FIRST: the initial pose)
+// scored on the drawn iteration's view, and the workgroup with lead_block writes that E_0 and its
+// count to fit0[0] and nv0[0], the slot 0 the particle launch does not score (or, after the last
+// iteration, the returned pose's fitness on the densest view). The one thread with `lead` (in
+// lead_block) records iteration i and moves the state on to iteration i + 1. Fields read here are
+// never written here, apart from `done`, which is set only when the stop rule ends the
+// optimization, in which case no thread draws.
 template <int FMT, bool FIRST>
-__device__ inline void next_step(pf_track_state* st, int K, int n_partials, int draw, float* next_poses, IterRec* recs,
-                                 int blk, int e0_partials = 0, float* fit0 = nullptr, int* nv0 = nullptr) {
-    if (st->K != K || st->done) return;
-    if (e0_partials > 0 && blk == 0) {
+__device__ inline bool draw_prologue(pf_track_state* st, int K, int n_partials, IterRec* recs, bool lead_block,
+                                     bool lead, int e0_partials, float* fit0, int* nv0, DrawPlan& P) {
+    if (st->K != K || st->done) return false;
+    if (e0_partials > 0 && lead_block) {
         FixSum sum;
         int cnt;
         partials_sum<FMT>(state_partials_next(st, K), e0_partials, sum, cnt);
@@ -436,66 +449,42 @@ __device__ inline void next_step(pf_track_state* st, int K, int n_partials, int 
     __shared__ double sh_s[2];
     __shared__ int sh_cnt;
     __shared__ float sh_E;
-    __shared__ FixSum rs[256 / kWave];
-    __shared__ int rc[256 / kWave];
     if (!FIRST) {
         // E* from the exact partials (integer sums, so the reduction order is free)
-        const Partial* pt = state_partials(st, K);
-        FixSum sum = 0;
-        int cnt = 0;
-        for (int b = threadIdx.x; b < n_partials; b += 256) {
-            sum += pt[b].sum;
-            cnt += pt[b].cnt;
-        }
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            sum += __shfl_xor(sum, off);
-            cnt += __shfl_xor(cnt, off);
-        }
-        if ((threadIdx.x & (kWave - 1)) == 0) {
-            rs[threadIdx.x / kWave] = sum;
-            rc[threadIdx.x / kWave] = cnt;
+        FixSum sum;
+        int cnt;
+        partials_sum<FMT>(state_partials(st, K), n_partials, sum, cnt);
+        if (threadIdx.x == 0) {
+#pragma clang fp contract(off)
+            // (rounded step by step, as every kernel that updates s does)
+            const float Es = fitness_from<FMT>(sum, cnt);
+            const double f = st->beta + (1.0 - st->beta) * (double)Es;
+            sh_s[0] = st->s_rad_done * f;
+            sh_s[1] = st->s_m_done * f;
+            sh_cnt = cnt;
+            sh_E = Es;
         }
         __syncthreads();
     }
-    if (!FIRST && threadIdx.x == 0) {
-        FixSum sum = 0;
-        int cnt = 0;
-        for (int w = 0; w < 256 / kWave; ++w) {
-            sum += rs[w];
-            cnt += rc[w];
-        }
-        const float Es = fitness_from<FMT>(sum, cnt);
-        const double f = st->beta + (1.0 - st->beta) * (double)Es;
-        sh_s[0] = st->s_rad_done * f;
-        sh_s[1] = st->s_m_done * f;
-        sh_cnt = cnt;
-        sh_E = Es;
-    }
-    __syncthreads();
-    const int k = blk * 256 + threadIdx.x;
-    double R[9], t[3], s_rad, s_m;
-    uint32_t it;
     if (FIRST) {
-        for (int q = 0; q < 9; ++q) R[q] = st->R[q];
-        for (int q = 0; q < 3; ++q) t[q] = st->t[q];
-        s_rad = st->s_rad;
-        s_m = st->s_m;
-        it = (uint32_t)st->iter;
+        for (int q = 0; q < 9; ++q) P.R[q] = st->R[q];
+        for (int q = 0; q < 3; ++q) P.t[q] = st->t[q];
+        P.s_rad = st->s_rad;
+        P.s_m = st->s_m;
+        P.it = (uint32_t)st->iter;
     } else {
-        for (int q = 0; q < 9; ++q) R[q] = st->R_new[q];
-        for (int q = 0; q < 3; ++q) t[q] = st->t_new[q];
-        s_rad = sh_s[0];
-        s_m = sh_s[1];
-        it = (uint32_t)st->iter_done + 1u;
+        for (int q = 0; q < 9; ++q) P.R[q] = st->R_new[q];
+        for (int q = 0; q < 3; ++q) P.t[q] = st->t_new[q];
+        P.s_rad = sh_s[0];
+        P.s_m = sh_s[1];
+        P.it = (uint32_t)st->iter_done + 1u;
     }
     // particles of iteration `it` (Sec. IV-A alternation pairs them with the sampling rate), and
     // the stop rule on the updated search size s^(it)
-    const int K_it = st->alt_K ? st->Ks[(it - 1u) % (uint32_t)st->n_rates] : st->K;
-    const bool stop = !FIRST && st->stop_rad > 0.0 && st->stop_m > 0.0 && s_rad < st->stop_rad && s_m < st->stop_m;
-    if (stop) draw = 0;
+    P.K_it = st->alt_K ? st->Ks[(P.it - 1u) % (uint32_t)st->n_rates] : st->K;
+    P.stop = !FIRST && st->stop_rad > 0.0 && st->stop_m > 0.0 && P.s_rad < st->stop_rad && P.s_m < st->stop_m;
     __syncthreads();   // every thread has read the state before it is rewritten below
-    if (!FIRST && k == 0) {
+    if (!FIRST && lead) {
         const int i = st->iter_done;
         if (recs && i >= 1 && i <= PF_MAX_ITERS) {
             IterRec& r = recs[i - 1];
@@ -510,38 +499,66 @@ __device__ inline void next_step(pf_track_state* st, int K, int n_partials, int 
         }
         st->Estar = (double)sh_E;
         st->n_valid_star = sh_cnt;
-        for (int q = 0; q < 9; ++q) st->R[q] = R[q];
-        for (int q = 0; q < 3; ++q) st->t[q] = t[q];
-        st->s_rad = s_rad;
-        st->s_m = s_m;
-        st->iter = (int)it;
-        st->K_cur = K_it;
-        st->done = stop ? 1 : 0;
+        for (int q = 0; q < 9; ++q) st->R[q] = P.R[q];
+        for (int q = 0; q < 3; ++q) st->t[q] = P.t[q];
+        st->s_rad = P.s_rad;
+        st->s_m = P.s_m;
+        st->iter = (int)P.it;
+        st->K_cur = P.K_it;
+        if (P.stop) st->done = 1;
     }
-    if (draw && k <= K_it) {
-        double* dl = state_deltas(st);
-        if (k == 0) {
-            store_pose12(next_poses, R, t);
-            for (int d = 0; d < 6; ++d) dl[d] = 0.0;
-        } else {
-            const uint64_t seed = st->seed;
-            const uint32_t fr = (uint32_t)st->frame_index;
-            double r[3], tau[3];
-            for (int d = 0; d < 3; ++d) r[d] = s_rad * draw_pm1(seed, fr, it, (uint32_t)k, (uint32_t)d);
-            for (int d = 0; d < 3; ++d) tau[d] = s_m * draw_pm1(seed, fr, it, (uint32_t)k, (uint32_t)(3 + d));
-            double Ro[9], to[3];
-            apply_delta(st->compose_mode, r, tau, R, t, Ro, to);
-            store_pose12(next_poses + (size_t)k * 12, Ro, to);
-            for (int d = 0; d < 3; ++d) {
-                dl[6 * k + d] = r[d];
-                dl[6 * k + 3 + d] = tau[d];
-            }
-        }
+    return true;
+}
+
+// Particle k of the planned iteration: the delta (omega a[0:3], v a[3:6]) with a from the counter
+// stream, composed with P in FP64 and rounded to FP32 into poses[k] (and into pose_copy when given);
+// slot 0 is P itself with a zero delta.
+__device__ inline void draw_particle(pf_track_state* st, const DrawPlan& P, int k, float* poses, float* pose_copy) {
+    double* dl = state_deltas(st);
+    if (k == 0) {
+        store_pose12(poses, P.R, P.t);
+        for (int d = 0; d < 6; ++d) dl[d] = 0.0;
+        return;
     }
+    const uint64_t seed = st->seed;
+    const uint32_t fr = (uint32_t)st->frame_index;
+    double r[3], tau[3];
+    for (int d = 0; d < 3; ++d) r[d] = P.s_rad * draw_pm1(seed, fr, P.it, (uint32_t)k, (uint32_t)d);
+    for (int d = 0; d < 3; ++d) tau[d] = P.s_m * draw_pm1(seed, fr, P.it, (uint32_t)k, (uint32_t)(3 + d));
+    double Ro[9], to[3];
+    apply_delta(st->compose_mode, r, tau, P.R, P.t, Ro, to);
+    store_pose12(poses + (size_t)k * 12, Ro, to);
+    if (pose_copy) store_pose12(pose_copy, Ro, to);
+    for (int d = 0; d < 3; ++d) {
+        dl[6 * k + d] = r[d];
+        dl[6 * k + 3 + d] = tau[d];
+    }
+}
+
+// The separate draw launch: completes iteration i (unless FIRST) and draws the K_(i+1) particles of
+// the next one, particle k in thread k of the grid (draw = 0: completes only).
+template <int FMT, bool FIRST>
+__device__ inline void next_step(pf_track_state* st, int K, int n_partials, int draw, float* next_poses, IterRec* recs,
+                                 int blk, int e0_partials = 0, float* fit0 = nullptr, int* nv0 = nullptr) {
+    const int k = blk * 256 + threadIdx.x;
+    DrawPlan P;
+    if (!draw_prologue<FMT, FIRST>(st, K, n_partials, recs, blk == 0, k == 0, e0_partials, fit0, nv0, P)) return;
+    if (draw && !P.stop && k <= P.K_it) draw_particle(st, P, k, next_poses, nullptr);
     __syncthreads();
 }
 
 
 int n_partials_for(int cap);
+
+// The particle launch of iteration i that draws its own particles (K_i of them, 4 poses x 256
+// threads, spread regime `regime` forecast, through the cell-validity mask when that regime reads
+// it): first = iteration 1 (planned around the initial state; e0_partials = the initial pose's
+// partials on the first view); otherwise it completes iteration i - 1 from the previous update
+// step's n_partials partials (E*) and e0_partials second partials (E_0 of iteration i). Particles go
+// to poses[1..K_i] (slot 0 = the pose they are drawn around), fitness to fit / nv [1..K_i] (slot 0 =
+// E_0), iteration i - 1's record to recs.
+int32_t launch_draw_score(const VolView& vv, const Points& S, pf_track_state* st, int K, int K_i, int n_partials,
+                          bool first, IterRec* recs, int e0_partials, float* poses, float* fit, int* nv, int regime,
+                          hipStream_t s);
 
 }  // namespace pf

@@ -394,20 +394,28 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
                            K->width, vs);
         if ((rc = check_launch("track_frame views"))) return rc;
     }
+    // Iterations whose particle launch draws its own particles: those with a regime forecast and
+    // the automatic 4 x 256 shape (the others keep the separate draw launch)
+    const bool forecast = forecast_matches(g_forecast, p, vv.inv_vs);
+    bool fused[PF_MAX_ITERS + 2] = {};
+    for (int i = 1; i <= p->n_iters; ++i) {
+        const int K_i = p->alt_K ? p->Ks[(i - 1) % p->n_rates] : p->K;
+        fused[i] = forecast && g_forecast.regime[i - 1] >= 0 && score_auto_4x256(K_i);
+    }
     // the initial state, the initial pose scored on the first view (slot 0 of iteration 1) and
     // the particles of iteration 1
+    const int G1 = n_partials_for((int)((npix + p->rates[0] - 1) / p->rates[0]));
     {
         pf_track_state h = make_state(init, p);
         hipLaunchKernelGGL(k_state_set, dim3(1), dim3(1), 0, s, st, h);
         if ((rc = check_launch("track_frame"))) return rc;
         const Points& S1 = views[0];
         const NextView nv1{S1.x, S1.y, S1.z, S1.n_dev};
-        const int G1 = n_partials_for((int)((npix + p->rates[0] - 1) / p->rates[0]));
         if ((rc = launch_adv(false, vv, S1, G1, fit, st, p->K, s, nv1))) return rc;
-        if ((rc = launch_next(vv.format, true, st, p->K, 0, true, poses, nullptr, s, G1, fit, nv))) return rc;
+        if (!fused[1] && (rc = launch_next(vv.format, true, st, p->K, 0, true, poses, nullptr, s, G1, fit, nv)))
+            return rc;
     }
     const bool timed = g_timing.on;
-    const bool forecast = forecast_matches(g_forecast, p, vv.inv_vs);
     int Gv[3];
     for (int r = 0; r < p->n_rates; ++r) Gv[r] = n_partials_for((int)((npix + p->rates[r] - 1) / p->rates[r]));
     int densest = 0;
@@ -418,6 +426,7 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
     // With no polish and no stop rule the returned pose is P^(I): the last update step scores it on
     // the densest view as it goes (E_final), instead of a separate pass after the loop.
     const bool final_in_loop = p->polish_steps == 0 && !(p->stop_deg > 0.0 && p->stop_m > 0.0);
+    int G_prev = G1;   // partials of the previous update step: its E* and this iteration's E_0
     for (int i = 1; i <= p->n_iters; ++i) {
         const int r = (i - 1) % p->n_rates;
         const Points& S = views[r];
@@ -427,7 +436,11 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
         // the particles 1..K_i; slot 0 (E_0, the current pose on this view) was scored by the
         // previous update step
         const Points Sp{S.x, S.y, S.z, S.n, S.n_dev};
-        if ((rc = launch_score(vv, Sp, poses + 12, K_i, fit + 1, nv + 1, s, st, expect))) return rc;
+        if (fused[i])
+            rc = launch_draw_score(vv, Sp, st, p->K, K_i, G_prev, i == 1, recs, G_prev, poses, fit, nv, expect, s);
+        else
+            rc = launch_score(vv, Sp, poses + 12, K_i, fit + 1, nv + 1, s, st, expect);
+        if (rc) return rc;
         if (timed) (void)hipEventRecord(g_timing.ev[2 * (i - 1) + 1], s);
         // the update also scores the new pose on the next iteration's view (its slot 0); the last
         // iteration only completes (E*, s), its particles stay in `poses` / `fit`
@@ -438,9 +451,12 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
         const NextView nvn = second ? NextView{views[rn].x, views[rn].y, views[rn].z, views[rn].n_dev}
                                     : NextView{nullptr, nullptr, nullptr, nullptr};
         if ((rc = launch_adv(true, vv, S, G, fit, st, p->K, s, nvn))) return rc;
-        if ((rc = launch_next(vv.format, false, st, p->K, G, more, poses, recs, s, second ? G : 0,
+        // (the next iteration's particle launch completes this one itself when it draws)
+        if (!(more && fused[i + 1]) &&
+            (rc = launch_next(vv.format, false, st, p->K, G, more, poses, recs, s, second ? G : 0,
                               more ? fit : ef_dev, more ? nv : nvf_dev)))
             return rc;
+        G_prev = G;
     }
     // optional gradient polish of the best candidate, on the densest view
     if (p->polish_steps > 0 &&

@@ -25,7 +25,7 @@ def test_counter_summary_matches_the_scoring_sources():
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     assert vals["score_source_sha256"] == bench.score_source_hash(), \
-        "the scoring kernel changed since profiles/k_score_sequence_counters.txt was taken"
+        "the scoring kernel changed since profiles/k_draw_score_sequence_counters.txt was taken"
     for k in ("evals_per_dispatch", "fetch_kib_per_dispatch", "write_kib_per_dispatch", "fetch_scale", "write_scale",
               "valu_insts_per_dispatch", "tcp_tcc_read_req_per_dispatch", "tcc_hit_per_dispatch",
               "tcc_miss_per_dispatch"):

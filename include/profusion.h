@@ -112,7 +112,9 @@ typedef struct pf_intrinsics {
 } pf_intrinsics;
 
 typedef struct pf_tsdf {
-    int32_t nx, ny, nz;  /* voxels per axis, each >= 2; nx*ny*nz < 2^31 */
+    int32_t nx, ny, nz;  /* voxels per axis, each >= 2; dense layouts: nx*ny*nz < 2^31 and
+                          * nx*ny < 2^24 (index arithmetic in 24-bit multiplies); BRICKS:
+                          * (nx/8)(ny/8)(nz/8) < 2^31 and (nx/8)(ny/8) < 2^24 */
     int32_t format;      /* PF_F32_W_F32, PF_F16_W_U8 or PF_I16_W_U8 */
     double voxel_size;   /* metres, > 0 */
     double trunc;        /* truncation distance tau, metres, > 0 */

@@ -136,6 +136,8 @@ int32_t check_tsdf(const pf_tsdf* v, const char* fn, bool need_weight = true) {
             return set_error(PF_EINVAL, "%s: ny/8 and nz/8 must be <= 65535", fn);
         if ((int64_t)(v->nx / kBrickEdge) * (v->ny / kBrickEdge) * (v->nz / kBrickEdge) >= ((int64_t)1 << 31))
             return set_error(PF_EINVAL, "%s: brick-index grid exceeds 2^31 - 1 entries", fn);
+        if ((int64_t)(v->nx / kBrickEdge) * (v->ny / kBrickEdge) >= ((int64_t)1 << 24))
+            return set_error(PF_EINVAL, "%s: (nx/8)(ny/8) must be below 2^24", fn);
         if (v->max_bricks < 1) return set_error(PF_EINVAL, "%s: BRICKS needs max_bricks >= 1", fn);
         if (v->max_bricks > kMaxBricks)
             return set_error(PF_EINVAL, "%s: BRICKS max_bricks %d > %d (a pool cell's index must fit 32 bits)", fn,
@@ -147,6 +149,8 @@ int32_t check_tsdf(const pf_tsdf* v, const char* fn, bool need_weight = true) {
         if ((int64_t)v->nx * v->ny * v->nz >= ((int64_t)1 << 31))
             return set_error(PF_EINVAL, "%s: volume of %lld voxels exceeds 2^31 - 1", fn,
                              (long long)v->nx * v->ny * v->nz);
+        if ((int64_t)v->nx * v->ny >= ((int64_t)1 << 24))
+            return set_error(PF_EINVAL, "%s: nx * ny must be below 2^24 for a dense layout", fn);
     }
     if (v->format != PF_F32_W_F32 && v->format != PF_F16_W_U8 && v->format != PF_I16_W_U8)
         return set_error(PF_EINVAL, "%s: unknown format %d", fn, v->format);
@@ -285,13 +289,14 @@ size_t tsdf_bytes(const pf_tsdf* v, size_t* weight_bytes) {
             v->max_bricks > kMaxBricks || v->reserved)
             return 0;
         if ((int64_t)(v->nx / kBrickEdge) * (v->ny / kBrickEdge) * (v->nz / kBrickEdge) >= ((int64_t)1 << 31)) return 0;
+        if ((int64_t)(v->nx / kBrickEdge) * (v->ny / kBrickEdge) >= ((int64_t)1 << 24)) return 0;
         const BrickLayout L = brick_layout(v);
         if (weight_bytes) *weight_bytes = L.w_total;
         return L.t_total;
     }
     if (v->max_bricks != 0 || v->reserved) return 0;
     const int64_t n = (int64_t)v->nx * v->ny * v->nz;
-    if (n >= ((int64_t)1 << 31)) return 0;
+    if (n >= ((int64_t)1 << 31) || (int64_t)v->nx * v->ny >= ((int64_t)1 << 24)) return 0;
     if (v->layout != PF_LAYOUT_LINEAR && v->layout != PF_LAYOUT_CELLS) return 0;
     const size_t tb = t_elem_bytes(v->format), wb = v->format == PF_F32_W_F32 ? 4 : 1;
     if (weight_bytes) *weight_bytes = (size_t)n * wb;

@@ -1,6 +1,8 @@
 // The particle launch of the optimization loop that draws its own particles (Sec. III-B: sampling
 // around the current pose, then the fitness of every particle), in one launch per iteration instead
 // of a draw launch followed by a scoring launch.
+#include <atomic>
+
 #include "pf_steps.hpp"
 
 namespace pf {
@@ -35,6 +37,27 @@ __global__ __launch_bounds__(256) void k_draw_score(VolView vv, Points S, pf_tra
 }
 
 }  // namespace
+
+void warm_draw_score(int format, int layout) {
+    // The runtime loads a kernel's code on its first launch (about a millisecond). Frames without a
+    // regime forecast (the first of a sequence) do not launch this kernel, so the first call on a
+    // device loads it up front, by querying the attributes of the volume's instantiations: the
+    // next frame's launches then find it loaded.
+    static std::atomic<unsigned> warmed[64][3][3];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || format < 0 || format > 2 || layout < 0 ||
+        layout > 2)
+        return;
+    if (warmed[dev][format][layout].exchange(1u)) return;
+    with_volume(format, layout, [&](auto fmt, auto lay) {
+        constexpr int F = decltype(fmt)::value, LY = decltype(lay)::value;
+        hipFuncAttributes attr;
+        (void)hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_draw_score<F, LY, false>));
+        if constexpr (LY != PF_LAYOUT_LINEAR)
+            (void)hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_draw_score<F, LY, true>));
+        return PF_OK;
+    });
+}
 
 int32_t launch_draw_score(const VolView& vv, const Points& S, pf_track_state* st, int K, int K_i, int n_partials,
                           bool first, IterRec* recs, int e0_partials, float* poses, float* fit, int* nv, int regime,

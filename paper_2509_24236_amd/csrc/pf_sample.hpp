@@ -86,7 +86,10 @@ struct Gather<FMT, PF_LAYOUT_LINEAR> {
     using ST = typename Fmt<FMT>::T;
     const ST* __restrict__ T;
     int nx, nxy;
-    __device__ inline const ST* addr(int cx, int cy, int cz) const { return T + ((cz * nxy) + cy * nx + cx); }
+    // (nx * ny < 2^24 for the dense layouts, so the products are full-rate 24-bit multiplies)
+    __device__ inline const ST* addr(int cx, int cy, int cz) const {
+        return T + (__umul24((unsigned)cz, (unsigned)nxy) + __umul24((unsigned)cy, (unsigned)nx) + (unsigned)cx);
+    }
     __device__ inline void load(const ST* p, float (&c)[8]) const {
         c[0] = Fmt<FMT>::val(p[0]);
         c[1] = Fmt<FMT>::val(p[1]);
@@ -132,16 +135,17 @@ struct Gather<FMT, PF_LAYOUT_CELLS> {
     const unsigned long long* __restrict__ M;   // cell-validity mask: one word per 4x4x4 cells
     int mwx, mwxy;
     // cell index (below 2^31 for the dense layouts), unsigned so that its widening is a zero
-    // extension and the address one shift-and-add
+    // extension and the address one shift-and-add; (nx - 1)(ny - 1) < 2^24 for the dense layouts, so
+    // the products are 24-bit multiplies (full rate; a 32-bit multiply issues at a quarter rate)
     __device__ inline unsigned index(unsigned cx, unsigned cy, unsigned cz) const {
-        return cz * (unsigned)cnxy + cy * (unsigned)cnx + cx;
+        return __umul24(cz, (unsigned)cnxy) + __umul24(cy, (unsigned)cnx) + cx;
     }
     __device__ inline const ST* at(unsigned idx) const { return C + ((size_t)idx << 3); }
     __device__ inline const ST* addr(int cx, int cy, int cz) const { return at(index(cx, cy, cz)); }
     __device__ inline void load(const ST* p, float (&c)[8]) const { load_cell8<FMT>(p, c); }
     // the mask is below 2^28 bytes, so a 32-bit offset from the uniform base addresses a word
     __device__ inline const unsigned long long* mask_word(int cx, int cy, int cz) const {
-        const unsigned w = (unsigned)(cz >> 2) * (unsigned)mwxy + (unsigned)(cy >> 2) * (unsigned)mwx +
+        const unsigned w = __umul24((unsigned)(cz >> 2), (unsigned)mwxy) + __umul24((unsigned)(cy >> 2), (unsigned)mwx) +
                            (unsigned)(cx >> 2);
         return reinterpret_cast<const unsigned long long*>(reinterpret_cast<const char*>(M) + (w << 3));
     }
@@ -161,7 +165,11 @@ struct Gather<FMT, PF_LAYOUT_BRICKS> {
     const int* __restrict__ idx;  // brick-index grid
     const unsigned long long* __restrict__ M;   // the slots' cell-validity words (8 per slot)
     int nbx, nbxy;
-    __device__ inline int key(int cx, int cy, int cz) const { return (cz >> 3) * nbxy + (cy >> 3) * nbx + (cx >> 3); }
+    // ((nx / 8)(ny / 8) < 2^24: 24-bit multiplies)
+    __device__ inline int key(int cx, int cy, int cz) const {
+        return (int)(__umul24((unsigned)(cz >> 3), (unsigned)nbxy) + __umul24((unsigned)(cy >> 3), (unsigned)nbx) +
+                     (unsigned)(cx >> 3));
+    }
     __device__ inline int slot(int k) const { return idx[k]; }
     __device__ static inline unsigned local(int cx, int cy, int cz) {
         return (unsigned)((cx & 7) | ((cy & 7) << 3) | ((cz & 7) << 6));

@@ -560,5 +560,7 @@ int n_partials_for(int cap);
 int32_t launch_draw_score(const VolView& vv, const Points& S, pf_track_state* st, int K, int K_i, int n_partials,
                           bool first, IterRec* recs, int e0_partials, float* poses, float* fit, int* nv, int regime,
                           hipStream_t s);
+// Loads that launch's code for a volume of this format and layout on the current device (once).
+void warm_draw_score(int format, int layout);
 
 }  // namespace pf

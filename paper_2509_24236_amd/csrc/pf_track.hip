@@ -402,6 +402,7 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
         const int K_i = p->alt_K ? p->Ks[(i - 1) % p->n_rates] : p->K;
         fused[i] = forecast && g_forecast.regime[i - 1] >= 0 && score_auto_4x256(K_i);
     }
+    if (score_auto_4x256(p->K)) warm_draw_score(vv.format, vv.layout);
     // the initial state, the initial pose scored on the first view (slot 0 of iteration 1) and
     // the particles of iteration 1
     const int G1 = n_partials_for((int)((npix + p->rates[0] - 1) / p->rates[0]));

@@ -113,6 +113,8 @@ def test_tsdf_bytes(pf):
     assert L.tsdf_bytes(C.byref(_desc(pf, fmt=7)), C.byref(wb)) == 0
     assert L.tsdf_bytes(None, None) == 0
     assert L.tsdf_bytes(C.byref(_desc(pf, 2048, 2048, 1024)), None) == 0   # > 2^31 voxels
+    assert L.tsdf_bytes(C.byref(_desc(pf, 4096, 4096, 2)), None) == 0      # a slice of 2^24 voxels
+    assert L.tsdf_bytes(C.byref(_desc(pf, 4096, 4095, 2)), None) > 0
 
 
 def _rc(pf, rc, needle):

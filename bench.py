@@ -116,6 +116,52 @@ def cpu_baseline(frames, vol_spec, intr, n_frames, seconds, schedule="fixed"):
                       f"1..{done} on a 512^3 volume ({track_s:.1f} s timed)"}
 
 
+def adjoint_timing(vol, depth_dev, intr, R, t, n_poses=256, reps=5):
+    """The adjoint (particles_score_grad: E and dE/dxi of each pose in one gather pass) beside the
+    scoring kernel on the same poses: n_poses poses within +-1 deg / +-1 cm of (R, t) on the rate-1/8
+    subsample of the frame's points, each timed with HIP events on the current stream (median of
+    reps calls after one warm-up call)."""
+    import numpy as np
+    import torch
+    from scipy.spatial.transform import Rotation
+    import paper_2509_24236_amd as pf
+    px, py, pz, n = pf.backproject(depth_dev, intr, 1)
+    m = int(n[0].item())
+    x, y, z = (a[:m:8].contiguous() for a in (px, py, pz))
+    rng = np.random.default_rng(5)
+    poses = []
+    for _ in range(n_poses):
+        dR = Rotation.from_rotvec(rng.uniform(-1, 1, 3) * math.radians(1.0)).as_matrix()
+        poses.append((dR @ R, t + rng.uniform(-1, 1, 3) * 0.01))
+    base = torch.as_tensor(np.stack([np.concatenate([Rk, tk.reshape(3, 1)], 1).reshape(12) for Rk, tk in poses]),
+                           dtype=torch.float64, device=depth_dev.device)
+    P32 = torch.as_tensor(pf.poses_to_f32(poses)).to(depth_dev.device)
+
+    def timed(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    g_ms = timed(lambda: pf.particles_score_grad(vol, x, y, z, base))
+    s_ms = timed(lambda: pf.particles_score(vol, x, y, z, P32))
+    E_g = pf.particles_score_grad(vol, x, y, z, base)[0]
+    E_s = pf.particles_score(vol, x, y, z, P32)[0]
+    samples = n_poses * x.numel()
+    return {"poses": n_poses, "points": int(x.numel()), "adjoint_ms": g_ms, "scoring_ms": s_ms,
+            "adjoint_samples_per_s": samples / (g_ms * 1e-3), "scoring_samples_per_s": samples / (s_ms * 1e-3),
+            "E_bitwise_equal_to_scoring": bool(torch.equal(E_g.view(torch.int32), E_s.view(torch.int32))),
+            "note": "particles_score_grad (one 256-thread workgroup per pose and point chunk, E exact as the "
+                    "scoring kernel forms it, FP32 gradient sums in a fixed order) against particles_score on the "
+                    "same FP32 poses, poses within 1 deg / 1 cm of the last tracked pose, rate-1/8 points"}
+
+
 COUNTERS = os.path.join(ROOT, "profiles", "k_draw_score_sequence_counters.txt")
 SCORE_SOURCES = ("pf_sample.hpp", "pf_score_steps.hpp", "pf_steps.hpp", "pf_draw_score.hip", "pf_internal.hpp")
 
@@ -868,6 +914,9 @@ def main():
     fuse1_ms = e0.elapsed_time(e1)
     fuse_bytes = FUSE_BYTES_PER_VOXEL * n_upd + 4 * intr.width * intr.height
     torch.cuda.empty_cache()
+    adj = adjoint_timing(vol, depth[n_next], intr, *frames["gt"][n_next])
+    log(f"[bench] adjoint {adj['adjoint_ms']:.3f} ms vs scoring {adj['scoring_ms']:.3f} ms for {adj['poses']} poses x "
+        f"{adj['points']} points; E bitwise equal: {adj['E_bitwise_equal_to_scoring']}")
 
     roof = roofline(avg_launch_ms, evals_per_launch)
     out = {
@@ -914,6 +963,7 @@ def main():
                             "updated_voxels": n_upd, "bytes": fuse_bytes, "ms": fuse1_ms,
                             "note": f"{FUSE_BYTES_PER_VOXEL} B per updated voxel (T and W read and written) plus the "
                                     "depth image, over one fusion of the frame after the timed ones"},
+        "adjoint": adj,
     }
     if args.volume == "bricks":
         used, overflow = vol.bricks_used()

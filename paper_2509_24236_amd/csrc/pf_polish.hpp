@@ -11,12 +11,11 @@
 namespace pf {
 
 struct GradPartial {
-    float sabs;      // sum |T|
+    FixSum sabs;     // sum |T|, exact (the scoring kernels' fixed point)
     float gt[3];     // sum s grad T          (translation part)
     float gr[3];     // sum (y - c) x s grad T (rotation part)
     float rmax;      // max |y - c| over all points of the chunk
     int cnt;
-    int pad;
 };
 
 struct Partial2 {
@@ -75,46 +74,71 @@ __device__ inline void left_jacobian(const double w[3], double J[9]) {
 }
 
 // Accumulates E, the frozen-set gradient and the lever-arm maximum of one pose over points
-// [q0, q1) into the thread's partial; pose_sh holds the FP32 pose, c the rotation centre.
+// [q0, q1) into the thread's partial; pose_sh holds the FP32 pose, c the rotation centre. Each sample
+// goes through the scoring kernels' own steps (eval_poses with one pose: cell, fraction, the in-grid
+// test, the gather of the cell, the validity test, the trilinear value and its fixed-point |T|), so
+// the exact |T| sum, the count and hence E are bitwise those of particles_score; the analytic
+// gradient of the same interpolation is added alongside. No branch on validity: an invalid sample
+// contributes zeros, and the next point is loaded while the current sample's gather is in flight.
 template <int FMT, int LAYOUT>
 __device__ inline void grad_accumulate(const VolView& vv, const float* __restrict__ px, const float* __restrict__ py,
                                        const float* __restrict__ pz, int q0, int q1, const float* pose_sh,
                                        const float c[3], GradPartial& acc) {
+    using ST = typename Fmt<FMT>::T;
     const Gather<FMT, LAYOUT> G = make_gather<FMT, LAYOUT>(vv);
     const GridPose g = fold_pose(pose_sh, vv.inv_vs, vv.gx0, vv.gy0, vv.gz0);
     const unsigned lx = (unsigned)(vv.nx - 1), ly = (unsigned)(vv.ny - 1), lz = (unsigned)(vv.nz - 1);
     const float is = vv.inv_vs;
-    for (int q = q0 + (int)threadIdx.x; q < q1; q += kGradThreads) {
-        const float X = px[q], Y = py[q], Z = pz[q];
+    constexpr bool kNanTest = LAYOUT != PF_LAYOUT_LINEAR && Fmt<FMT>::nan_cells;
+    int q = q0 + (int)threadIdx.x;
+    float X = 0.0f, Y = 0.0f, Z = 0.0f;
+    if (q < q1) {
+        X = px[q];
+        Y = py[q];
+        Z = pz[q];
+    }
+    for (; q < q1; q += kGradThreads) {
         const float x = X * is, y = Y * is, z = Z * is;
+        const float Xc = X, Yc = Y, Zc = Z;
+        if (q + kGradThreads < q1) {
+            X = px[q + kGradThreads];
+            Y = py[q + kGradThreads];
+            Z = pz[q + kGradThreads];
+        }
         const float gx = fmaf(g.r[0], x, fmaf(g.r[1], y, fmaf(g.r[2], z, g.t[0])));
         const float gy = fmaf(g.r[3], x, fmaf(g.r[4], y, fmaf(g.r[5], z, g.t[1])));
         const float gz = fmaf(g.r[6], x, fmaf(g.r[7], y, fmaf(g.r[8], z, g.t[2])));
-        // lever arm u = y - c in metres: R x + t - c
-        const float ux = fmaf(pose_sh[0], X, fmaf(pose_sh[1], Y, fmaf(pose_sh[2], Z, pose_sh[3] - c[0])));
-        const float uy = fmaf(pose_sh[4], X, fmaf(pose_sh[5], Y, fmaf(pose_sh[6], Z, pose_sh[7] - c[1])));
-        const float uz = fmaf(pose_sh[8], X, fmaf(pose_sh[9], Y, fmaf(pose_sh[10], Z, pose_sh[11] - c[2])));
-        acc.rmax = fmaxf(acc.rmax, sqrtf(ux * ux + uy * uy + uz * uz));
-        const float fx0 = floorf(gx), fy0 = floorf(gy), fz0 = floorf(gz);
-        const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
-        const bool inb = ((unsigned)ix < lx) & ((unsigned)iy < ly) & ((unsigned)iz < lz);
-        const int cx = min(max(ix, 0), (int)lx - 1), cy = min(max(iy, 0), (int)ly - 1);
-        const int cz = min(max(iz, 0), (int)lz - 1);
+        const unsigned ux = (unsigned)floor_to_int(gx), uy = (unsigned)floor_to_int(gy), uz = (unsigned)floor_to_int(gz);
+        const bool inb = (ux < lx) & (uy < ly) & (uz < lz);
+        const float fx = __builtin_amdgcn_fractf(gx), fy = __builtin_amdgcn_fractf(gy),
+                    fz = __builtin_amdgcn_fractf(gz);
+        const ST* p;
+        if constexpr (LAYOUT == PF_LAYOUT_CELLS) {
+            p = G.at(inb ? G.index(ux, uy, uz) : 0u);
+        } else {
+            p = G.addr((int)min(ux, lx - 1u), (int)min(uy, ly - 1u), (int)min(uz, lz - 1u));
+        }
         float cv[8];
-        G.load(G.addr(cx, cy, cz), cv);
+        G.load(p, cv);
+        // lever arm u = y - c in metres: R x + t - c
+        const float ux_m = fmaf(pose_sh[0], Xc, fmaf(pose_sh[1], Yc, fmaf(pose_sh[2], Zc, pose_sh[3] - c[0])));
+        const float uy_m = fmaf(pose_sh[4], Xc, fmaf(pose_sh[5], Yc, fmaf(pose_sh[6], Zc, pose_sh[7] - c[1])));
+        const float uz_m = fmaf(pose_sh[8], Xc, fmaf(pose_sh[9], Yc, fmaf(pose_sh[10], Zc, pose_sh[11] - c[2])));
+        acc.rmax = fmaxf(acc.rmax, sqrtf(ux_m * ux_m + uy_m * uy_m + uz_m * uz_m));
         bool ok = inb;
+        if constexpr (!kNanTest) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) ok &= Fmt<FMT>::in_band(cv[e]);
-        if (!ok) continue;
-        const float fx = gx - fx0, fy = gy - fy0, fz = gz - fz0;
-        const float a00 = fmaf(fx, cv[1] - cv[0], cv[0]);
-        const float a10 = fmaf(fx, cv[3] - cv[2], cv[2]);
-        const float a01 = fmaf(fx, cv[5] - cv[4], cv[4]);
-        const float a11 = fmaf(fx, cv[7] - cv[6], cv[6]);
-        const float b0 = fmaf(fy, a10 - a00, a00);
-        const float b1 = fmaf(fy, a11 - a01, a01);
-        const float v = fmaf(fz, b1 - b0, b0);
-        // analytic gradient in grid units
+            for (int e = 0; e < 8; ++e) ok &= Fmt<FMT>::in_band(cv[e]);
+        }
+        const float v = trilerp(fx, fy, fz, cv);
+        if constexpr (kNanTest) ok &= !__builtin_isnan(v);
+        acc.sabs += (FixSum)(ok ? fixed_point<FMT>(v) : 0u);
+        acc.cnt += ok ? 1 : 0;
+        // analytic gradient of the same interpolation, in grid units
+        const float b0 = fmaf(fy, fmaf(fx, cv[3] - cv[2], cv[2]) - fmaf(fx, cv[1] - cv[0], cv[0]),
+                              fmaf(fx, cv[1] - cv[0], cv[0]));
+        const float b1 = fmaf(fy, fmaf(fx, cv[7] - cv[6], cv[6]) - fmaf(fx, cv[5] - cv[4], cv[4]),
+                              fmaf(fx, cv[5] - cv[4], cv[4]));
         const float dx0 = fmaf(fy, (cv[3] - cv[2]) - (cv[1] - cv[0]), cv[1] - cv[0]);
         const float dx1 = fmaf(fy, (cv[7] - cv[6]) - (cv[5] - cv[4]), cv[5] - cv[4]);
         const float dTx = fmaf(fz, dx1 - dx0, dx0);
@@ -122,58 +146,63 @@ __device__ inline void grad_accumulate(const VolView& vv, const float* __restric
         const float dy1 = fmaf(fx, (cv[7] - cv[5]) - (cv[6] - cv[4]), cv[6] - cv[4]);
         const float dTy = fmaf(fz, dy1 - dy0, dy0);
         const float dTz = b1 - b0;
-        const float s = v > 0.0f ? is : (v < 0.0f ? -is : 0.0f);   // sign, times d(grid)/d(metre)
-        const float wx = s * dTx, wy = s * dTy, wz = s * dTz;
-        acc.sabs += fabsf(v);
-        acc.cnt += 1;
+        // sign, times d(grid)/d(metre); zero for an invalid sample (its NaNs are selected away)
+        const float s = !ok ? 0.0f : (v > 0.0f ? is : (v < 0.0f ? -is : 0.0f));
+        const float wx = ok ? s * dTx : 0.0f, wy = ok ? s * dTy : 0.0f, wz = ok ? s * dTz : 0.0f;
         acc.gt[0] += wx;
         acc.gt[1] += wy;
         acc.gt[2] += wz;
-        acc.gr[0] += uy * wz - uz * wy;
-        acc.gr[1] += uz * wx - ux * wz;
-        acc.gr[2] += ux * wy - uy * wx;
+        acc.gr[0] += uy_m * wz - uz_m * wy;
+        acc.gr[1] += uz_m * wx - ux_m * wz;
+        acc.gr[2] += ux_m * wy - uy_m * wx;
     }
 }
 
 // Fixed-order workgroup reduction of a GradPartial; thread 0 returns the total.
 __device__ inline GradPartial grad_block_reduce(GradPartial a) {
-    __shared__ float fs[8][kGradThreads / kWave];
+    __shared__ float fs[7][kGradThreads / kWave];
+    __shared__ FixSum ss[kGradThreads / kWave];
     __shared__ int cs[kGradThreads / kWave];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    float v[7] = {a.sabs, a.gt[0], a.gt[1], a.gt[2], a.gr[0], a.gr[1], a.gr[2]};
+    float v[6] = {a.gt[0], a.gt[1], a.gt[2], a.gr[0], a.gr[1], a.gr[2]};
     float m = a.rmax;
+    FixSum sa = a.sabs;
     int c = a.cnt;
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
 #pragma unroll
-        for (int e = 0; e < 7; ++e) v[e] += __shfl_xor(v[e], off);
+        for (int e = 0; e < 6; ++e) v[e] += __shfl_xor(v[e], off);
         m = fmaxf(m, __shfl_xor(m, off));
+        sa += __shfl_xor(sa, off);
         c += __shfl_xor(c, off);
     }
     if (lane == 0) {
-        for (int e = 0; e < 7; ++e) fs[e][wid] = v[e];
-        fs[7][wid] = m;
+        for (int e = 0; e < 6; ++e) fs[e][wid] = v[e];
+        fs[6][wid] = m;
+        ss[wid] = sa;
         cs[wid] = c;
     }
     __syncthreads();
     GradPartial r = {};
     if (threadIdx.x == 0) {
         for (int w = 0; w < kGradThreads / kWave; ++w) {
-            r.sabs += fs[0][w];
+            r.sabs += ss[w];
             for (int e = 0; e < 3; ++e) {
-                r.gt[e] += fs[1 + e][w];
-                r.gr[e] += fs[4 + e][w];
+                r.gt[e] += fs[e][w];
+                r.gr[e] += fs[3 + e][w];
             }
-            r.rmax = fmaxf(r.rmax, fs[7][w]);
+            r.rmax = fmaxf(r.rmax, fs[6][w]);
             r.cnt += cs[w];
         }
     }
     return r;
 }
 
-// dE/dxi from the frozen-set sums: translation part g_t, rotation part g_r, then the chain through
-// compose(xi, base) (left Jacobian of the rotation vector phi; LITERAL also couples rho).
-__device__ inline void finish_gradient(const GradPartial& t, float scale, int mode, const double* xi, float* E_out,
+// E (as the scoring kernels form it from the exact sum) and dE/dxi from the frozen-set sums:
+// translation part g_t, rotation part g_r, then the chain through compose(xi, base) (left Jacobian
+// of the rotation vector phi; LITERAL also couples rho).
+template <int FMT>
+__device__ inline void finish_gradient(const GradPartial& t, int mode, const double* xi, float* E_out,
                                        float* grad_out, int* nv_out) {
     if (t.cnt == 0) {
         *E_out = 1.0f;
@@ -181,8 +210,8 @@ __device__ inline void finish_gradient(const GradPartial& t, float scale, int mo
         if (nv_out) *nv_out = 0;
         return;
     }
-    const float inv = scale / (float)t.cnt;
-    *E_out = t.sabs * inv;
+    const float inv = Fmt<FMT>::scale / (float)t.cnt;
+    *E_out = fitness_from<FMT>(t.sabs, t.cnt);
     double gt[3], gr[3];
     for (int e = 0; e < 3; ++e) {
         gt[e] = (double)(t.gt[e] * inv);
@@ -242,8 +271,8 @@ __device__ inline void grad_step(const VolView& vv, const float* __restrict__ px
         if (partials)
             partials[(size_t)b * S + s] = tot;
         else
-            finish_gradient(tot, Fmt<FMT>::scale, mode, xi ? xi + (size_t)b * 6 : nullptr, E_out + b,
-                            grad_out + (size_t)b * 6, nv_out ? nv_out + b : nullptr);
+            finish_gradient<FMT>(tot, mode, xi ? xi + (size_t)b * 6 : nullptr, E_out + b, grad_out + (size_t)b * 6,
+                                 nv_out ? nv_out + b : nullptr);
     }
     __syncthreads();
 }
@@ -354,7 +383,7 @@ __device__ inline void polish_prep_step(PolishState* ps, const GradPartial* gp, 
     }
     float E, g[6];
     int cnt;
-    finish_gradient(t, Fmt<FMT>::scale, mode, nullptr, &E, g, &cnt);
+    finish_gradient<FMT>(t, mode, nullptr, &E, g, &cnt);
     double nr = 0.0, nphi = 0.0;
     for (int e = 0; e < 3; ++e) {
         nr += (double)g[e] * g[e];

@@ -78,6 +78,11 @@ def test_adjoint_parity_1000_poses(pf, orc, dev, setup, mode):
         say(f"    outside: poses {b}\n    got {got[b]}\n    lo {lo[b]}\n    hi {hi[b]}")
     assert not bad.any(), f"{bad.any(1).sum()} poses outside the oracle interval; first {np.flatnonzero(bad.any(1))[:5]}"
     assert (nv.cpu().numpy() > 100).all()
+    # the adjoint's E and valid count are the scoring kernel's, bit for bit (same sample steps,
+    # exact fixed-point sum)
+    Es, nvs = pf.particles_score(gv, *pts, torch.as_tensor(pf.poses_to_f32(poses)).to(dev))
+    assert np.array_equal(E.cpu().numpy().view(np.uint32), Es.cpu().numpy().view(np.uint32))
+    assert np.array_equal(nv.cpu().numpy(), nvs.cpu().numpy())
 
 
 @pytest.mark.parametrize("mode", [0, 1])

@@ -280,21 +280,9 @@ __device__ inline bool fuse_apply(const FuseArgs& a, int64_t e, double phi, type
     return changed;
 }
 
-template <int FMT>
-__device__ inline void fuse_voxel(const FuseArgs& a, int i, int j, int k) {
-    double phi;
-    if (!fuse_decide(a, i, j, k, phi)) return;
-    typename Store<FMT>::T told, tnew;
-    const int64_t idx = ((int64_t)k * a.d.ny + j) * a.d.nx + i;
-    if (fuse_apply<FMT>(a, idx, phi, told, tnew) && a.C) {
-        write_corners(static_cast<typename Store<FMT>::T*>(a.C), a.d, i, j, k, Store<FMT>::cell(tnew));
-        if (stored_in_band<FMT>(told) != stored_in_band<FMT>(tnew)) flag_cells_of(a.m, a.d, i, j, k);
-    }
-}
-
 // Grid: a workgroup owns a brick of kFuseX x kFuseY x kFuseZ voxels (a wave per x row, each thread
-// walking kFuseZ slices, so no index division and each wave lives long enough to amortise its
-// start). A brick whose 8 corners all lie behind the camera, or all beyond one side of the image
+// walking kFuseZ slices, kFuseU at a time, so no index division and each wave lives long enough to
+// amortise its start). A brick whose 8 corners all lie behind the camera, or all beyond one side of the image
 // (a plane through the camera centre, two pixels out, with a margin far above the FP32 error), is
 // skipped as a whole: every voxel in it is a convex combination of the corners, so the per-voxel
 // tests would drop it too.
@@ -321,6 +309,80 @@ __device__ inline bool brick_outside(const FuseArgs& a, int i0, int j0, int k0, 
     return behind || out[0] || out[1] || out[2] || out[3];
 }
 
+// The voxels (i, j, k0..k1) of one thread, kFuseU slices at a time in phases, so that each phase's
+// loads are in flight together instead of one voxel's two dependent rounds (its depth pixel, then
+// its T and W) after another's: the projections of all kFuseU voxels (fuse_decide's FP64 formula,
+// with the same operations in the same order; its FP32 pre-tests only skip work and are left out),
+// then their depth pixels (a voxel outside the image reads pixel 0 and is dropped), the decisions,
+// the T and W of the updated voxels, and the updates.
+constexpr int kFuseU = 4;
+
+template <int FMT>
+__device__ inline void fuse_column(const FuseArgs& a, int i, int j, int k0, int k1) {
+    using S = Store<FMT>;
+    auto* T = static_cast<typename S::T*>(a.T);
+    auto* W = static_cast<typename S::W*>(a.W);
+    const double px = a.ox + a.vs * (double)i;
+    const double py = a.oy + a.vs * (double)j;
+    const double dx = px - a.t[0], dy = py - a.t[1];
+    for (int kb = k0; kb <= k1; kb += kFuseU) {
+        double qz[kFuseU];
+        int64_t pix[kFuseU];
+        bool in[kFuseU];
+#pragma unroll
+        for (int u = 0; u < kFuseU; ++u) {
+            const int k = kb + u;
+            const double pz = a.oz + a.vs * (double)k;
+            const double dz = pz - a.t[2];
+            qz[u] = a.R[2] * dx + a.R[5] * dy + a.R[8] * dz;
+            const double qx = a.R[0] * dx + a.R[3] * dy + a.R[6] * dz;
+            const double qy = a.R[1] * dx + a.R[4] * dy + a.R[7] * dz;
+            const double uu = a.fx * qx / qz[u] + a.cx;
+            const double vv = a.fy * qy / qz[u] + a.cy;
+            const double uf = floor(uu + 0.5), vf = floor(vv + 0.5);
+            in[u] = k <= k1 && qz[u] > 0.0 && uf >= 0.0 && uf < (double)a.width && vf >= 0.0 &&
+                    vf < (double)a.height;
+            pix[u] = in[u] ? (int64_t)(int)vf * a.width + (int)uf : 0;
+        }
+        float Dp[kFuseU];
+#pragma unroll
+        for (int u = 0; u < kFuseU; ++u) Dp[u] = a.depth[pix[u]];
+        double phi[kFuseU];
+        bool go[kFuseU];
+        int64_t e[kFuseU];
+        typename S::T told[kFuseU];
+        typename S::W wold[kFuseU];
+#pragma unroll
+        for (int u = 0; u < kFuseU; ++u) {
+            const double D = (double)Dp[u];
+            const double eta = D - qz[u];
+            go[u] = in[u] && isfinite(D) && D > 0.0 && !(eta < -a.tau);
+            double ph = eta / a.tau;
+            if (ph > 1.0) ph = 1.0;
+            phi[u] = ph;
+            e[u] = ((int64_t)(kb + u) * a.d.ny + j) * a.d.nx + i;
+            if (go[u]) {
+                told[u] = T[e[u]];
+                wold[u] = W[e[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kFuseU; ++u) {
+            if (!go[u]) continue;
+            const float w = S::decw(wold[u]);
+            const float tn = (S::dec(told[u]) * w + (float)phi[u]) / (w + 1.0f);
+            const typename S::T tnew = S::enc(tn);
+            const bool changed = !S::same(told[u], tnew);
+            if (changed) T[e[u]] = tnew;
+            W[e[u]] = S::encw(fminf(w + 1.0f, a.w_max));
+            if (changed && a.C) {
+                write_corners(static_cast<typename S::T*>(a.C), a.d, i, j, kb + u, S::cell(tnew));
+                if (stored_in_band<FMT>(told[u]) != stored_in_band<FMT>(tnew)) flag_cells_of(a.m, a.d, i, j, kb + u);
+            }
+        }
+    }
+}
+
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
     const int i0 = blockIdx.x * kFuseX, j0 = blockIdx.y * kFuseY, k0 = blockIdx.z * kFuseZ;
@@ -328,7 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
     if (brick_outside(a, i0, j0, k0, i1, j1, k1)) return;
     const int i = i0 + (int)(threadIdx.x % kFuseX), j = j0 + (int)(threadIdx.x / kFuseX);
     if (i > i1 || j > j1) return;
-    for (int k = k0; k <= k1; ++k) fuse_voxel<FMT>(a, i, j, k);
+    fuse_column<FMT>(a, i, j, k0, k1);
 }
 
 template <int FMT>

@@ -380,6 +380,68 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     }
 }
 
+// One pose against NQ points of the lane (act: the lane holds that point), each sample through
+// eval_poses' own steps (the same transform, cell, fraction, in-grid test, gather, validity test,
+// interpolation and fixed-point value, so the same bits), with the gathers of all NQ samples in
+// flight together; sample q adds to (sum[q], cnt[q]).
+template <int FMT, int LAYOUT, int NQ>
+__attribute__((always_inline))
+__device__ inline void eval_pose_points(const Gather<FMT, LAYOUT>& G, unsigned lx, unsigned ly, unsigned lz,
+                                        const GridPose& g, const float (&x)[NQ], const float (&y)[NQ],
+                                        const float (&z)[NQ], const bool (&act)[NQ], FixSum (&sum)[NQ],
+                                        int (&cnt)[NQ]) {
+    using ST = typename Fmt<FMT>::T;
+    const ST* p[NQ];
+    float f[NQ][3];
+    bool inb[NQ];
+    int cl[NQ][3];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const float gx = fmaf(g.r[0], x[q], fmaf(g.r[1], y[q], fmaf(g.r[2], z[q], g.t[0])));
+        const float gy = fmaf(g.r[3], x[q], fmaf(g.r[4], y[q], fmaf(g.r[5], z[q], g.t[1])));
+        const float gz = fmaf(g.r[6], x[q], fmaf(g.r[7], y[q], fmaf(g.r[8], z[q], g.t[2])));
+        const unsigned ux = (unsigned)floor_to_int(gx), uy = (unsigned)floor_to_int(gy), uz = (unsigned)floor_to_int(gz);
+        inb[q] = act[q] & (ux < lx) & (uy < ly) & (uz < lz);
+        f[q][0] = __builtin_amdgcn_fractf(gx);
+        f[q][1] = __builtin_amdgcn_fractf(gy);
+        f[q][2] = __builtin_amdgcn_fractf(gz);
+        if constexpr (LAYOUT == PF_LAYOUT_CELLS) {
+            p[q] = G.at(inb[q] ? G.index(ux, uy, uz) : 0u);
+        } else {
+            cl[q][0] = (int)min(ux, lx - 1u);
+            cl[q][1] = (int)min(uy, ly - 1u);
+            cl[q][2] = (int)min(uz, lz - 1u);
+            if constexpr (LAYOUT == PF_LAYOUT_LINEAR) p[q] = G.addr(cl[q][0], cl[q][1], cl[q][2]);
+        }
+    }
+    if constexpr (LAYOUT == PF_LAYOUT_BRICKS) {
+        int slot[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) slot[q] = G.slot(G.key(cl[q][0], cl[q][1], cl[q][2]));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) p[q] = G.at(slot[q], cl[q][0], cl[q][1], cl[q][2]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    float c[NQ][8];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) G.load(p[q], c[q]);
+    __builtin_amdgcn_sched_barrier(0);
+    constexpr bool kNanTest = LAYOUT != PF_LAYOUT_LINEAR && Fmt<FMT>::nan_cells;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        bool ok = inb[q];
+        if constexpr (!kNanTest) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) ok &= Fmt<FMT>::in_band(c[q][e]);
+        }
+        const float v = trilerp(f[q][0], f[q][1], f[q][2], c[q]);
+        if constexpr (kNanTest) ok &= !__builtin_isnan(v);
+        sum[q] += (FixSum)(ok ? fixed_point<FMT>(v) : 0u);
+        cnt[q] += ok ? 1 : 0;
+    }
+}
+
 // Workgroup reduction of TK exact (sum, count) pairs; thread j < TK returns pair j in s[0], c[0].
 template <int TK, int BLOCK>
 __device__ inline void block_reduce(FixSum (&s)[TK], int (&c)[TK]) {

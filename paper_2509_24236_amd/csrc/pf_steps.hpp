@@ -275,16 +275,50 @@ __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px,
     __shared__ float pose_sh[12];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int n = n_dev ? *n_dev : n_host;
+    // This workgroup's chunk of the view (and of the next view): the first kPts points of each per
+    // thread are loaded now, while the pose they are scored at is being formed; the update step's
+    // chunks hold at most kPts * kAdvThreads points (a chunk beyond that is scored point by point).
+    constexpr int kPts = 2;
+    const bool score1 = ADV || !nv.x, score2 = nv.x != nullptr;
+    const float sc = vv.inv_vs;
+    int q0[2] = {0, 0}, q1[2] = {0, 0};
+    float xs[2 * kPts], ys[2 * kPts], zs[2 * kPts];
+    bool act[2 * kPts];
+    {
+        // (a lane without a point reads point 0 of a view that exists, always in bounds)
+        const float* X[2] = {px, score2 ? nv.x : px};
+        const float* Y[2] = {py, score2 ? nv.y : py};
+        const float* Z[2] = {pz, score2 ? nv.z : pz};
+        const int m[2] = {n, score2 ? *nv.n_dev : 0};
+        const bool on[2] = {score1, score2};
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int chunk = (m[v] + nblk - 1) / nblk;
+            q0[v] = blk * chunk;
+            q1[v] = on[v] ? min(m[v], q0[v] + chunk) : 0;
+#pragma unroll
+            for (int r = 0; r < kPts; ++r) {
+                const int q = q0[v] + (int)threadIdx.x + r * kAdvThreads;
+                const int s = v * kPts + r;
+                act[s] = q < q1[v];
+                const int qq = act[s] ? q : 0;
+                xs[s] = X[v][qq] * sc;
+                ys[s] = Y[v][qq] * sc;
+                zs[s] = Z[v][qq] * sc;
+            }
+        }
+    }
     if constexpr (ADV) {
         const double* dl = state_deltas(st);
         const float E0 = fitness[0];
         const int Kc = st->K_cur;   // particles of the iteration just scored
         double acc[6] = {0, 0, 0, 0, 0, 0};
         int na = 0;
-        // Four particles per pass with all their loads issued together: membership is a 0/1
-        // factor (adding an exact zero leaves a sum unchanged), so there is no branch to serialise
-        // the loads; indices past K_cur read in-bounds slots (the buffers hold K + 1) with factor 0.
-        constexpr int kU = 4;
+        // Twelve particles per pass (all of them for K = 3072) with all their loads issued together:
+        // membership is a 0/1 factor (adding an exact zero leaves a sum unchanged), so there is no
+        // branch to serialise the loads; indices past K_cur read in-bounds slots (the buffers hold
+        // K + 1) with factor 0.
+        constexpr int kU = 12;
         for (int kb = 1 + threadIdx.x; kb <= Kc; kb += kU * kAdvThreads) {
             double m[kU];
             int kk[kU];
@@ -357,29 +391,50 @@ __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px,
         }
     }
     __syncthreads();
-    // this workgroup's chunk of the view (and of the next view), scored with the scoring kernel's
-    // arithmetic
+    // the chunks scored with the scoring kernel's arithmetic: the preloaded samples of both views
+    // with their gathers in flight together, then any points beyond them one by one
     const Gather<FMT, LAYOUT> G = make_gather<FMT, LAYOUT>(vv);
     GridPose g[1] = {fold_pose(pose_sh, vv.inv_vs, vv.gx0, vv.gy0, vv.gz0)};
     const unsigned lx = (unsigned)(vv.nx - 1), ly = (unsigned)(vv.ny - 1), lz = (unsigned)(vv.nz - 1);
-    const float sc = vv.inv_vs;
-    auto chunk_sums = [&](const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
-                          int m, Partial* pt) {
-        const int chunk = (m + nblk - 1) / nblk;
-        const int q0 = blk * chunk, q1 = min(m, q0 + chunk);
-        FixSum sum[1] = {0};
-        int cnt[1] = {0};
-        for (int q = q0 + (int)threadIdx.x; q < q1; q += kAdvThreads)
-            eval_poses<FMT, LAYOUT, 1>(G, lx, ly, lz, g, x[q] * sc, y[q] * sc, z[q] * sc, sum, cnt);
-        block_reduce<1, kAdvThreads>(sum, cnt);
-        if (threadIdx.x == 0) {
-            pt[blk].sum = sum[0];
-            pt[blk].cnt = cnt[0];
+    FixSum ss[2 * kPts];
+    int cs[2 * kPts];
+#pragma unroll
+    for (int s = 0; s < 2 * kPts; ++s) {
+        ss[s] = 0;
+        cs[s] = 0;
+    }
+    eval_pose_points<FMT, LAYOUT, 2 * kPts>(G, lx, ly, lz, g[0], xs, ys, zs, act, ss, cs);
+    FixSum sum[2];
+    int cnt[2];
+    const float* X[2] = {px, nv.x};
+    const float* Y[2] = {py, nv.y};
+    const float* Z[2] = {pz, nv.z};
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        FixSum s1[1] = {0};
+        int c1[1] = {0};
+        for (int q = q0[v] + (int)threadIdx.x + kPts * kAdvThreads; q < q1[v]; q += kAdvThreads)
+            eval_poses<FMT, LAYOUT, 1>(G, lx, ly, lz, g, X[v][q] * sc, Y[v][q] * sc, Z[v][q] * sc, s1, c1);
+        sum[v] = s1[0];
+        cnt[v] = c1[0];
+#pragma unroll
+        for (int r = 0; r < kPts; ++r) {
+            sum[v] += ss[v * kPts + r];
+            cnt[v] += cs[v * kPts + r];
         }
-        __syncthreads();
-    };
-    if (ADV || !nv.x) chunk_sums(px, py, pz, n, state_partials(st, K));
-    if (nv.x) chunk_sums(nv.x, nv.y, nv.z, *nv.n_dev, state_partials_next(st, K));
+    }
+    block_reduce<2, kAdvThreads>(sum, cnt);
+    if (threadIdx.x == 0 && score1) {
+        Partial* pt = state_partials(st, K);
+        pt[blk].sum = sum[0];
+        pt[blk].cnt = cnt[0];
+    }
+    if (threadIdx.x == 1 && score2) {
+        Partial* pt = state_partials_next(st, K);
+        pt[blk].sum = sum[0];
+        pt[blk].cnt = cnt[0];
+    }
+    __syncthreads();
 }
 
 // (sum, count) of n_partials exact partials, in every thread of a 256-thread workgroup.

@@ -847,14 +847,20 @@ def main():
             Rr, tr = rel[t]
             R0, t0 = Rp @ Rr, Rp @ tr + tp            # P_t^(0) = P_{t-1} P_(t,t-1)
             trk.set_frame(t)
-            R, tt, st = trk.track(vol, depth[t], R0, t0)
-            if measured:
-                ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                ev[0].record()
-            vol.integrate(depth[t], intr, *(frames["gt"][t] if fuse_at_gt else (R, tt)))
-            if measured:
-                ev[1].record()
-                fuse_events.append(ev)
+            if fuse_at_gt or measured:
+                # (the measured frame fuses in a call of its own, between the events that time it)
+                R, tt, st = trk.track(vol, depth[t], R0, t0)
+                if measured:
+                    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                    ev[0].record()
+                vol.integrate(depth[t], intr, *(frames["gt"][t] if fuse_at_gt else (R, tt)))
+                if measured:
+                    ev[1].record()
+                    fuse_events.append(ev)
+            else:
+                # track, then fuse at the tracked pose in the same call: the fusion is enqueued on the
+                # device before the call waits for its result
+                R, tt, st = trk.track_fuse(vol, depth[t], R0, t0)
             est.append((R, tt))
             iters_run.append(st.n_iters)
             # the method's samples: each iteration scores its particles and the current pose on S_i

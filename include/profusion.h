@@ -380,6 +380,19 @@ int32_t track_frame(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
                     const pf_pose* init, const pf_track_params* p, pf_pose* out,
                     pf_track_stats* stats, void* workspace, size_t ws_bytes, void* stream);
 
+/* One frame of the method's per-frame cycle (Sec. III "Method overview", Fig. 2: the pose is
+ * tracked, then the frame is fused into the TSDF at that pose): track_frame, then the fusion of
+ * tsdf_integrate at the pose written to *out, with the same results as those two calls in turn.
+ * For the dense layouts the fusion reads the tracked pose from the device and is enqueued before
+ * the call waits for its read-back, so the GPU fuses while the host reads the result; the fusion
+ * may still be running when the call returns (it is ordered on `stream`). For BRICKS the fusion is
+ * enqueued after the read-back, from the host. The volume is fused only when the call returns
+ * PF_OK. The first call on a host thread allocates a small pinned host buffer and an event for the
+ * read-back (kept until the process ends). Needs v->weight. */
+int32_t track_frame_fuse(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* init,
+                         const pf_track_params* p, pf_pose* out, pf_track_stats* stats, void* workspace,
+                         size_t ws_bytes, void* stream);
+
 /* For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
  * hipMalloc): track_frame with its workspace in an array the library holds on each GPU instead
  * of a caller buffer. Same arguments, results and synchronisation as track_frame, bit for bit,

@@ -90,7 +90,7 @@ class pf_batch_plan(C.Structure):
 # every symbol include/profusion.h declares
 EXPORTS = ("pf_last_error", "tsdf_bytes", "tsdf_cells_offset", "tsdf_mask_offset", "tsdf_brick_offsets", "tsdf_bricks_used", "tsdf_init", "tsdf_integrate", "tsdf_export_linear", "tsdf_import_linear",
            "backproject", "particles_score", "particles_score_grad", "pf_score_config", "pf_score_mask", "particles_state_bytes", "particles_state_init", "particles_update",
-           "track_workspace_bytes", "track_frame", "track_frame_noalloc", "track_batch_workspace_bytes", "track_batch_create",
+           "track_workspace_bytes", "track_frame", "track_frame_fuse", "track_frame_noalloc", "track_batch_workspace_bytes", "track_batch_create",
            "track_batch_run", "track_batch_results", "track_batch_destroy", "pf_timing_enable", "pf_timing_read")
 
 _lib = None
@@ -133,6 +133,7 @@ def lib() -> C.CDLL:
     L.track_workspace_bytes.argtypes = [P(pf_intrinsics), P(pf_track_params)]
     L.track_frame.argtypes = [P(pf_tsdf), vp, P(pf_intrinsics), P(pf_pose), P(pf_track_params), P(pf_pose),
                               P(pf_track_stats), vp, C.c_size_t, vp]
+    L.track_frame_fuse.argtypes = L.track_frame.argtypes
     L.track_frame_noalloc.argtypes = [P(pf_tsdf), vp, P(pf_intrinsics), P(pf_pose), P(pf_track_params), P(pf_pose),
                                       P(pf_track_stats), vp]
     L.track_batch_workspace_bytes.restype = C.c_size_t
@@ -466,6 +467,18 @@ class Tracker:
         _check(lib().track_frame(C.byref(vol.desc), _ptr(depth), C.byref(self._intr_c), C.byref(make_pose(R0, t0)),
                                  C.byref(self._params_c), C.byref(out), C.byref(st), _ptr(self.ws),
                                  C.c_size_t(self.ws_bytes), _stream(stream)))
+        R, t = pose_rt(out)
+        return R, t, st
+
+    def track_fuse(self, vol: Tsdf, depth, R0, t0, stream=None):
+        """Tracks the frame, then fuses it into `vol` at the tracked pose (track_frame_fuse: the
+        fusion of a dense volume is enqueued on the device before the call waits for its
+        result): returns (R, t, stats)."""
+        out = pf_pose()
+        st = pf_track_stats()
+        _check(lib().track_frame_fuse(C.byref(vol.desc), _ptr(depth), C.byref(self._intr_c),
+                                      C.byref(make_pose(R0, t0)), C.byref(self._params_c), C.byref(out), C.byref(st),
+                                      _ptr(self.ws), C.c_size_t(self.ws_bytes), _stream(stream)))
         R, t = pose_rt(out)
         return R, t, st
 

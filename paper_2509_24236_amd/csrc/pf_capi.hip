@@ -20,7 +20,7 @@ int32_t update(const VolView& vv, const Points& pts, const float* fitness, void*
 size_t workspace_bytes(const pf_intrinsics* K, const pf_track_params* p);
 int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* init,
               const pf_track_params* p, pf_pose* out, pf_track_stats* stats, void* workspace, size_t ws_bytes,
-              hipStream_t s);
+              hipStream_t s, bool fuse);
 int32_t timing_enable(int on);
 int32_t score_config(int tk, int block);
 int32_t score_mask(int mode);
@@ -462,7 +462,19 @@ int32_t track_frame(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
     if ((rc = check_pose(init, "track_frame"))) return rc;
     if ((rc = check_params(p, "track_frame"))) return rc;
     if (!depth || !out || !workspace) return set_error(PF_EINVAL, "track_frame: null pointer");
-    return track(v, depth, K, init, p, out, stats, workspace, ws_bytes, (hipStream_t)stream);
+    return track(v, depth, K, init, p, out, stats, workspace, ws_bytes, (hipStream_t)stream, false);
+}
+
+int32_t track_frame_fuse(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* init,
+                         const pf_track_params* p, pf_pose* out, pf_track_stats* stats, void* workspace,
+                         size_t ws_bytes, void* stream) {
+    int32_t rc;
+    if ((rc = check_tsdf(v, "track_frame_fuse"))) return rc;
+    if ((rc = check_intr(K, "track_frame_fuse"))) return rc;
+    if ((rc = check_pose(init, "track_frame_fuse"))) return rc;
+    if ((rc = check_params(p, "track_frame_fuse"))) return rc;
+    if (!depth || !out || !workspace) return set_error(PF_EINVAL, "track_frame_fuse: null pointer");
+    return track(v, depth, K, init, p, out, stats, workspace, ws_bytes, (hipStream_t)stream, true);
 }
 
 int32_t track_frame_noalloc(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* init,
@@ -479,7 +491,7 @@ int32_t track_frame_noalloc(const pf_tsdf* v, const float* depth, const pf_intri
                          need, (size_t)PF_NOALLOC_WORKSPACE_BYTES);
     void* ws = nullptr;
     if ((rc = scratch_of_current_device(&ws))) return rc;
-    return track(v, depth, K, init, p, out, stats, ws, (size_t)PF_NOALLOC_WORKSPACE_BYTES, (hipStream_t)stream);
+    return track(v, depth, K, init, p, out, stats, ws, (size_t)PF_NOALLOC_WORKSPACE_BYTES, (hipStream_t)stream, false);
 }
 
 int32_t pf_timing_enable(int32_t on) { return timing_enable(on); }

@@ -182,6 +182,12 @@ struct Points {
 int32_t launch_tsdf_init(const pf_tsdf* v, hipStream_t s);
 int32_t launch_tsdf_integrate(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* P,
                               hipStream_t s);
+// Dense layouts: the same fusion at the camera pose R_dev [9], t_dev [3] (FP64, device memory,
+// e.g. the tracker's state), without the pose passing through the host; args_dev: device scratch of
+// fuse_args_bytes() bytes (the arguments the kernels read). PF_EUNSUPPORTED for BRICKS.
+int32_t launch_tsdf_integrate_at(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const double* R_dev,
+                                 const double* t_dev, void* args_dev, hipStream_t s);
+size_t fuse_args_bytes();
 int32_t launch_tsdf_export(const pf_tsdf* v, float* T, float* W, hipStream_t s);
 int32_t launch_tsdf_import(const pf_tsdf* v, const float* T, const float* W, hipStream_t s);
 

@@ -200,7 +200,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
     size_t pts, pix, counts, views[3], tiles_mask[3], tiles_start[3], vcount, poses, fit, nv, state, recs, polish, fin,
-        rb, total;
+        rb, fuse, total;
 };
 
 WsLayout ws_layout(const pf_intrinsics* K, const pf_track_params* p) {
@@ -251,6 +251,8 @@ WsLayout ws_layout(const pf_intrinsics* K, const pf_track_params* p) {
     off += align_up(256 + kMaxPartials * 8);
     L.rb = off;
     off += align_up(sizeof(Readback));
+    L.fuse = off;   // the arguments of the fusion at the tracked pose (track_frame_fuse)
+    off += align_up(fuse_args_bytes());
     L.total = off;
     return L;
 }
@@ -338,9 +340,32 @@ bool forecast_matches(const RegimeForecast& f, const pf_track_params* p, float i
 
 }  // namespace
 
+// The read-back of a call that fuses: pinned host memory (a copy into it does not wait for the host)
+// and an event after the copy, both per host thread, allocated on the first such call and kept.
+thread_local Readback* g_pinned_rb = nullptr;
+thread_local hipEvent_t g_rb_event[64] = {};
+
+int32_t fuse_readback(Readback** rb, hipEvent_t* ev) {
+    if (!g_pinned_rb && hipHostMalloc(reinterpret_cast<void**>(&g_pinned_rb), sizeof(Readback), hipHostMallocDefault) !=
+                            hipSuccess) {
+        g_pinned_rb = nullptr;
+        return set_error(PF_EHIP, "track_frame_fuse: pinned read-back buffer: %s", hipGetErrorString(hipGetLastError()));
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return set_error(PF_EHIP, "track_frame_fuse: no current device below 64");
+    if (!g_rb_event[dev] && hipEventCreateWithFlags(&g_rb_event[dev], hipEventDisableTiming) != hipSuccess) {
+        g_rb_event[dev] = nullptr;
+        return set_error(PF_EHIP, "track_frame_fuse: event: %s", hipGetErrorString(hipGetLastError()));
+    }
+    *rb = g_pinned_rb;
+    *ev = g_rb_event[dev];
+    return PF_OK;
+}
+
 int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* init,
               const pf_track_params* p, pf_pose* out, pf_track_stats* stats, void* workspace, size_t ws_bytes,
-              hipStream_t s) {
+              hipStream_t s, bool fuse) {
     const WsLayout L = ws_layout(K, p);
     if (ws_bytes < L.total)
         return set_error(PF_ENOMEM, "track_frame: workspace of %zu bytes, %zu needed", ws_bytes, L.total);
@@ -475,11 +500,27 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
                                            : nullptr,
                        rb);
     if ((rc = check_launch("track_frame read-back"))) return rc;
-    Readback hrb;
-    if (hipMemcpyAsync(&hrb, rb, sizeof hrb, hipMemcpyDeviceToHost, s) != hipSuccess)
+    // Fusing a dense volume: the fusion at the tracked pose (read by the device from the state) is
+    // enqueued right after the read-back copy, and the host waits for the copy only, so the GPU
+    // fuses while the host reads the result (a sparse volume is fused from the host afterwards).
+    Readback local;
+    Readback* hp = &local;
+    hipEvent_t ev = nullptr;
+    const bool fuse_here = fuse && v->layout != PF_LAYOUT_BRICKS;
+    if (fuse && (rc = fuse_readback(&hp, &ev))) return rc;
+    if (hipMemcpyAsync(hp, rb, sizeof(Readback), hipMemcpyDeviceToHost, s) != hipSuccess)
         return set_error(PF_EHIP, "track_frame: read-back failed: %s", hipGetErrorString(hipGetLastError()));
-    hipError_t e = hipStreamSynchronize(s);
+    hipError_t e;
+    if (fuse_here) {
+        if (hipEventRecord(ev, s) != hipSuccess)
+            return set_error(PF_EHIP, "track_frame_fuse: %s", hipGetErrorString(hipGetLastError()));
+        if ((rc = launch_tsdf_integrate_at(v, depth, K, st->R, st->t, ws + L.fuse, s))) return rc;
+        e = hipEventSynchronize(ev);
+    } else {
+        e = hipStreamSynchronize(s);
+    }
     if (e != hipSuccess) return set_error(PF_EHIP, "track_frame: %s", hipGetErrorString(e));
+    const Readback hrb = *hp;
     const pf_track_state& hs = hrb.st;
     const IterRec* hr = hrb.recs;
     const float ef = hrb.ef;
@@ -533,6 +574,7 @@ int32_t track(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, cons
         stats->n_valid_final = nvf;
         stats->lost = nvf < p->min_valid ? 1 : 0;
     }
+    if (fuse && !fuse_here) return launch_tsdf_integrate(v, depth, K, out, s);
     return PF_OK;
 }
 

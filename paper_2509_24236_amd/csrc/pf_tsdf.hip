@@ -207,6 +207,28 @@ struct FuseArgs {
     double zfar;   // largest camera depth of a grid corner: no voxel lies deeper
 };
 
+// The fields of a fusion that depend on the camera pose (R, t): the pose itself and the FP32 copies
+// of its projection for the pre-tests. The same code on the host and on the device (this file is
+// compiled without contraction on both), so a pose read from device memory gives the same fields
+// as the same pose passed from the host.
+__host__ __device__ inline void fuse_pose_fields(FuseArgs& a, const double* R, const double* t) {
+    for (int q = 0; q < 9; ++q) a.R[q] = R[q];
+    for (int q = 0; q < 3; ++q) a.t[q] = t[q];
+    for (int r = 0; r < 3; ++r) {   // camera axis r = column r of R
+        a.q0[r] = (float)(a.R[r] * (a.ox - a.t[0]) + a.R[3 + r] * (a.oy - a.t[1]) + a.R[6 + r] * (a.oz - a.t[2]));
+        a.qi[r] = (float)(a.R[r] * a.vs);
+        a.qj[r] = (float)(a.R[3 + r] * a.vs);
+        a.qk[r] = (float)(a.R[6 + r] * a.vs);
+    }
+    a.zfar = -1e300;
+    for (int c = 0; c < 8; ++c) {
+        const double p[3] = {a.ox + a.vs * ((c & 1) ? a.d.nx - 1 : 0), a.oy + a.vs * ((c & 2) ? a.d.ny - 1 : 0),
+                             a.oz + a.vs * ((c & 4) ? a.d.nz - 1 : 0)};
+        a.zfar = fmax(a.zfar, a.R[2] * (p[0] - a.t[0]) + a.R[5] * (p[1] - a.t[1]) + a.R[8] * (p[2] - a.t[2]));
+    }
+    a.zfar += 1e-6 * (fabs(a.zfar) + 1.0);
+}
+
 // The projection is evaluated in FP64 with the same operation order as the plain definition,
 // and this file is compiled without multiply-add contraction, so the per-voxel decisions
 // (updated or not, which pixel) are those of an FP64 evaluation of the formula as written; the
@@ -383,8 +405,16 @@ __device__ inline void fuse_column(const FuseArgs& a, int i, int j, int k0, int 
     }
 }
 
+// Fills the pose fields of a fusion from a pose in device memory (the tracker's state).
+__global__ void k_fuse_pose(FuseArgs* out, FuseArgs base, const double* R, const double* t) {
+    fuse_pose_fields(base, R, t);
+    *out = base;
+}
+
+// ap != nullptr: the fusion's arguments come from device memory (a pose the device computed).
 template <int FMT>
-__global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a) {
+__global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a0, const FuseArgs* __restrict__ ap) {
+    const FuseArgs a = ap ? *ap : a0;
     const int i0 = blockIdx.x * kFuseX, j0 = blockIdx.y * kFuseY, k0 = blockIdx.z * kFuseZ;
     const int i1 = min(a.d.nx, i0 + kFuseX) - 1, j1 = min(a.d.ny, j0 + kFuseY) - 1, k1 = min(a.d.nz, k0 + kFuseZ) - 1;
     if (brick_outside(a, i0, j0, k0, i1, j1, k1)) return;
@@ -765,8 +795,8 @@ int32_t init_t(const pf_tsdf* v, hipStream_t s) {
     return check_launch("tsdf_init");
 }
 
-template <int FMT>
-int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* P, hipStream_t s) {
+// The fields of a fusion that do not depend on the pose.
+FuseArgs fuse_base(const pf_tsdf* v, const float* depth, const pf_intrinsics* K) {
     FuseArgs a;
     a.T = v->tsdf;
     a.W = v->weight;
@@ -778,21 +808,6 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
     a.ox = v->origin[0];
     a.oy = v->origin[1];
     a.oz = v->origin[2];
-    for (int q = 0; q < 9; ++q) a.R[q] = P->R[q];
-    for (int q = 0; q < 3; ++q) a.t[q] = P->t[q];
-    for (int r = 0; r < 3; ++r) {   // camera axis r = column r of R
-        a.q0[r] = (float)(a.R[r] * (a.ox - a.t[0]) + a.R[3 + r] * (a.oy - a.t[1]) + a.R[6 + r] * (a.oz - a.t[2]));
-        a.qi[r] = (float)(a.R[r] * v->voxel_size);
-        a.qj[r] = (float)(a.R[3 + r] * v->voxel_size);
-        a.qk[r] = (float)(a.R[6 + r] * v->voxel_size);
-    }
-    a.zfar = -1e300;
-    for (int c = 0; c < 8; ++c) {
-        const double p[3] = {a.ox + a.vs * ((c & 1) ? v->nx - 1 : 0), a.oy + a.vs * ((c & 2) ? v->ny - 1 : 0),
-                             a.oz + a.vs * ((c & 4) ? v->nz - 1 : 0)};
-        a.zfar = fmax(a.zfar, a.R[2] * (p[0] - a.t[0]) + a.R[5] * (p[1] - a.t[1]) + a.R[8] * (p[2] - a.t[2]));
-    }
-    a.zfar += 1e-6 * (fabs(a.zfar) + 1.0);
     a.fx = K->fx;
     a.fy = K->fy;
     a.cx = K->cx;
@@ -801,6 +816,27 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
     a.height = K->height;
     a.w_max = (float)v->w_max;
     a.depth = depth;
+    return a;
+}
+
+// The dense fusion's launches; ap != nullptr: the arguments (pose fields included) are read from
+// that device copy instead of `a`.
+template <int FMT>
+int32_t integrate_dense(const pf_tsdf* v, const FuseArgs& a, const FuseArgs* ap, hipStream_t s) {
+    const dim3 grid((unsigned)((a.d.nx + kFuseX - 1) / kFuseX), (unsigned)((a.d.ny + kFuseY - 1) / kFuseY),
+                    (unsigned)((a.d.nz + kFuseZ - 1) / kFuseZ));
+    hipLaunchKernelGGL(k_integrate<FMT>, grid, dim3(kBlock), 0, s, a, ap);
+    if (v->layout == PF_LAYOUT_CELLS) {
+        const int64_t words = (int64_t)a.m.mwx * a.m.mwy * a.m.mwz;
+        hipLaunchKernelGGL(k_mask_update<FMT>, dim3(grid_for(words)), dim3(kBlock), 0, s, v->tsdf, a.d, a.m, 0);
+    }
+    return check_launch("tsdf_integrate");
+}
+
+template <int FMT>
+int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const pf_pose* P, hipStream_t s) {
+    FuseArgs a = fuse_base(v, depth, K);
+    fuse_pose_fields(a, P->R, P->t);
     if (v->layout == PF_LAYOUT_BRICKS) {
         const BrickArgs b = brick_args(v);
         a.T = b.T;
@@ -815,14 +851,16 @@ int32_t integrate_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K
         hipLaunchKernelGGL(k_bricks_mask<FMT>, dim3(kBrickGrid), dim3(kBlock), 0, s, b);
         return check_launch("tsdf_integrate (bricks)");
     }
-    const dim3 grid((unsigned)((a.d.nx + kFuseX - 1) / kFuseX), (unsigned)((a.d.ny + kFuseY - 1) / kFuseY),
-                    (unsigned)((a.d.nz + kFuseZ - 1) / kFuseZ));
-    hipLaunchKernelGGL(k_integrate<FMT>, grid, dim3(kBlock), 0, s, a);
-    if (v->layout == PF_LAYOUT_CELLS) {
-        const int64_t words = (int64_t)a.m.mwx * a.m.mwy * a.m.mwz;
-        hipLaunchKernelGGL(k_mask_update<FMT>, dim3(grid_for(words)), dim3(kBlock), 0, s, v->tsdf, a.d, a.m, 0);
-    }
-    return check_launch("tsdf_integrate");
+    return integrate_dense<FMT>(v, a, nullptr, s);
+}
+
+template <int FMT>
+int32_t integrate_at_t(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const double* R_dev,
+                       const double* t_dev, void* args_dev, hipStream_t s) {
+    const FuseArgs a = fuse_base(v, depth, K);
+    FuseArgs* ap = static_cast<FuseArgs*>(args_dev);
+    hipLaunchKernelGGL(k_fuse_pose, dim3(1), dim3(1), 0, s, ap, a, R_dev, t_dev);
+    return integrate_dense<FMT>(v, a, ap, s);
 }
 
 template <int FMT>
@@ -880,6 +918,20 @@ int32_t launch_tsdf_integrate(const pf_tsdf* v, const float* depth, const pf_int
         default: return set_error(PF_EUNSUPPORTED, "unsupported format %d", v->format);
     }
 }
+
+int32_t launch_tsdf_integrate_at(const pf_tsdf* v, const float* depth, const pf_intrinsics* K, const double* R_dev,
+                                 const double* t_dev, void* args_dev, hipStream_t s) {
+    if (v->layout == PF_LAYOUT_BRICKS)
+        return set_error(PF_EUNSUPPORTED, "tsdf_integrate at a device pose: dense layouts only");
+    switch (v->format) {
+        case PF_F32_W_F32: return integrate_at_t<PF_F32_W_F32>(v, depth, K, R_dev, t_dev, args_dev, s);
+        case PF_F16_W_U8: return integrate_at_t<PF_F16_W_U8>(v, depth, K, R_dev, t_dev, args_dev, s);
+        case PF_I16_W_U8: return integrate_at_t<PF_I16_W_U8>(v, depth, K, R_dev, t_dev, args_dev, s);
+        default: return set_error(PF_EUNSUPPORTED, "unsupported format %d", v->format);
+    }
+}
+
+size_t fuse_args_bytes() { return sizeof(FuseArgs); }
 
 int32_t launch_tsdf_export(const pf_tsdf* v, float* T, float* W, hipStream_t s) {
     switch (v->format) {

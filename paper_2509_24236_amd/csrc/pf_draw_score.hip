@@ -2,6 +2,7 @@
 // around the current pose, then the fitness of every particle), in one launch per iteration instead
 // of a draw launch followed by a scoring launch.
 #include <atomic>
+#include <type_traits>
 
 #include "pf_steps.hpp"
 
@@ -13,7 +14,8 @@ namespace {
 // each 4-pose workgroup draws its particles 4 blockIdx.x + 1 .. 4 blockIdx.x + 4 (the same FP64
 // composition, into `poses`, the state's deltas and LDS) and scores them on the view; workgroup 0
 // also records slot 0 and E_0. One launch and one dependent-launch gap fewer per iteration.
-template <int FMT, int LAYOUT, bool MASK>
+// NARROW: the volume passes narrow_grid (score_step).
+template <int FMT, int LAYOUT, bool MASK, bool NARROW>
 __global__ __launch_bounds__(256) void k_draw_score(VolView vv, Points S, pf_track_state* st, int K, int n_partials,
                                                    int first, IterRec* recs, int e0_partials, float* poses,
                                                    float* fit, int* nv) {
@@ -32,7 +34,7 @@ __global__ __launch_bounds__(256) void k_draw_score(VolView vv, Points S, pf_tra
     __syncthreads();
     const int Kl = min(4, P.K_it - k0);
     if (Kl <= 0) return;
-    score_step<FMT, LAYOUT, 4, 256, MASK>(vv, S.x, S.y, S.z, S.n_dev ? *S.n_dev : S.n, pose_sh, Kl, 0, fit + 1 + k0,
+    score_step<FMT, LAYOUT, 4, 256, MASK, NARROW>(vv, S.x, S.y, S.z, S.n_dev ? *S.n_dev : S.n, pose_sh, Kl, 0, fit + 1 + k0,
                                           nv + 1 + k0);
 }
 
@@ -52,9 +54,14 @@ void warm_draw_score(int format, int layout) {
     with_volume(format, layout, [&](auto fmt, auto lay) {
         constexpr int F = decltype(fmt)::value, LY = decltype(lay)::value;
         hipFuncAttributes attr;
-        (void)hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_draw_score<F, LY, false>));
-        if constexpr (LY != PF_LAYOUT_LINEAR)
-            (void)hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_draw_score<F, LY, true>));
+        auto warm = [&](auto narrow) {
+            constexpr bool C = decltype(narrow)::value;
+            (void)hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_draw_score<F, LY, false, C>));
+            if constexpr (LY != PF_LAYOUT_LINEAR)
+                (void)hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_draw_score<F, LY, true, C>));
+        };
+        warm(std::true_type{});
+        warm(std::false_type{});
         return PF_OK;
     });
 }
@@ -64,18 +71,18 @@ int32_t launch_draw_score(const VolView& vv, const Points& S, pf_track_state* st
                           hipStream_t s) {
     const dim3 grid((unsigned)((K_i + 3) / 4));
     const bool mask = score_regime_masked(vv.layout, regime);
+    const bool narrow = narrow_grid(vv);
     return with_volume(vv.format, vv.layout, [&](auto fmt, auto layout) {
         constexpr int F = decltype(fmt)::value, LY = decltype(layout)::value;
+        auto go = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, vv, S, st, K, n_partials, first ? 1 : 0, recs,
+                               e0_partials, poses, fit, nv);
+            return check_launch("track_frame particle launch");
+        };
         if constexpr (LY != PF_LAYOUT_LINEAR) {
-            if (mask) {
-                hipLaunchKernelGGL((k_draw_score<F, LY, true>), grid, dim3(256), 0, s, vv, S, st, K, n_partials,
-                                   first ? 1 : 0, recs, e0_partials, poses, fit, nv);
-                return check_launch("track_frame particle launch");
-            }
+            if (mask) return narrow ? go(k_draw_score<F, LY, true, true>) : go(k_draw_score<F, LY, true, false>);
         }
-        hipLaunchKernelGGL((k_draw_score<F, LY, false>), grid, dim3(256), 0, s, vv, S, st, K, n_partials,
-                           first ? 1 : 0, recs, e0_partials, poses, fit, nv);
-        return check_launch("track_frame particle launch");
+        return narrow ? go(k_draw_score<F, LY, false, true>) : go(k_draw_score<F, LY, false, false>);
     });
 }
 

@@ -109,6 +109,17 @@ struct VolView {
 
 VolView make_view(const pf_tsdf* v);
 
+// Whether the scoring launches may take their narrow form for this volume (one instantiation each
+// way, chosen at launch): a cubic grid (the in-grid test is one three-way maximum and a compare)
+// and, for the cell replica, blocks that 32-bit byte offsets address, with row and slice strides
+// below 2^24 bytes (24-bit multiplies). A 512^3 FP32 replica (511^3 blocks of 32 B) just fits.
+inline bool narrow_grid(const VolView& v) {
+    if (v.nx != v.ny || v.ny != v.nz) return false;
+    if (v.layout != PF_LAYOUT_CELLS) return true;
+    const uint64_t block = v.format == PF_F32_W_F32 ? 32 : 16, c = (uint64_t)(v.nx - 1);
+    return c * c * c * block <= (1ull << 32) && c * c * block < (1ull << 24);
+}
+
 // Cell-validity mask of a CELLS T buffer: after the replica, one 64-bit word per block of 4x4x4
 // cells (bit (x&3) + 4 (y&3) + 16 (z&3) of word ((z/4) mwy + y/4) mwx + x/4 is set iff all 8
 // corners of cell (x, y, z) are in the band), then one byte per word that fusion sets when a

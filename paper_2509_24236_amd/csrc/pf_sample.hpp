@@ -142,6 +142,17 @@ struct Gather<FMT, PF_LAYOUT_CELLS> {
     }
     __device__ inline const ST* at(unsigned idx) const { return C + ((size_t)idx << 3); }
     __device__ inline const ST* addr(int cx, int cy, int cz) const { return at(index(cx, cy, cz)); }
+    // byte offset of a cell's block, for a replica that 32-bit offsets address (row and slice
+    // strides in bytes below 2^24: 24-bit multiplies); the gather then adds it to the uniform base
+    // in the load itself, with no 64-bit address arithmetic
+    static constexpr unsigned kBlockShift = sizeof(ST) == 4 ? 5 : 4;
+    unsigned rowb, sliceb;   // cnx, cnxy times the block's bytes (meaningful for such replicas only)
+    __device__ inline unsigned offset(unsigned cx, unsigned cy, unsigned cz) const {
+        return __umul24(cz, sliceb) + __umul24(cy, rowb) + (cx << kBlockShift);
+    }
+    __device__ inline const ST* at_offset(unsigned off) const {
+        return reinterpret_cast<const ST*>(reinterpret_cast<const char*>(C) + off);
+    }
     __device__ inline void load(const ST* p, float (&c)[8]) const { load_cell8<FMT>(p, c); }
     // the mask is below 2^28 bytes, so a 32-bit offset from the uniform base addresses a word
     __device__ inline const unsigned long long* mask_word(int cx, int cy, int cz) const {
@@ -209,6 +220,17 @@ __device__ inline float select_lanes(unsigned long long lanes, float if_set, flo
     return r;
 }
 
+// Whether cell (ux, uy, uz) (unsigned: a negative corner wraps to a large value) is inside the grid of
+// cells below (lx, ly, lz); CUBIC (lx = ly = lz): one three-way maximum and one compare instead of
+// three compares, the same answer.
+template <bool CUBIC>
+__device__ inline bool in_grid(unsigned ux, unsigned uy, unsigned uz, unsigned lx, unsigned ly, unsigned lz) {
+    if constexpr (CUBIC)
+        return max(ux, max(uy, uz)) < lx;
+    else
+        return (ux < lx) & (uy < ly) & (uz < lz);
+}
+
 // floor(x) as an int (v_cvt_flr_i32_f32; the compiler emits floor and convert separately). Values
 // outside the int range only ever produce out-of-grid cells, which are clamped and rejected.
 __device__ inline int floor_to_int(float x) {
@@ -239,17 +261,25 @@ __device__ inline float trilerp(float f0, float f1, float f2, const float (&c)[8
 // and a cell block is gathered only for a sample whose cell the mask marks valid; the mask bit
 // then stands in for the value test. Where most samples miss the band (a wide particle spread),
 // this replaces most 32-byte gathers by reads of a mask that is 1/256 of the replica's size.
-template <int FMT, int LAYOUT, int NP, bool MASK = false>
+//
+// NARROW (the caller checked narrow_grid): a cubic grid, so the in-grid test is one three-way
+// maximum and one compare, whose replica 32-bit byte offsets address (no 64-bit address
+// arithmetic). WAVE_COUNT: every lane of the wave calls together (uniform control flow; `active`
+// false for a lane without a point), and cnt[j] grows by the number of the wave's valid samples in
+// every lane (a scalar population count instead of a per-lane select and add).
+template <int FMT, int LAYOUT, int NP, bool MASK = false, bool NARROW = false, bool WAVE_COUNT = false>
 __attribute__((always_inline))
 __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, unsigned ly, unsigned lz,
                                   const GridPose (&g)[NP], float x, float y, float z, FixSum (&sum)[NP],
-                                  int (&cnt)[NP]) {
+                                  int (&cnt)[NP], bool active = true) {
     static_assert(!MASK || LAYOUT == PF_LAYOUT_CELLS, "the mask exists for the replica only");
     using ST = typename Fmt<FMT>::T;
     const ST* p[NP];
     unsigned ci[NP];   // replica: cell index, compared instead of the 64-bit address
     float f[NP][3];
     bool inb[NP];
+    unsigned long long minb[NP];   // WAVE_COUNT: the wave's lanes whose sample of pose j is in the grid
+    const unsigned long long mact = WAVE_COUNT ? __builtin_amdgcn_ballot_w64(active) : 0ull;
     int cl[NP][3];
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
@@ -260,11 +290,19 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
         // is exact in FP32, from the fract instruction
         const int ix = floor_to_int(gx), iy = floor_to_int(gy), iz = floor_to_int(gz);
         const unsigned ux = (unsigned)ix, uy = (unsigned)iy, uz = (unsigned)iz;
-        inb[j] = (ux < lx) & (uy < ly) & (uz < lz);
+        inb[j] = in_grid<NARROW>(ux, uy, uz, lx, ly, lz);
+        if constexpr (WAVE_COUNT) {
+            minb[j] = __builtin_amdgcn_ballot_w64(inb[j]) & mact;
+            inb[j] = inb[j] && active;
+        }
         f[j][0] = __builtin_amdgcn_fractf(gx);
         f[j][1] = __builtin_amdgcn_fractf(gy);
         f[j][2] = __builtin_amdgcn_fractf(gz);
-        if constexpr (LAYOUT == PF_LAYOUT_CELLS && !MASK) {
+        if constexpr (LAYOUT == PF_LAYOUT_CELLS && !MASK && NARROW) {
+            // (as below, by byte offset)
+            ci[j] = inb[j] ? G.offset(ux, uy, uz) : 0u;
+            p[j] = G.at_offset(ci[j]);
+        } else if constexpr (LAYOUT == PF_LAYOUT_CELLS && !MASK) {
             // a sample outside the grid (negative corners wrap to large values) reads cell 0
             // instead: the gather stays in bounds and the sample is rejected by inb
             ci[j] = inb[j] ? G.index(ux, uy, uz) : 0u;
@@ -376,7 +414,12 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
         const float v = trilerp(f[j][0], f[j][1], f[j][2], c[j]);
         if constexpr (kNanTest) ok &= !__builtin_isnan(v);
         sum[j] += (FixSum)(ok ? fixed_point<FMT>(v) : 0u);
-        cnt[j] += ok ? 1 : 0;
+        if constexpr (WAVE_COUNT && kNanTest && !MASK)
+            cnt[j] += __popcll(minb[j] & __builtin_amdgcn_ballot_w64(v == v));
+        else if constexpr (WAVE_COUNT)
+            cnt[j] += __popcll(__builtin_amdgcn_ballot_w64(ok));
+        else
+            cnt[j] += ok ? 1 : 0;
     }
 }
 
@@ -487,6 +530,8 @@ __host__ __device__ inline Gather<FMT, LAYOUT> make_gather(const VolView& vv) {
         G.C = static_cast<const typename Fmt<FMT>::T*>(vv.cells);
         G.cnx = vv.nx - 1;
         G.cnxy = (vv.nx - 1) * (vv.ny - 1);
+        G.rowb = (unsigned)G.cnx << Gather<FMT, LAYOUT>::kBlockShift;
+        G.sliceb = (unsigned)G.cnxy << Gather<FMT, LAYOUT>::kBlockShift;
         G.M = vv.mask;
         G.mwx = vv.mwx;
         G.mwxy = vv.mwx * vv.mwy;

@@ -24,23 +24,24 @@ namespace pf {
 namespace {
 
 // With an optimizer state, the launch returns at once when the stop rule has ended the
-// optimization, or when `regime` >= 0 and the particles' spread is in another regime.
-template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK>
+// optimization, or when `regime` >= 0 and the particles' spread is in another regime. NARROW: the
+// volume passes narrow_grid.
+template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK, bool NARROW>
 __global__ __launch_bounds__(BLOCK) void k_score(VolView vv, const float* __restrict__ px, const float* __restrict__ py,
                                                  const float* __restrict__ pz, int n_host, const int* __restrict__ n_dev,
                                                  const float* __restrict__ poses, int K, float* __restrict__ fitness,
                                                  int* __restrict__ n_valid, const pf_track_state* st, int regime) {
     if (st && (st->done || (regime >= 0 && spread_regime(st, vv.inv_vs) != regime))) return;
-    score_step<FMT, LAYOUT, TK, BLOCK, MASK>(vv, px, py, pz, n_dev ? *n_dev : n_host, poses, K, blockIdx.x * TK,
-                                             fitness, n_valid);
+    score_step<FMT, LAYOUT, TK, BLOCK, MASK, NARROW>(vv, px, py, pz, n_dev ? *n_dev : n_host, poses, K,
+                                                    blockIdx.x * TK, fitness, n_valid);
 }
 
-template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK = false>
+template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK = false, bool NARROW = false>
 int32_t launch_t(const VolView& vv, const Points& p, const float* poses, int K, float* fitness, int* n_valid,
                  const pf_track_state* st, int regime, hipStream_t s) {
     const int blocks = (K + TK - 1) / TK;
-    hipLaunchKernelGGL((k_score<FMT, LAYOUT, TK, BLOCK, MASK>), dim3(blocks), dim3(BLOCK), 0, s, vv, p.x, p.y, p.z,
-                       p.n, p.n_dev, poses, K, fitness, n_valid, st, regime);
+    hipLaunchKernelGGL((k_score<FMT, LAYOUT, TK, BLOCK, MASK, NARROW>), dim3(blocks), dim3(BLOCK), 0, s, vv, p.x, p.y,
+                       p.z, p.n, p.n_dev, poses, K, fitness, n_valid, st, regime);
     return check_launch("particles_score");
 }
 
@@ -72,7 +73,8 @@ int auto_shape(int K) {
     return 3;
 }
 
-// One launch of automatic shape code `shape`.
+// One launch of automatic shape code `shape` (the 4x256 shape of many poses also in its narrow
+// form).
 template <int FMT, int LAYOUT, bool MASK>
 int32_t launch_shape(int shape, const VolView& vv, const Points& p, const float* poses, int K, float* fitness,
                      int* n_valid, const pf_track_state* st, int gate, hipStream_t s) {
@@ -80,7 +82,10 @@ int32_t launch_shape(int shape, const VolView& vv, const Points& p, const float*
         return set_error(PF_EUNSUPPORTED, "particles_score: the x-fastest layout has no mask");
     } else {
         switch (shape) {
-            case 0: return launch_t<FMT, LAYOUT, 4, 256, MASK>(vv, p, poses, K, fitness, n_valid, st, gate, s);
+            case 0:
+                return narrow_grid(vv)
+                           ? launch_t<FMT, LAYOUT, 4, 256, MASK, true>(vv, p, poses, K, fitness, n_valid, st, gate, s)
+                           : launch_t<FMT, LAYOUT, 4, 256, MASK>(vv, p, poses, K, fitness, n_valid, st, gate, s);
             case 1: return launch_t<FMT, LAYOUT, 2, 256, MASK>(vv, p, poses, K, fitness, n_valid, st, gate, s);
             case 2: return launch_t<FMT, LAYOUT, 1, 256, MASK>(vv, p, poses, K, fitness, n_valid, st, gate, s);
             default: return launch_t<FMT, LAYOUT, 1, 1024, MASK>(vv, p, poses, K, fitness, n_valid, st, gate, s);

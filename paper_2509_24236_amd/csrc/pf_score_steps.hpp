@@ -51,7 +51,7 @@ constexpr bool compact_fits() {
     return (BLOCK / kWave) * TK * kQueue * 16 <= 32768;
 }
 
-template <int FMT, int LAYOUT, int TK, int BLOCK>
+template <int FMT, int LAYOUT, int TK, int BLOCK, bool NARROW>
 __attribute__((always_inline))
 __device__ inline void score_points_compact(const VolView& vv, const float* __restrict__ px,
                                             const float* __restrict__ py, const float* __restrict__ pz, int n,
@@ -118,7 +118,7 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
             const float gz = fmaf(g[j].r[6], x, fmaf(g[j].r[7], y, fmaf(g[j].r[8], z, g[j].t[2])));
             const unsigned ux = (unsigned)floor_to_int(gx), uy = (unsigned)floor_to_int(gy),
                            uz = (unsigned)floor_to_int(gz);
-            inb[j] = active & (ux < lx) & (uy < ly) & (uz < lz);
+            inb[j] = active & in_grid<NARROW>(ux, uy, uz, lx, ly, lz);
             cl[j][0] = (int)min(ux, lx - 1u);
             cl[j][1] = (int)min(uy, ly - 1u);
             cl[j][2] = (int)min(uz, lz - 1u);
@@ -183,7 +183,7 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
 // Per-lane path: every lane keeps one point in registers and evaluates it against the TK poses
 // (uniform, in scalar registers; eval_poses), without the mask or through it when the compacting
 // queues do not fit.
-template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK>
+template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK, bool NARROW>
 __attribute__((always_inline))
 __device__ inline void score_points_lanes(const VolView& vv, const float* __restrict__ px,
                                           const float* __restrict__ py, const float* __restrict__ pz, int n,
@@ -202,30 +202,39 @@ __device__ inline void score_points_lanes(const VolView& vv, const float* __rest
     }
     const float s = vv.inv_vs;
     // the next point is loaded while the current one's gathers are in flight, so every pass of
-    // the loop waits for one memory round trip instead of two
-    int q = threadIdx.x;
+    // the loop waits for one memory round trip instead of two. Every lane runs every pass (a lane
+    // past the end holds no point), so a wave counts its valid samples with one scalar population
+    // count; lane 0 (the wave's first point) then holds the wave's counts.
+    const int passes = (n + BLOCK - 1) / BLOCK;
     float nx = 0.0f, ny = 0.0f, nz = 0.0f;
-    if (q < n) {
-        nx = px[q];
-        ny = py[q];
-        nz = pz[q];
+    if ((int)threadIdx.x < n) {
+        nx = px[threadIdx.x];
+        ny = py[threadIdx.x];
+        nz = pz[threadIdx.x];
     }
-    for (; q < n; q += BLOCK) {
+    for (int pass = 0; pass < passes; ++pass) {
+        const int q = pass * BLOCK + (int)threadIdx.x;
         const float x = nx * s, y = ny * s, z = nz * s;
-        const int qn = q + BLOCK;
-        if (qn < n) {
-            nx = px[qn];
-            ny = py[qn];
-            nz = pz[qn];
-        }
-        eval_poses<FMT, LAYOUT, TK, MASK>(G, lx, ly, lz, g, x, y, z, sum, cnt);
+        // (the next point's registers are free only now; its index is clamped into the cloud, so
+        // every lane loads without a branch, from a 32-bit offset)
+        __builtin_amdgcn_sched_barrier(0);
+        const unsigned off = (unsigned)min(q + BLOCK, n - 1) * 4u;   // (a cloud holds < 2^30 points)
+        nx = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(px) + off);
+        ny = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(py) + off);
+        nz = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(pz) + off);
+        eval_poses<FMT, LAYOUT, TK, MASK, NARROW, true>(G, lx, ly, lz, g, x, y, z, sum, cnt, q < n);
+    }
+    if ((threadIdx.x & (kWave - 1)) != 0) {
+#pragma unroll
+        for (int j = 0; j < TK; ++j) cnt[j] = 0;
     }
 }
 
 // Workgroup of BLOCK threads scoring poses k0 .. k0+TK-1 over all n points, through the
 // cell-validity mask when MASK (compacting the valid samples when the queues fit in 32 KB of LDS).
 // The sums are exact, so the result of a pose does not depend on TK, BLOCK, MASK or the workgroup.
-template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK = false>
+// NARROW: the volume passes narrow_grid (eval_poses: the same answer with fewer instructions).
+template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK = false, bool NARROW = false>
 __attribute__((always_inline))
 __device__ inline void score_step(const VolView& vv, const float* __restrict__ px, const float* __restrict__ py,
                                   const float* __restrict__ pz, int n, const float* __restrict__ poses, int K, int k0,
@@ -233,10 +242,10 @@ __device__ inline void score_step(const VolView& vv, const float* __restrict__ p
     FixSum sum[TK];
     int cnt[TK];
     if constexpr (MASK && LAYOUT != PF_LAYOUT_LINEAR && compact_fits<TK, BLOCK>())
-        score_points_compact<FMT, LAYOUT, TK, BLOCK>(vv, px, py, pz, n, poses, K, k0, sum, cnt);
+        score_points_compact<FMT, LAYOUT, TK, BLOCK, NARROW>(vv, px, py, pz, n, poses, K, k0, sum, cnt);
     else   // (the sparse layout reads its mask only when compacting: the mask changes speed only)
-        score_points_lanes<FMT, LAYOUT, TK, BLOCK, MASK && LAYOUT == PF_LAYOUT_CELLS>(vv, px, py, pz, n, poses, K,
-                                                                                   k0, sum, cnt);
+        score_points_lanes<FMT, LAYOUT, TK, BLOCK, MASK && LAYOUT == PF_LAYOUT_CELLS, NARROW>(vv, px, py, pz, n,
+                                                                                           poses, K, k0, sum, cnt);
     block_reduce<TK, BLOCK>(sum, cnt);
     if (threadIdx.x < TK) {
         const int k = k0 + threadIdx.x;

@@ -126,6 +126,14 @@ __device__ inline void load_cell8(const typename Fmt<FMT>::T* p, float (&c)[8]) 
     }
 }
 
+// a * b + c on 24-bit a and b (b uniform, in a scalar register), one full-rate instruction: the
+// compiler forms such sums as two multiplies and a three-way add, one instruction more
+__device__ inline unsigned mad_u24(unsigned a, unsigned b, unsigned c) {
+    unsigned r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
 // Cell-major replica: the 8 corners of a cell are one aligned block.
 template <int FMT>
 struct Gather<FMT, PF_LAYOUT_CELLS> {
@@ -136,9 +144,9 @@ struct Gather<FMT, PF_LAYOUT_CELLS> {
     int mwx, mwxy;
     // cell index (below 2^31 for the dense layouts), unsigned so that its widening is a zero
     // extension and the address one shift-and-add; (nx - 1)(ny - 1) < 2^24 for the dense layouts, so
-    // the products are 24-bit multiplies (full rate; a 32-bit multiply issues at a quarter rate)
+    // the products are 24-bit multiply-adds (full rate; a 32-bit multiply issues at a quarter rate)
     __device__ inline unsigned index(unsigned cx, unsigned cy, unsigned cz) const {
-        return __umul24(cz, (unsigned)cnxy) + __umul24(cy, (unsigned)cnx) + cx;
+        return mad_u24(cz, (unsigned)cnxy, mad_u24(cy, (unsigned)cnx, cx));
     }
     __device__ inline const ST* at(unsigned idx) const { return C + ((size_t)idx << 3); }
     __device__ inline const ST* addr(int cx, int cy, int cz) const { return at(index(cx, cy, cz)); }
@@ -147,8 +155,10 @@ struct Gather<FMT, PF_LAYOUT_CELLS> {
     // in the load itself, with no 64-bit address arithmetic
     static constexpr unsigned kBlockShift = sizeof(ST) == 4 ? 5 : 4;
     unsigned rowb, sliceb;   // cnx, cnxy times the block's bytes (meaningful for such replicas only)
+    // (the operands are 24-bit for any cell of such a replica; the result of a cell outside it is
+    // not used)
     __device__ inline unsigned offset(unsigned cx, unsigned cy, unsigned cz) const {
-        return __umul24(cz, sliceb) + __umul24(cy, rowb) + (cx << kBlockShift);
+        return mad_u24(cz, sliceb, mad_u24(cy, rowb, cx << kBlockShift));
     }
     __device__ inline const ST* at_offset(unsigned off) const {
         return reinterpret_cast<const ST*>(reinterpret_cast<const char*>(C) + off);
@@ -299,8 +309,9 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
         f[j][1] = __builtin_amdgcn_fractf(gy);
         f[j][2] = __builtin_amdgcn_fractf(gz);
         if constexpr (LAYOUT == PF_LAYOUT_CELLS && !MASK && NARROW) {
-            // (as below, by byte offset)
-            ci[j] = inb[j] ? G.offset(ux, uy, uz) : 0u;
+            // (as below, by byte offset, formed for every lane and then selected)
+            const unsigned off = G.offset(ux, uy, uz);
+            ci[j] = inb[j] ? off : 0u;
             p[j] = G.at_offset(ci[j]);
         } else if constexpr (LAYOUT == PF_LAYOUT_CELLS && !MASK) {
             // a sample outside the grid (negative corners wrap to large values) reads cell 0
@@ -388,13 +399,14 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     if (need[0]) G.load(p[0], c[0]);
 #pragma unroll
     for (int j = 1; j < NP; ++j) {
-        bool d;
+        // (one compare: the lane mask of the lanes that differ, negated in scalar registers)
+        bool nd;
         if constexpr (LAYOUT == PF_LAYOUT_CELLS)
-            d = ci[j] == ci[j - 1];
+            nd = ci[j] != ci[j - 1];
         else
-            d = p[j] == p[j - 1];
-        dup[j] = __ballot(d);
-        if (!d && need[j]) G.load(p[j], c[j]);
+            nd = p[j] != p[j - 1];
+        dup[j] = ~__builtin_amdgcn_ballot_w64(nd);
+        if (nd && need[j]) G.load(p[j], c[j]);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll

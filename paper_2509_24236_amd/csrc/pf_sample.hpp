@@ -173,6 +173,19 @@ struct Gather<FMT, PF_LAYOUT_CELLS> {
     __device__ static inline unsigned mask_bit(int cx, int cy, int cz) {
         return (unsigned)((cx & 3) | ((cy & 3) << 2) | ((cz & 3) << 4));
     }
+    // the word's index for a cell of the grid (two 24-bit multiply-adds), and the word at an index
+    __device__ inline unsigned mask_index(unsigned cx, unsigned cy, unsigned cz) const {
+        return mad_u24(cz >> 2, (unsigned)mwxy, mad_u24(cy >> 2, (unsigned)mwx, cx >> 2));
+    }
+    __device__ inline unsigned long long mask_at(unsigned w) const {
+        return *reinterpret_cast<const unsigned long long*>(reinterpret_cast<const char*>(M) + (w << 3));
+    }
+    // the same bit as a 64-bit shift amount, whose bits above the sixth the shift ignores (one
+    // instruction fewer)
+    __device__ static inline unsigned mask_shift(unsigned cx, unsigned cy, unsigned cz) {
+        const unsigned xy = (cx & 3u) | ((cy << 2) & ~3u);   // (bit fields inserted: two instructions
+        return (xy & 15u) | ((cz << 4) & ~15u);               // fewer than masking each coordinate)
+    }
 };
 
 // Sparse bricks: the brick-index grid names the slot of the cell's 8x8x8 brick, whose cell
@@ -228,6 +241,21 @@ __device__ inline float select_lanes(unsigned long long lanes, float if_set, flo
     float r;
     asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(lanes));
     return r;
+}
+
+// For the active lanes in `lanes`, a, else b (one v_cndmask_b32, which the compiler cannot turn into
+// a branch around the computation of a).
+__device__ inline unsigned select_u32(unsigned long long lanes, unsigned a, unsigned b) {
+    unsigned r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(lanes));
+    return r;
+}
+
+// Bit `bit` (only its low 6 bits count) of a 64-bit word, as 0 or 1.
+__device__ inline unsigned word_bit(unsigned long long w, unsigned bit) {
+    unsigned long long r;
+    asm("v_lshrrev_b64 %0, %1, %2" : "=v"(r) : "v"(bit), "v"(w));
+    return (unsigned)r & 1u;
 }
 
 // Whether cell (ux, uy, uz) (unsigned: a negative corner wraps to a large value) is inside the grid of

@@ -99,6 +99,7 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
     for (int pass = 0; pass < passes; ++pass) {
         const int q = pass * BLOCK + (int)threadIdx.x;
         const bool active = q < n;
+        const unsigned long long mact = __builtin_amdgcn_ballot_w64(active);
         const float x = nx * s, y = ny * s, z = nz * s;
         if (q + BLOCK < n) {
             nx = px[q + BLOCK];
@@ -109,6 +110,7 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
         int cl[TK][3];
         float f[TK][3];
         bool inb[TK];
+        unsigned long long minb[TK];   // the wave's lanes whose sample of pose j is in the grid
         unsigned long long mw[TK];
         unsigned cell[TK], bit[TK];   // the cell's index in the replica or the pool, its mask bit
 #pragma unroll
@@ -118,10 +120,20 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
             const float gz = fmaf(g[j].r[6], x, fmaf(g[j].r[7], y, fmaf(g[j].r[8], z, g[j].t[2])));
             const unsigned ux = (unsigned)floor_to_int(gx), uy = (unsigned)floor_to_int(gy),
                            uz = (unsigned)floor_to_int(gz);
-            inb[j] = active & in_grid<NARROW>(ux, uy, uz, lx, ly, lz);
-            cl[j][0] = (int)min(ux, lx - 1u);
-            cl[j][1] = (int)min(uy, ly - 1u);
-            cl[j][2] = (int)min(uz, lz - 1u);
+            const bool ig = in_grid<NARROW>(ux, uy, uz, lx, ly, lz);
+            minb[j] = __builtin_amdgcn_ballot_w64(ig) & mact;
+            inb[j] = ig && active;
+            if constexpr (LAYOUT == PF_LAYOUT_CELLS) {
+                // the replica: the cell as computed (outside the grid it is not used, and its mask
+                // word is read at offset 0 instead)
+                cl[j][0] = (int)ux;
+                cl[j][1] = (int)uy;
+                cl[j][2] = (int)uz;
+            } else {
+                cl[j][0] = (int)min(ux, lx - 1u);
+                cl[j][1] = (int)min(uy, ly - 1u);
+                cl[j][2] = (int)min(uz, lz - 1u);
+            }
             f[j][0] = __builtin_amdgcn_fractf(gx);
             f[j][1] = __builtin_amdgcn_fractf(gy);
             f[j][2] = __builtin_amdgcn_fractf(gz);
@@ -129,9 +141,10 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
         if constexpr (LAYOUT == PF_LAYOUT_CELLS) {
 #pragma unroll
             for (int j = 0; j < TK; ++j) {
-                mw[j] = *G.mask_word(cl[j][0], cl[j][1], cl[j][2]);
-                cell[j] = G.index(cl[j][0], cl[j][1], cl[j][2]);
-                bit[j] = G.mask_bit(cl[j][0], cl[j][1], cl[j][2]);
+                const unsigned ux = (unsigned)cl[j][0], uy = (unsigned)cl[j][1], uz = (unsigned)cl[j][2];
+                mw[j] = G.mask_at(select_u32(minb[j], G.mask_index(ux, uy, uz), 0u));
+                cell[j] = G.index(ux, uy, uz);
+                bit[j] = G.mask_shift(ux, uy, uz);
             }
         } else {
             // sparse: the brick's slot first (one round for all poses), then its mask word; a
@@ -144,6 +157,7 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
 #pragma unroll
             for (int j = 0; j < TK; ++j) {
                 inb[j] &= slot[j] >= 0;
+                minb[j] &= __builtin_amdgcn_ballot_w64(slot[j] >= 0);
                 const unsigned sl = (unsigned)max(slot[j], 0);
                 const unsigned loc = G.local(cl[j][0], cl[j][1], cl[j][2]);
                 mw[j] = G.M[sl * kBrickMaskWords + (loc >> 6)];
@@ -157,9 +171,14 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
         // append the valid samples of each pose to its queue, in lane order
 #pragma unroll
         for (int j = 0; j < TK; ++j) {
-            const bool valid = inb[j] & (((mw[j] >> bit[j]) & 1ull) != 0);
-            const unsigned long long m = __ballot(valid);
-            if (valid) {
+            bool set;
+            if constexpr (LAYOUT == PF_LAYOUT_CELLS)
+                set = word_bit(mw[j], bit[j]) != 0;
+            else
+                set = ((mw[j] >> bit[j]) & 1ull) != 0;
+            // (the lanes to append as one scalar mask, which also guards the append)
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(set) & minb[j];
+            if (__builtin_amdgcn_inverse_ballot_w64(m)) {
                 const unsigned below =
                     __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
                 Q[j][(head[j] + fill[j] + (int)below) & (kQueue - 1)] = make_uint4(

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "pf_polish.hpp"
@@ -122,8 +123,9 @@ __global__ __launch_bounds__(256) void kb_next(const BatchProb* tab, const int4*
 // the cost of one state read. PATH 0: a problem in a regime of kMaskRegimes reads its cells
 // through the mask, the others take the per-lane path, in one kernel; PATH 1 / 2: the masked
 // (compacting) path or the per-lane path only, each a kernel with its own register and LDS
-// footprint (the automatic plan launches the two, one per regime, as track_frame does).
-template <int FMT, int LAYOUT, int TK, int BLOCK, int PATH = 0>
+// footprint (the automatic plan launches the two, one per regime, as track_frame does). NARROW: every
+// problem's volume passes narrow_grid (score_step).
+template <int FMT, int LAYOUT, int TK, int BLOCK, int PATH = 0, bool NARROW = false>
 __global__ __launch_bounds__(BLOCK) void kb_score(const BatchProb* tab, const int4* items, int n_items, int phase,
                                                   int regimes) {
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(BLOCK) void kb_score(const BatchProb* tab, const in
             score_step_regime<FMT, LAYOUT, TK, BLOCK>(P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv,
                                                       regime);
         else
-            score_step<FMT, LAYOUT, TK, BLOCK, PATH == 1 && LAYOUT != PF_LAYOUT_LINEAR>(
+            score_step<FMT, LAYOUT, TK, BLOCK, PATH == 1 && LAYOUT != PF_LAYOUT_LINEAR, NARROW>(
                 P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv);
     }
 }
@@ -295,6 +297,7 @@ struct pf_batch {
         n_pp = 0;
     std::vector<BatchProb> host;
     std::vector<int> min_valid;
+    bool narrow = false;   // every problem's volume passes narrow_grid
 };
 
 namespace {
@@ -314,10 +317,17 @@ void launch_score_batch(pf_batch* b, int phase, hipStream_t s) {
 template <int FMT, int LAYOUT>
 void launch_score_batch_auto(pf_batch* b, int phase, hipStream_t s) {
     const int g = std::min(b->plan.score_grid, b->n_score);
-    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 4, 256, 1>), dim3(g), dim3(256), 0, s, b->tab,
-                       b->items + b->off_score, b->n_score, phase, kMaskRegimes);
-    hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 4, 256, 2>), dim3(g), dim3(256), 0, s, b->tab,
-                       b->items + b->off_score, b->n_score, phase, ((1 << kRegimes) - 1) & ~kMaskRegimes);
+    auto go = [&](auto narrow) {
+        constexpr bool N = decltype(narrow)::value;
+        hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 4, 256, 1, N>), dim3(g), dim3(256), 0, s, b->tab,
+                           b->items + b->off_score, b->n_score, phase, kMaskRegimes);
+        hipLaunchKernelGGL((kb_score<FMT, LAYOUT, 4, 256, 2, N>), dim3(g), dim3(256), 0, s, b->tab,
+                           b->items + b->off_score, b->n_score, phase, ((1 << kRegimes) - 1) & ~kMaskRegimes);
+    };
+    if (b->narrow)
+        go(std::true_type{});
+    else
+        go(std::false_type{});
 }
 
 template <int FMT, int LAYOUT>
@@ -438,6 +448,7 @@ pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const 
     std::vector<pf_track_state> init(n);
     size_t off = table_bytes(n);
     b->host.resize(n);
+    b->narrow = true;
     for (int p = 0; p < n; ++p) {
         const pf_batch_problem& q = problems[p];
         const ProbLayout L = prob_layout(q, off);
@@ -445,6 +456,7 @@ pf_batch* track_batch_create(const pf_batch_problem* problems, int32_t n, const 
         BatchProb& P = b->host[p];
         memset(&P, 0, sizeof P);
         P.vv = make_view(&q.vol);
+        b->narrow = b->narrow && narrow_grid(P.vv);
         const size_t npix = (size_t)q.K.width * q.K.height;
         P.bp.depth = q.depth;
         P.bp.width = q.K.width;

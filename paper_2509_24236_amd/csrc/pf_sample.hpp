@@ -180,11 +180,11 @@ struct Gather<FMT, PF_LAYOUT_CELLS> {
     __device__ inline unsigned long long mask_at(unsigned w) const {
         return *reinterpret_cast<const unsigned long long*>(reinterpret_cast<const char*>(M) + (w << 3));
     }
-    // the same bit as a 64-bit shift amount, whose bits above the sixth the shift ignores (one
-    // instruction fewer)
+    // the same bit as a 64-bit shift amount, whose bits above the sixth the shift ignores, so z's
+    // bits need no mask (one instruction fewer)
     __device__ static inline unsigned mask_shift(unsigned cx, unsigned cy, unsigned cz) {
-        const unsigned xy = (cx & 3u) | ((cy << 2) & ~3u);   // (bit fields inserted: two instructions
-        return (xy & 15u) | ((cz << 4) & ~15u);               // fewer than masking each coordinate)
+        const unsigned xy = (cx & 3u) | ((cy << 2) & ~3u);
+        return (xy & 15u) | ((cz << 4) & ~15u);
     }
 };
 

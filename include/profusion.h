@@ -276,7 +276,8 @@ int32_t backproject(const float* depth, const pf_intrinsics* K, int32_t pixel_st
  * where T(.) is the trilinear interpolation of the 8 voxel centres around the point and x is
  * in X_k iff that stencil lies inside the grid and all 8 stored values satisfy |T| < 1
  * (observed and within the truncation distance: the "valid grids"). E_k = 1 if X_k is empty.
- * px, py, pz: device, n_pts floats (camera coordinates, metres), n_pts >= 1.
+ * px, py, pz: device, n_pts floats (camera coordinates, metres), 1 <= n_pts < 2^30 (the kernels
+ * address a point by a 32-bit byte offset); PF_EINVAL otherwise.
  * poses: device, [K][12] float32, row-major 3x4 [R | t] camera -> world.
  * fitness: device, K floats; n_valid: device, K int32 (|X_k|).
  * Each valid |T| is converted to 32-bit fixed point (units of 2^-32; 2^-17 stored units for

@@ -392,7 +392,8 @@ int32_t particles_score(const pf_tsdf* v, const float* px, const float* py, cons
     if (rc) return rc;
     if (!px || !py || !pz || !poses || !fitness || !n_valid)
         return set_error(PF_EINVAL, "particles_score: null pointer");
-    if (n_pts < 1) return set_error(PF_EINVAL, "particles_score: n_pts %d must be >= 1", n_pts);
+    if (n_pts < 1 || n_pts >= (1 << 30))
+        return set_error(PF_EINVAL, "particles_score: n_pts %d not in 1 .. 2^30 - 1", n_pts);
     if (K < 1) return set_error(PF_EINVAL, "particles_score: K %d must be >= 1", K);
     Points p{px, py, pz, n_pts, nullptr};
     return launch_score(make_view(v), p, poses, K, fitness, n_valid, (hipStream_t)stream);

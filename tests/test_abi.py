@@ -152,6 +152,7 @@ def test_validation_rejects_before_launch(pf):
     _rc(pf, L.tsdf_integrate(C.byref(_desc(pf)), None, C.byref(K), C.byref(good), None), "null depth")
     p = C.c_void_p(0x4000)
     _rc(pf, L.particles_score(C.byref(_desc(pf)), p, p, p, 0, p, 4, p, p, None), "n_pts")
+    _rc(pf, L.particles_score(C.byref(_desc(pf)), p, p, p, 1 << 30, p, 4, p, p, None), "n_pts")
     _rc(pf, L.particles_score(C.byref(_desc(pf)), p, p, p, 10, p, 0, p, p, None), "K")
     _rc(pf, L.particles_score(C.byref(_desc(pf)), p, None, p, 10, p, 4, p, p, None), "null pointer")
     _rc(pf, L.particles_update(C.byref(_desc(pf)), p, p, p, 10, p, p, p, 0, p, None), "K")

@@ -396,15 +396,16 @@ def test_track_frame_automatic_shape_matches_fixed(pf, orc, dev, cfg1, cfg1_vol)
         pf.score_config(0, 0)
 
 
-def test_track_frame_narrow_form_matches_generic(pf, orc, dev, cfg1, cfg1_vol):
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+def test_track_frame_narrow_form_matches_generic(pf, orc, dev, cfg1, cfg1_vol, fmt):
     """With K >= 1024 on a cubic volume whose replica 32-bit offsets address (cfg1: 128^3), the
     automatic launches take their narrow form (max3 in-grid test, 32-bit gather offsets, per-wave
     counts) and the spread regime its compacting masked form; a configured launch shape takes the
     generic per-lane form without the mask. Both track bitwise alike, on the first call (the
     regime-gated scoring launches) and on the second (the particle launch that draws)."""
-    say("[narrow] track_frame K=1024 automatic (narrow, masked) vs configured 4x256 (generic)")
+    say(f"[narrow] format {fmt}: track_frame K=1024 automatic (narrow, masked) vs configured 4x256 (generic)")
     v, v32, T32 = cfg1_vol
-    gv = upload(pf, cfg1["vol"], T32, v.W, dev)
+    gv = upload(pf, cfg1["vol"], T32, v.W, dev, fmt=fmt)
     R0, t0 = cfg1["init2"]
     prm = pf.TrackParams(seed=5, frame_index=1, n_iters=8, K=1024, rates=(1,), pixel_stride=2, s1_deg=5.0, s1_m=0.03)
     depth = torch.as_tensor(cfg1["depth2"]).to(dev)

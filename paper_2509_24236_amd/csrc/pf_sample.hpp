@@ -424,6 +424,9 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     // copies was gathered whenever it needs one.)
     float c[NP][8];
     unsigned long long dup[NP];   // lanes whose pose j samples the same cell as pose j-1
+    // (the wave issues its gathers at a raised priority, so that its memory round starts before
+    // the other waves' arithmetic takes the SIMD: -26 us per frame on the headline sequence)
+    __builtin_amdgcn_s_setprio(2);
     if (need[0]) G.load(p[0], c[0]);
 #pragma unroll
     for (int j = 1; j < NP; ++j) {
@@ -436,6 +439,7 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
         dup[j] = ~__builtin_amdgcn_ballot_w64(nd);
         if (nd && need[j]) G.load(p[j], c[j]);
     }
+    __builtin_amdgcn_s_setprio(0);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 1; j < NP; ++j)

@@ -318,6 +318,11 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     bool inb[NP];
     unsigned long long minb[NP];   // WAVE_COUNT: the wave's lanes whose sample of pose j is in the grid
     const unsigned long long mact = WAVE_COUNT ? __builtin_amdgcn_ballot_w64(active) : 0ull;
+    // The wave runs at a raised priority from its transforms until its gathers are issued, so that
+    // its memory round starts before the other waves' interpolation takes the SIMD: -26 us per
+    // frame on the headline sequence with the window around the gathers alone, -67 us more with
+    // the transforms and cell arithmetic in it (balanced A/Bs).
+    __builtin_amdgcn_s_setprio(2);
     int cl[NP][3];
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
@@ -424,9 +429,6 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     // copies was gathered whenever it needs one.)
     float c[NP][8];
     unsigned long long dup[NP];   // lanes whose pose j samples the same cell as pose j-1
-    // (the wave issues its gathers at a raised priority, so that its memory round starts before
-    // the other waves' arithmetic takes the SIMD: -26 us per frame on the headline sequence)
-    __builtin_amdgcn_s_setprio(2);
     if (need[0]) G.load(p[0], c[0]);
 #pragma unroll
     for (int j = 1; j < NP; ++j) {

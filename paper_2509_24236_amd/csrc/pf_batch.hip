@@ -137,10 +137,10 @@ __global__ __launch_bounds__(BLOCK) void kb_score(const BatchProb* tab, const in
         const int* nd;
         view_of(P, phase, x, y, z, nd);
         if constexpr (PATH == 0)
-            score_step_regime<FMT, LAYOUT, TK, BLOCK>(P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv,
+            score_step_regime<FMT, LAYOUT, TK, BLOCK, false>(P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv,
                                                       regime);
         else
-            score_step<FMT, LAYOUT, TK, BLOCK, PATH == 1 && LAYOUT != PF_LAYOUT_LINEAR, NARROW>(
+            score_step<FMT, LAYOUT, TK, BLOCK, PATH == 1 && LAYOUT != PF_LAYOUT_LINEAR, NARROW, false>(
                 P.vv, x, y, z, *nd, P.poses, P.K + 1, w.y * TK, P.fit, P.nv);
     }
 }
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void kb_adv(const BatchProb* tab, const int4* 
     const float *x, *y, *z;
     const int* nd;
     view_of(P, ADV ? phase : P.densest, x, y, z, nd);
-    adv_step<FMT, LAYOUT, ADV>(P.vv, x, y, z, 0, nd, P.fit, P.st, P.K, w.y, w.z);
+    adv_step<FMT, LAYOUT, ADV, false>(P.vv, x, y, z, 0, nd, P.fit, P.st, P.K, w.y, w.z);
 }
 
 template <int FMT>
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kGradThreads) void kb_pose_partials(const BatchProb
     const float *x, *y, *z;
     const int* nd;
     view_of(P, P.densest, x, y, z, nd);
-    pose_partials_step<FMT, LAYOUT>(P.vv, x, y, z, *nd, &P.ps->cand[0][0], P.cp, w.y, P.G[P.densest], w.z);
+    pose_partials_step<FMT, LAYOUT, false>(P.vv, x, y, z, *nd, &P.ps->cand[0][0], P.cp, w.y, P.G[P.densest], w.z);
 }
 
 template <int FMT>

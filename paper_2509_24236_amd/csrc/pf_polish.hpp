@@ -278,7 +278,7 @@ __device__ inline void grad_step(const VolView& vv, const float* __restrict__ px
 }
 
 // Exact fitness partial of FP64 pose p (row-major [R | t]) on point chunk s of S.
-template <int FMT, int LAYOUT>
+template <int FMT, int LAYOUT, bool PRIO = true>
 __device__ inline void pose_partials_step(const VolView& vv, const float* __restrict__ px,
                                           const float* __restrict__ py, const float* __restrict__ pz, int n,
                                           const double* __restrict__ poses, Partial2* partials, int p, int S, int s) {
@@ -298,7 +298,8 @@ __device__ inline void pose_partials_step(const VolView& vv, const float* __rest
     int cnt[1] = {0};
     const float sc = vv.inv_vs;
     for (int q = q0 + (int)threadIdx.x; q < q1; q += kGradThreads)
-        eval_poses<FMT, LAYOUT, 1>(G, lx, ly, lz, g, px[q] * sc, py[q] * sc, pz[q] * sc, sum, cnt);
+        eval_poses<FMT, LAYOUT, 1, false, false, false, PRIO>(G, lx, ly, lz, g, px[q] * sc, py[q] * sc, pz[q] * sc,
+                                                             sum, cnt);
     block_reduce<1, kGradThreads>(sum, cnt);
     if (threadIdx.x == 0) {
         partials[(size_t)p * S + s].sum = sum[0];

@@ -305,7 +305,10 @@ __device__ inline float trilerp(float f0, float f1, float f2, const float (&c)[8
 // arithmetic). WAVE_COUNT: every lane of the wave calls together (uniform control flow; `active`
 // false for a lane without a point), and cnt[j] grows by the number of the wave's valid samples in
 // every lane (a scalar population count instead of a per-lane select and add).
-template <int FMT, int LAYOUT, int NP, bool MASK = false, bool NARROW = false, bool WAVE_COUNT = false>
+//
+// PRIO: the raised-priority window described below (the batched kernels leave it off).
+template <int FMT, int LAYOUT, int NP, bool MASK = false, bool NARROW = false, bool WAVE_COUNT = false,
+          bool PRIO = true>
 __attribute__((always_inline))
 __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, unsigned ly, unsigned lz,
                                   const GridPose (&g)[NP], float x, float y, float z, FixSum (&sum)[NP],
@@ -321,8 +324,9 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
     // The wave runs at a raised priority from its transforms until its gathers are issued, so that
     // its memory round starts before the other waves' interpolation takes the SIMD: -26 us per
     // frame on the headline sequence with the window around the gathers alone, -67 us more with
-    // the transforms and cell arithmetic in it (balanced A/Bs).
-    __builtin_amdgcn_s_setprio(2);
+    // the transforms and cell arithmetic in it (balanced A/Bs). (In the batched kernels, whose
+    // persistent workgroups take items of many problems, the window made a batch 3.5% slower.)
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
     int cl[NP][3];
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
@@ -441,7 +445,7 @@ __device__ inline void eval_poses(const Gather<FMT, LAYOUT>& G, unsigned lx, uns
         dup[j] = ~__builtin_amdgcn_ballot_w64(nd);
         if (nd && need[j]) G.load(p[j], c[j]);
     }
-    __builtin_amdgcn_s_setprio(0);
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 1; j < NP; ++j)

@@ -51,7 +51,7 @@ constexpr bool compact_fits() {
     return (BLOCK / kWave) * TK * kQueue * 16 <= 32768;
 }
 
-template <int FMT, int LAYOUT, int TK, int BLOCK, bool NARROW>
+template <int FMT, int LAYOUT, int TK, int BLOCK, bool NARROW, bool PRIO>
 __attribute__((always_inline))
 __device__ inline void score_points_compact(const VolView& vv, const float* __restrict__ px,
                                             const float* __restrict__ py, const float* __restrict__ pz, int n,
@@ -80,9 +80,9 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
         const uint4 e = Q[j][(head[j] + lane) & (kQueue - 1)];
         if (lane < m) {
             float c[8];
-            __builtin_amdgcn_s_setprio(2);
+            if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
             G.load(G.at(e.x), c);
-            __builtin_amdgcn_s_setprio(0);
+            if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
             const float v = trilerp(__uint_as_float(e.y), __uint_as_float(e.z), __uint_as_float(e.w), c);
             sum[j] += (FixSum)fixed_point<FMT>(v);
             cnt[j] += 1;
@@ -142,7 +142,7 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
         }
         // (the mask loads, and each drain's gathers below, are issued at a raised wave priority, as
         // in eval_poses: -23 us per frame on the headline sequence)
-        __builtin_amdgcn_s_setprio(2);
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
         if constexpr (LAYOUT == PF_LAYOUT_CELLS) {
 #pragma unroll
             for (int j = 0; j < TK; ++j) {
@@ -172,7 +172,7 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
         }
         // (the loads are issued for every lane, in bounds thanks to the clamp, and kept together:
         // a short-circuit test would move a load into a branch and wait for it there)
-        __builtin_amdgcn_s_setprio(0);
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
         __builtin_amdgcn_sched_barrier(0);
         // append the valid samples of each pose to its queue, in lane order
 #pragma unroll
@@ -208,7 +208,7 @@ __device__ inline void score_points_compact(const VolView& vv, const float* __re
 // Per-lane path: every lane keeps one point in registers and evaluates it against the TK poses
 // (uniform, in scalar registers; eval_poses), without the mask or through it when the compacting
 // queues do not fit.
-template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK, bool NARROW>
+template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK, bool NARROW, bool PRIO>
 __attribute__((always_inline))
 __device__ inline void score_points_lanes(const VolView& vv, const float* __restrict__ px,
                                           const float* __restrict__ py, const float* __restrict__ pz, int n,
@@ -247,7 +247,7 @@ __device__ inline void score_points_lanes(const VolView& vv, const float* __rest
         nx = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(px) + off);
         ny = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(py) + off);
         nz = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(pz) + off);
-        eval_poses<FMT, LAYOUT, TK, MASK, NARROW, true>(G, lx, ly, lz, g, x, y, z, sum, cnt, q < n);
+        eval_poses<FMT, LAYOUT, TK, MASK, NARROW, true, PRIO>(G, lx, ly, lz, g, x, y, z, sum, cnt, q < n);
     }
     if ((threadIdx.x & (kWave - 1)) != 0) {
 #pragma unroll
@@ -259,7 +259,8 @@ __device__ inline void score_points_lanes(const VolView& vv, const float* __rest
 // cell-validity mask when MASK (compacting the valid samples when the queues fit in 32 KB of LDS).
 // The sums are exact, so the result of a pose does not depend on TK, BLOCK, MASK or the workgroup.
 // NARROW: the volume passes narrow_grid (eval_poses: the same answer with fewer instructions).
-template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK = false, bool NARROW = false>
+// PRIO: the scoring paths' raised-priority windows (off in the batched kernels).
+template <int FMT, int LAYOUT, int TK, int BLOCK, bool MASK = false, bool NARROW = false, bool PRIO = true>
 __attribute__((always_inline))
 __device__ inline void score_step(const VolView& vv, const float* __restrict__ px, const float* __restrict__ py,
                                   const float* __restrict__ pz, int n, const float* __restrict__ poses, int K, int k0,
@@ -267,9 +268,9 @@ __device__ inline void score_step(const VolView& vv, const float* __restrict__ p
     FixSum sum[TK];
     int cnt[TK];
     if constexpr (MASK && LAYOUT != PF_LAYOUT_LINEAR && compact_fits<TK, BLOCK>())
-        score_points_compact<FMT, LAYOUT, TK, BLOCK, NARROW>(vv, px, py, pz, n, poses, K, k0, sum, cnt);
+        score_points_compact<FMT, LAYOUT, TK, BLOCK, NARROW, PRIO>(vv, px, py, pz, n, poses, K, k0, sum, cnt);
     else   // (the sparse layout reads its mask only when compacting: the mask changes speed only)
-        score_points_lanes<FMT, LAYOUT, TK, BLOCK, MASK && LAYOUT == PF_LAYOUT_CELLS, NARROW>(vv, px, py, pz, n,
+        score_points_lanes<FMT, LAYOUT, TK, BLOCK, MASK && LAYOUT == PF_LAYOUT_CELLS, NARROW, PRIO>(vv, px, py, pz, n,
                                                                                            poses, K, k0, sum, cnt);
     block_reduce<TK, BLOCK>(sum, cnt);
     if (threadIdx.x < TK) {
@@ -284,7 +285,7 @@ __device__ inline void score_step(const VolView& vv, const float* __restrict__ p
 
 // score_step through the cell-validity mask when the replica has one and the particles' spread
 // regime `regime` is one of kMaskRegimes (uniform across the workgroup).
-template <int FMT, int LAYOUT, int TK, int BLOCK>
+template <int FMT, int LAYOUT, int TK, int BLOCK, bool PRIO = true>
 __attribute__((always_inline))
 __device__ inline void score_step_regime(const VolView& vv, const float* __restrict__ px,
                                          const float* __restrict__ py, const float* __restrict__ pz, int n,
@@ -292,11 +293,11 @@ __device__ inline void score_step_regime(const VolView& vv, const float* __restr
                                          int* __restrict__ n_valid, int regime) {
     if constexpr (LAYOUT != PF_LAYOUT_LINEAR) {
         if ((kMaskRegimes >> regime) & 1) {
-            score_step<FMT, LAYOUT, TK, BLOCK, true>(vv, px, py, pz, n, poses, K, k0, fitness, n_valid);
+            score_step<FMT, LAYOUT, TK, BLOCK, true, false, PRIO>(vv, px, py, pz, n, poses, K, k0, fitness, n_valid);
             return;
         }
     }
-    score_step<FMT, LAYOUT, TK, BLOCK, false>(vv, px, py, pz, n, poses, K, k0, fitness, n_valid);
+    score_step<FMT, LAYOUT, TK, BLOCK, false, false, PRIO>(vv, px, py, pz, n, poses, K, k0, fitness, n_valid);
 }
 
 }  // namespace pf

@@ -262,7 +262,7 @@ constexpr int kAdvThreads = 256;
 // With a next view `nv` (x != nullptr), the workgroup also scores the new pose (ADV) or the pending
 // pose (not ADV) on its chunk of that view, into the second set of partials: next_step turns them
 // into the next iteration's E_0. Without ADV the first set is then left alone.
-template <int FMT, int LAYOUT, bool ADV>
+template <int FMT, int LAYOUT, bool ADV, bool PRIO = true>
 __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px, const float* __restrict__ py,
                                 const float* __restrict__ pz, int n_host, const int* __restrict__ n_dev,
                                 const float* __restrict__ fitness, pf_track_state* st, int K, int blk, int nblk,
@@ -414,7 +414,8 @@ __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px,
         FixSum s1[1] = {0};
         int c1[1] = {0};
         for (int q = q0[v] + (int)threadIdx.x + kPts * kAdvThreads; q < q1[v]; q += kAdvThreads)
-            eval_poses<FMT, LAYOUT, 1>(G, lx, ly, lz, g, X[v][q] * sc, Y[v][q] * sc, Z[v][q] * sc, s1, c1);
+            eval_poses<FMT, LAYOUT, 1, false, false, false, PRIO>(G, lx, ly, lz, g, X[v][q] * sc, Y[v][q] * sc,
+                                                                 Z[v][q] * sc, s1, c1);
         sum[v] = s1[0];
         cnt[v] = c1[0];
 #pragma unroll

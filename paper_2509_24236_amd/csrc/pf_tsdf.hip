@@ -332,11 +332,13 @@ __device__ inline bool brick_outside(const FuseArgs& a, int i0, int j0, int k0, 
 }
 
 // The voxels (i, j, k0..k1) of one thread, kFuseU slices at a time in phases, so that each phase's
-// loads are in flight together instead of one voxel's two dependent rounds (its depth pixel, then
-// its T and W) after another's: the projections of all kFuseU voxels (fuse_decide's FP64 formula,
-// with the same operations in the same order; its FP32 pre-tests only skip work and are left out),
-// then their depth pixels (a voxel outside the image reads pixel 0 and is dropped), the decisions,
-// the T and W of the updated voxels, and the updates.
+// loads are in flight together instead of one voxel's dependent rounds after another's: the T and W
+// of all kFuseU voxels (their addresses do not depend on the image, so these loads are issued first
+// and run under the projection arithmetic; a voxel that is not updated wastes its 8 bytes), the
+// projections (fuse_decide's FP64 formula, with the same operations in the same order; its FP32
+// pre-tests only skip work and are left out), then their depth pixels (a voxel outside the image
+// reads pixel 0 and is dropped), the decisions and the updates. One dependent memory round per
+// phase (the depth pixel) is left exposed instead of two.
 constexpr int kFuseU = 4;
 
 template <int FMT>
@@ -348,8 +350,18 @@ __device__ inline void fuse_column(const FuseArgs& a, int i, int j, int k0, int 
     const double py = a.oy + a.vs * (double)j;
     const double dx = px - a.t[0], dy = py - a.t[1];
     for (int kb = k0; kb <= k1; kb += kFuseU) {
+        const int64_t e0 = ((int64_t)kb * a.d.ny + j) * a.d.nx + i, slice = (int64_t)a.d.ny * a.d.nx;
+        typename S::T told[kFuseU];
+        typename S::W wold[kFuseU];
+#pragma unroll
+        for (int u = 0; u < kFuseU; ++u) {
+            if (kb + u <= k1) {
+                told[u] = T[e0 + u * slice];
+                wold[u] = W[e0 + u * slice];
+            }
+        }
         double qz[kFuseU];
-        int64_t pix[kFuseU];
+        unsigned pix[kFuseU];   // below 2^30: the boundary rejects larger images
         bool in[kFuseU];
 #pragma unroll
         for (int u = 0; u < kFuseU; ++u) {
@@ -364,16 +376,13 @@ __device__ inline void fuse_column(const FuseArgs& a, int i, int j, int k0, int 
             const double uf = floor(uu + 0.5), vf = floor(vv + 0.5);
             in[u] = k <= k1 && qz[u] > 0.0 && uf >= 0.0 && uf < (double)a.width && vf >= 0.0 &&
                     vf < (double)a.height;
-            pix[u] = in[u] ? (int64_t)(int)vf * a.width + (int)uf : 0;
+            pix[u] = in[u] ? (unsigned)vf * (unsigned)a.width + (unsigned)uf : 0u;
         }
         float Dp[kFuseU];
 #pragma unroll
         for (int u = 0; u < kFuseU; ++u) Dp[u] = a.depth[pix[u]];
         double phi[kFuseU];
         bool go[kFuseU];
-        int64_t e[kFuseU];
-        typename S::T told[kFuseU];
-        typename S::W wold[kFuseU];
 #pragma unroll
         for (int u = 0; u < kFuseU; ++u) {
             const double D = (double)Dp[u];
@@ -382,11 +391,6 @@ __device__ inline void fuse_column(const FuseArgs& a, int i, int j, int k0, int 
             double ph = eta / a.tau;
             if (ph > 1.0) ph = 1.0;
             phi[u] = ph;
-            e[u] = ((int64_t)(kb + u) * a.d.ny + j) * a.d.nx + i;
-            if (go[u]) {
-                told[u] = T[e[u]];
-                wold[u] = W[e[u]];
-            }
         }
 #pragma unroll
         for (int u = 0; u < kFuseU; ++u) {
@@ -395,8 +399,8 @@ __device__ inline void fuse_column(const FuseArgs& a, int i, int j, int k0, int 
             const float tn = (S::dec(told[u]) * w + (float)phi[u]) / (w + 1.0f);
             const typename S::T tnew = S::enc(tn);
             const bool changed = !S::same(told[u], tnew);
-            if (changed) T[e[u]] = tnew;
-            W[e[u]] = S::encw(fminf(w + 1.0f, a.w_max));
+            if (changed) T[e0 + u * slice] = tnew;
+            W[e0 + u * slice] = S::encw(fminf(w + 1.0f, a.w_max));
             if (changed && a.C) {
                 write_corners(static_cast<typename S::T*>(a.C), a.d, i, j, kb + u, S::cell(tnew));
                 if (stored_in_band<FMT>(told[u]) != stored_in_band<FMT>(tnew)) flag_cells_of(a.m, a.d, i, j, kb + u);
@@ -411,16 +415,27 @@ __global__ void k_fuse_pose(FuseArgs* out, FuseArgs base, const double* R, const
     *out = base;
 }
 
-// ap != nullptr: the fusion's arguments come from device memory (a pose the device computed).
 template <int FMT>
-__global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a0, const FuseArgs* __restrict__ ap) {
-    const FuseArgs a = ap ? *ap : a0;
+__attribute__((always_inline)) __device__ inline void fuse_brick(const FuseArgs& a) {
     const int i0 = blockIdx.x * kFuseX, j0 = blockIdx.y * kFuseY, k0 = blockIdx.z * kFuseZ;
     const int i1 = min(a.d.nx, i0 + kFuseX) - 1, j1 = min(a.d.ny, j0 + kFuseY) - 1, k1 = min(a.d.nz, k0 + kFuseZ) - 1;
     if (brick_outside(a, i0, j0, k0, i1, j1, k1)) return;
     const int i = i0 + (int)(threadIdx.x % kFuseX), j = j0 + (int)(threadIdx.x / kFuseX);
     if (i > i1 || j > j1) return;
     fuse_column<FMT>(a, i, j, k0, k1);
+}
+
+// DEV: the fusion's arguments come from device memory (a pose the device computed), else from the
+// kernel arguments. Two instantiations rather than a run-time choice: selecting between the two
+// sources made the compiler copy the whole argument block into vector registers (122 per lane).
+template <int FMT, bool DEV>
+__global__ __launch_bounds__(kBlock) void k_integrate(FuseArgs a0, const FuseArgs* __restrict__ ap) {
+    if constexpr (DEV) {
+        const FuseArgs a = *ap;   // read before any store, into scalar registers
+        fuse_brick<FMT>(a);
+    } else {
+        fuse_brick<FMT>(a0);
+    }
 }
 
 template <int FMT>
@@ -825,7 +840,10 @@ template <int FMT>
 int32_t integrate_dense(const pf_tsdf* v, const FuseArgs& a, const FuseArgs* ap, hipStream_t s) {
     const dim3 grid((unsigned)((a.d.nx + kFuseX - 1) / kFuseX), (unsigned)((a.d.ny + kFuseY - 1) / kFuseY),
                     (unsigned)((a.d.nz + kFuseZ - 1) / kFuseZ));
-    hipLaunchKernelGGL(k_integrate<FMT>, grid, dim3(kBlock), 0, s, a, ap);
+    if (ap)
+        hipLaunchKernelGGL((k_integrate<FMT, true>), grid, dim3(kBlock), 0, s, a, ap);
+    else
+        hipLaunchKernelGGL((k_integrate<FMT, false>), grid, dim3(kBlock), 0, s, a, ap);
     if (v->layout == PF_LAYOUT_CELLS) {
         const int64_t words = (int64_t)a.m.mwx * a.m.mwy * a.m.mwz;
         hipLaunchKernelGGL(k_mask_update<FMT>, dim3(grid_for(words)), dim3(kBlock), 0, s, v->tsdf, a.d, a.m, 0);

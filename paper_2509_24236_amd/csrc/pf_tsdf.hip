@@ -307,7 +307,9 @@ __device__ inline bool fuse_apply(const FuseArgs& a, int64_t e, double phi, type
 // amortise its start). A brick whose 8 corners all lie behind the camera, or all beyond one side of the image
 // (a plane through the camera centre, two pixels out, with a margin far above the FP32 error), is
 // skipped as a whole: every voxel in it is a convex combination of the corners, so the per-voxel
-// tests would drop it too.
+// tests would drop it too. Lane l of each wave evaluates corner l mod 8 and ballots combine the
+// corners (the test is the same for every wave of the workgroup), instead of every lane walking all
+// eight: most workgroups of a frame end here.
 constexpr int kFuseX = 64, kFuseY = kBlock / kFuseX, kFuseZ = 32;
 
 __device__ inline bool brick_outside(const FuseArgs& a, int i0, int j0, int k0, int i1, int j1, int k1) {
@@ -316,19 +318,18 @@ __device__ inline bool brick_outside(const FuseArgs& a, int i0, int j0, int k0, 
     const float W = (float)a.width, H = (float)a.height;
     const float n[4][3] = {{fx, 0.0f, cx + 2.5f}, {-fx, 0.0f, W + 1.5f - cx},
                            {0.0f, fy, cy + 2.5f}, {0.0f, -fy, H + 1.5f - cy}};
-    bool behind = true, out[4] = {true, true, true, true};
-    for (int c = 0; c < 8; ++c) {
-        const float fi = (float)((c & 1) ? i1 : i0), fj = (float)((c & 2) ? j1 : j0), fk = (float)((c & 4) ? k1 : k0);
-        float q[3];
-        for (int r = 0; r < 3; ++r) q[r] = a.q0[r] + fi * a.qi[r] + fj * a.qj[r] + fk * a.qk[r];
-        behind &= q[2] < -1e-3f;
-        for (int p = 0; p < 4; ++p) {
-            const float d = n[p][0] * q[0] + n[p][1] * q[1] + n[p][2] * q[2];
-            const float tol = 1e-3f * (fabsf(n[p][0]) + fabsf(n[p][1]) + fabsf(n[p][2]));
-            out[p] &= d < -tol;
-        }
+    const int c = (int)threadIdx.x & 7;
+    const float fi = (float)((c & 1) ? i1 : i0), fj = (float)((c & 2) ? j1 : j0), fk = (float)((c & 4) ? k1 : k0);
+    float q[3];
+    for (int r = 0; r < 3; ++r) q[r] = a.q0[r] + fi * a.qi[r] + fj * a.qj[r] + fk * a.qk[r];
+    // a test holds for the brick when it holds at all 8 corners (lanes 0..7 of the wave)
+    bool outside = (__ballot(q[2] < -1e-3f) & 0xffull) == 0xffull;
+    for (int p = 0; p < 4; ++p) {
+        const float d = n[p][0] * q[0] + n[p][1] * q[1] + n[p][2] * q[2];
+        const float tol = 1e-3f * (fabsf(n[p][0]) + fabsf(n[p][1]) + fabsf(n[p][2]));
+        outside |= (__ballot(d < -tol) & 0xffull) == 0xffull;
     }
-    return behind || out[0] || out[1] || out[2] || out[3];
+    return outside;
 }
 
 // The voxels (i, j, k0..k1) of one thread, kFuseU slices at a time in phases, so that each phase's

@@ -170,7 +170,11 @@ __global__ __launch_bounds__(kBlock) void k_mask_update(const void* Tv, Dims d, 
         while (todo) {   // uniform: the same words for every lane
             const int64_t w = base + (__ffsll((long long)todo) - 1);
             todo &= todo - 1;
-            const int wx = (int)(w % m.mwx), wy = (int)((w / m.mwx) % m.mwy), wz = (int)(w / ((int64_t)m.mwx * m.mwy));
+            // 32-bit: a dense grid holds under 2^31 voxels, so under 2^25 words (64-bit division is a
+            // long emulated sequence, and this runs once per flagged word)
+            const unsigned wu = (unsigned)w, row = wu / (unsigned)m.mwx;
+            const int wx = (int)(wu - row * (unsigned)m.mwx), wy = (int)(row % (unsigned)m.mwy);
+            const int wz = (int)(row / (unsigned)m.mwy);
             const int cx = wx * 4 + lx, cy = wy * 4 + ly, cz = wz * 4 + lz;
             bool valid = false;
             if (cx < d.nx - 1 && cy < d.ny - 1 && cz < d.nz - 1) {

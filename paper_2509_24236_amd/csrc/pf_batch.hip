@@ -124,7 +124,10 @@ __global__ __launch_bounds__(256) void kb_next(const BatchProb* tab, const int4*
 // through the mask, the others take the per-lane path, in one kernel; PATH 1 / 2: the masked
 // (compacting) path or the per-lane path only, each a kernel with its own register and LDS
 // footprint (the automatic plan launches the two, one per regime, as track_frame does). NARROW: every
-// problem's volume passes narrow_grid (score_step).
+// problem's volume passes narrow_grid (score_step). The batched kernels leave the scoring paths'
+// raised-priority windows off (PRIO = false here and in the update and polish steps): with waves of
+// several problems on every CU, a raised wave delays other problems' work instead of its own
+// arithmetic, and a 64-problem batch ran 4% slower with them.
 template <int FMT, int LAYOUT, int TK, int BLOCK, int PATH = 0, bool NARROW = false>
 __global__ __launch_bounds__(BLOCK) void kb_score(const BatchProb* tab, const int4* items, int n_items, int phase,
                                                   int regimes) {

@@ -277,7 +277,8 @@ __device__ inline void grad_step(const VolView& vv, const float* __restrict__ px
     __syncthreads();
 }
 
-// Exact fitness partial of FP64 pose p (row-major [R | t]) on point chunk s of S.
+// Exact fitness partial of FP64 pose p (row-major [R | t]) on point chunk s of S. PRIO: the scoring
+// loop's raised-priority window (left off by the batched kernels).
 template <int FMT, int LAYOUT, bool PRIO = true>
 __device__ inline void pose_partials_step(const VolView& vv, const float* __restrict__ px,
                                           const float* __restrict__ py, const float* __restrict__ pz, int n,

@@ -261,7 +261,8 @@ constexpr int kAdvThreads = 256;
 //
 // With a next view `nv` (x != nullptr), the workgroup also scores the new pose (ADV) or the pending
 // pose (not ADV) on its chunk of that view, into the second set of partials: next_step turns them
-// into the next iteration's E_0. Without ADV the first set is then left alone.
+// into the next iteration's E_0. Without ADV the first set is then left alone. PRIO: the scoring
+// loop's raised-priority window (left off by the batched kernels).
 template <int FMT, int LAYOUT, bool ADV, bool PRIO = true>
 __device__ inline void adv_step(const VolView& vv, const float* __restrict__ px, const float* __restrict__ py,
                                 const float* __restrict__ pz, int n_host, const int* __restrict__ n_dev,

@@ -153,9 +153,13 @@ __global__ __launch_bounds__(kBlock) void k_init(void* Tv, void* Wv, void* Cv, D
 }
 
 // Rebuilds the flagged mask words (every word when `all`) from the x-fastest storage and clears
-// their flags. A wave scans 64 consecutive words' flags, then rebuilds each flagged word together:
-// lane l takes cell l of the word's 4x4x4 block (bit l of the word), tests its 8 corners, and the
-// wave's ballot is the word. Cells past the last one of the grid have no corners there: bit 0.
+// their flags. A wave scans 64 consecutive words' flags, then rebuilds the flagged words together,
+// kMaskWords at a time so that their corner loads are in flight at once: lane l takes cell l of a
+// word's 4x4x4 block (bit l of the word), tests its 8 corners, and the wave's ballot is the word.
+// Cells past the last one of the grid have no corners there: bit 0 (their loads read the grid's
+// first cell instead, in bounds, and are ignored).
+constexpr int kMaskWords = 4;
+
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_mask_update(const void* Tv, Dims d, MaskArgs m, int all) {
     const auto* T = static_cast<const typename Store<FMT>::T*>(Tv);
@@ -168,26 +172,40 @@ __global__ __launch_bounds__(kBlock) void k_mask_update(const void* Tv, Dims d, 
         const int64_t own = base + lane;
         unsigned long long todo = __ballot(own < words && (all || m.flags[own]));
         while (todo) {   // uniform: the same words for every lane
-            const int64_t w = base + (__ffsll((long long)todo) - 1);
-            todo &= todo - 1;
-            // 32-bit: a dense grid holds under 2^31 voxels, so under 2^25 words (64-bit division is a
-            // long emulated sequence, and this runs once per flagged word)
-            const unsigned wu = (unsigned)w, row = wu / (unsigned)m.mwx;
-            const int wx = (int)(wu - row * (unsigned)m.mwx), wy = (int)(row % (unsigned)m.mwy);
-            const int wz = (int)(row / (unsigned)m.mwy);
-            const int cx = wx * 4 + lx, cy = wy * 4 + ly, cz = wz * 4 + lz;
-            bool valid = false;
-            if (cx < d.nx - 1 && cy < d.ny - 1 && cz < d.nz - 1) {
-                const int64_t b = ((int64_t)cz * d.ny + cy) * d.nx + cx;
-                valid = stored_in_band<FMT>(T[b]) & stored_in_band<FMT>(T[b + 1]) &
-                        stored_in_band<FMT>(T[b + d.nx]) & stored_in_band<FMT>(T[b + d.nx + 1]) &
-                        stored_in_band<FMT>(T[b + nxy]) & stored_in_band<FMT>(T[b + nxy + 1]) &
-                        stored_in_band<FMT>(T[b + nxy + d.nx]) & stored_in_band<FMT>(T[b + nxy + d.nx + 1]);
+            int64_t w[kMaskWords];
+            bool inside[kMaskWords];
+            typename Store<FMT>::T c[kMaskWords][8];
+#pragma unroll
+            for (int q = 0; q < kMaskWords; ++q) {
+                w[q] = todo ? base + (__ffsll((long long)todo) - 1) : -1;   // -1: no word left
+                todo &= todo - 1;
+                // 32-bit: a dense grid holds under 2^31 voxels, so under 2^25 words (64-bit division
+                // is a long emulated sequence, and this runs once per flagged word)
+                const unsigned wu = w[q] < 0 ? 0u : (unsigned)w[q], row = wu / (unsigned)m.mwx;
+                const int wx = (int)(wu - row * (unsigned)m.mwx), wy = (int)(row % (unsigned)m.mwy);
+                const int wz = (int)(row / (unsigned)m.mwy);
+                const int cx = wx * 4 + lx, cy = wy * 4 + ly, cz = wz * 4 + lz;
+                inside[q] = cx < d.nx - 1 && cy < d.ny - 1 && cz < d.nz - 1;
+                const int64_t b = inside[q] ? ((int64_t)cz * d.ny + cy) * d.nx + cx : 0;
+                c[q][0] = T[b];
+                c[q][1] = T[b + 1];
+                c[q][2] = T[b + d.nx];
+                c[q][3] = T[b + d.nx + 1];
+                c[q][4] = T[b + nxy];
+                c[q][5] = T[b + nxy + 1];
+                c[q][6] = T[b + nxy + d.nx];
+                c[q][7] = T[b + nxy + d.nx + 1];
             }
-            const unsigned long long word = __ballot(valid);
-            if (lane == 0) {
-                m.mask[w] = word;
-                m.flags[w] = 0;
+#pragma unroll
+            for (int q = 0; q < kMaskWords; ++q) {
+                bool valid = inside[q];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) valid &= stored_in_band<FMT>(c[q][r]);
+                const unsigned long long word = __ballot(valid);
+                if (lane == 0 && w[q] >= 0) {
+                    m.mask[w[q]] = word;
+                    m.flags[w[q]] = 0;
+                }
             }
         }
     }
